@@ -1,0 +1,162 @@
+"""Nystrom fast kernel filter in the paper's own form.  Test infrastructure only.
+
+Section III and Algorithm 1 (Fast Kernel Filtering):
+
+* landmarks mu_1..mu_m0 (k-means centroids, see ``oracle.kmeans``);
+* A(i, j) = k(mu_i, mu_j)                      -- Eq. (defA)
+* A = sum_k alpha_k w_k w_k^T                  -- Eq. (eigA)
+* B(i, j) = k(mu_i, r_j)                       -- Eq. (defB)
+* v_k = B^T w_k / alpha_k                      -- Eq. (vk)
+* d_k(x) = v_k(iota(x)), h_k = d_k f
+* zeta += alpha_k d_k (w * h_k),  eta += alpha_k d_k (w * d_k)   -- the two
+  accumulation steps of Algorithm 1, i.e. Eqs. (finalnum), (finalden)
+* g_hat = zeta / eta.
+
+The index map iota is notational: v_k(iota(x)) is evaluated from p(x) directly.
+
+Readings where the paper is silent:
+* eigenvalues alpha_k <= tau * max(alpha) (tau = 1e-10) are dropped, which
+  makes the rank-deficient case (coincident landmarks, sigma_r -> inf) a
+  pseudo-inverse;
+* pixels where eta_hat <= 0 or is not finite output f(x);
+* convolutions use zero extension at the image border, as the exact filter.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .exact import range_kernel_sqdist, spatial_taps
+
+DEFAULT_TAU = 1e-10
+
+
+def sqdist(X, Y):
+    """Pairwise squared distances by direct differences; X [n, D], Y [m, D]."""
+    X = np.asarray(X, np.float64)
+    Y = np.asarray(Y, np.float64)
+    out = np.empty((X.shape[0], Y.shape[0]))
+    for j in range(Y.shape[0]):
+        diff = X - Y[j]
+        out[:, j] = np.einsum("ij,ij->i", diff, diff)
+    return out
+
+
+def landmark_gram(c, sigma_r):
+    """A of Eq. (defA)."""
+    return range_kernel_sqdist(sqdist(c, c), sigma_r)
+
+
+def landmark_eig(c, sigma_r, tau=DEFAULT_TAU):
+    """Eigenpairs of A (Eq. (eigA)) that are kept: alpha > tau * max alpha.
+    Returns (alpha [r_eff], W [r, r_eff]) with alpha ascending."""
+    A = landmark_gram(c, sigma_r)
+    alpha, Wv = np.linalg.eigh(A)
+    keep = alpha > tau * alpha.max()
+    return alpha[keep], Wv[:, keep]
+
+
+def cross_kernel_sr(c, P, sigma_r):
+    """B^T of Eq. (defB) as an [N, r] array: entry (x, i) = k(mu_i, p(x))."""
+    return range_kernel_sqdist(sqdist(P, c), sigma_r)
+
+
+def extrapolated_eigvecs(c, P, sigma_r, tau=DEFAULT_TAU):
+    """alpha_k and v_k = B^T w_k / alpha_k (Eq. (vk)) for the kept k; v as [N, r_eff]."""
+    alpha, Wv = landmark_eig(c, sigma_r, tau)
+    Bt = cross_kernel_sr(c, P, sigma_r)
+    return alpha, (Bt @ Wv) / alpha[None, :]
+
+
+def conv_zero(img, w1):
+    """(w * img) for the separable kernel w(z) = w1(z1) w1(z2) on the square
+    window, with the window intersected with the image (zero extension).
+    ``img`` is [H, W] or [H, W, C]; ``w1`` is symmetric so correlation and
+    convolution coincide."""
+    img = np.asarray(img, np.float64)
+    S = (len(w1) - 1) // 2
+    H, W = img.shape[:2]
+    tmp = np.zeros_like(img)
+    for t in range(-S, S + 1):
+        wt = w1[t + S]
+        if t >= 0:
+            tmp[:H - t] += wt * img[t:]
+        else:
+            tmp[-t:] += wt * img[:H + t]
+    out = np.zeros_like(img)
+    for t in range(-S, S + 1):
+        wt = w1[t + S]
+        if t >= 0:
+            out[:, :W - t] += wt * tmp[:, t:]
+        else:
+            out[:, -t:] += wt * tmp[:, :W + t]
+    return out
+
+
+def nystrom_filter(f, p, c, sigma_s, sigma_r, S, spatial="gaussian", tau=DEFAULT_TAU,
+                   return_eta=False):
+    """Algorithm 1 with given landmarks ``c`` [r, D].  ``f`` [H, W, C],
+    ``p`` [H, W, D].  Returns g_hat [H, W, C] (and eta_hat [H, W])."""
+    f = np.asarray(f, np.float64)
+    p = np.asarray(p, np.float64)
+    H, W, C = f.shape
+    P = p.reshape(H * W, -1)
+    w1 = spatial_taps(sigma_s, S, spatial)
+    alpha, Wv = landmark_eig(c, sigma_r, tau)
+    Bt = cross_kernel_sr(c, P, sigma_r)          # [N, r]
+    zeta = np.zeros((H, W, C))
+    eta = np.zeros((H, W))
+    for k in range(len(alpha)):
+        vk = (Bt @ Wv[:, k]) / alpha[k]           # Eq. (vk)
+        d = vk.reshape(H, W)                      # d_k(x) = v_k(iota(x))
+        h = d[:, :, None] * f                     # h_k = d_k f
+        zeta += alpha[k] * d[:, :, None] * conv_zero(h, w1)
+        eta += alpha[k] * d * conv_zero(d, w1)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        g = zeta / eta[:, :, None]
+    bad = ~(eta > 0) | ~np.isfinite(eta)
+    if bad.any():
+        g[bad] = f[bad]
+    if return_eta:
+        return g, eta
+    return g
+
+
+def nystrom_filter_at(f, p, c, sigma_s, sigma_r, S, coords, spatial="gaussian",
+                      tau=DEFAULT_TAU):
+    """The same approximation evaluated pixel by pixel before the sum switch:
+    Eq. (num1) with K replaced by K_hat = sum_k alpha_k v_k v_k^T (Eq. (hatK)).
+    ``coords`` [M, 2] of (y, x).  Returns (g_hat [M, C], eta_hat [M])."""
+    f = np.asarray(f, np.float64)
+    p = np.asarray(p, np.float64)
+    H, W, C = f.shape
+    w1 = spatial_taps(sigma_s, S, spatial)
+    alpha, Wv = landmark_eig(c, sigma_r, tau)
+    out = np.empty((len(coords), C))
+    etas = np.empty(len(coords))
+    for i, (y, x) in enumerate(np.asarray(coords)):
+        ya, yb = max(0, y - S), min(H, y + S + 1)
+        xa, xb = max(0, x - S), min(W, x + S + 1)
+        win = p[ya:yb, xa:xb].reshape(-1, p.shape[2])
+        v_win = (cross_kernel_sr(c, win, sigma_r) @ Wv) / alpha[None, :]
+        v_x = (cross_kernel_sr(c, p[y, x][None, :], sigma_r) @ Wv) / alpha[None, :]
+        khat = (v_win * alpha[None, :]) @ v_x[0]               # K_hat(x, y) over the window
+        wsp = np.outer(w1[ya - y + S:yb - y + S], w1[xa - x + S:xb - x + S]).ravel()
+        wt = wsp * khat
+        eta = wt.sum()
+        etas[i] = eta
+        if eta > 0 and np.isfinite(eta):
+            out[i] = wt @ f[ya:yb, xa:xb].reshape(-1, C) / eta
+        else:
+            out[i] = f[y, x]
+    return out, etas
+
+
+def kernel_matrix(P, sigma_r):
+    """K of Eq. (kernel) on the full range list (tiny inputs only)."""
+    return range_kernel_sqdist(sqdist(P, P), sigma_r)
+
+
+def nystrom_kernel_matrix(P, c, sigma_r, tau=DEFAULT_TAU):
+    """K_hat = sum_k alpha_k v_k v_k^T of Eq. (hatK) (tiny inputs only)."""
+    alpha, V = extrapolated_eigvecs(c, P, sigma_r, tau)
+    return (V * alpha[None, :]) @ V.T
