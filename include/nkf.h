@@ -1,0 +1,197 @@
+/*
+ * nkf.h -- C ABI of the Nystrom kernel filtering library (MI355X / gfx950).
+ *
+ * The library computes the fast kernel filter of Nair & Chaudhury, "Fast
+ * High-Dimensional Kernel Filtering": the bilateral / nonlocal-means filter of
+ * Eq. (num) (Section II) with the range kernel replaced by its Nystrom
+ * approximation K_hat = B^T A^{-1} B (Eqs. (hatK), (defA), (eigA), (defB),
+ * (vk), Section III), evaluated as r_eff * (C + 1) spatial convolutions and a
+ * per-pixel contraction and normalisation (Eqs. (finalnum), (finalden),
+ * Algorithm 1).  Landmarks are k-means centroids of the guide values
+ * (Section III).
+ *
+ * Notation: image f is [H, W, C] (C = n of the paper), guide p is [H, W, D]
+ * (D = rho of the paper), N = H * W pixels, r landmarks (m0 of the paper).
+ * Spatial kernel w(z) = w1(z1) w1(z2) on |z1|, |z2| <= S with
+ * w1(t) = exp(-t^2 / (2 sigma_s^2)) (Gaussian) or w1 = 1 (box) -- Section IV.
+ * Range kernel k(s, t) = exp(-|s - t|^2 / (2 sigma_r^2)).
+ *
+ * Conventions for every call:
+ *  - Array pointers are DEVICE pointers owned by the caller unless the name
+ *    ends in _host.  Layout is row-major, pixel-major, channel-contiguous:
+ *    element (y, x, c) of an [H, W, C] array is at (y * W + x) * C + c.
+ *    Images and guides are float32; host matrices are float64.
+ *  - No pointer is retained after a call returns.
+ *  - Device work is enqueued on the context's stream.  Unless stated
+ *    otherwise a call returns as soon as its work is enqueued.
+ *  - Errors are returned as nkf_status; nkf_last_error() gives a message.
+ *    Arguments are validated before any work is enqueued; a call that fails
+ *    validation has no effect.  No call aborts the process.
+ *  - Non-finite input pixels give unspecified output (not checked).
+ *  - The image border is handled by intersecting the window with the image
+ *    (zero extension of numerator and denominator alike).
+ */
+#ifndef NKF_H
+#define NKF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nkf_ctx nkf_ctx;
+
+typedef enum {
+  NKF_OK = 0,
+  NKF_ERR_INVALID_ARG = 1,   /* a size, pointer or parameter is out of range       */
+  NKF_ERR_OUT_OF_MEMORY = 2, /* device/host allocation failed or workspace limit hit */
+  NKF_ERR_HIP = 3,           /* a HIP runtime call failed                           */
+  NKF_ERR_NUMERICAL = 4,     /* every eigenvalue of A was truncated (r_eff == 0)    */
+  NKF_ERR_UNSUPPORTED = 5    /* valid request outside what this build implements    */
+} nkf_status;
+
+enum { NKF_SPATIAL_GAUSSIAN = 0, NKF_SPATIAL_BOX = 1 };
+/* Guide kinds: EXPLICIT = caller passes p [H, W, D]; SELF = p is f (D == C);
+ * PATCH = nonlocal-means guide, the (2pr+1)^2 * C patch of f around each pixel
+ * in (dy, dx, c) order, read from a symmetrically padded f (Section II, NLM). */
+enum { NKF_GUIDE_EXPLICIT = 0, NKF_GUIDE_SELF = 1, NKF_GUIDE_PATCH = 2 };
+/* Input precision of the distance / embedding contraction (k-means assignment
+ * and the cross kernel B).  FP32 is the plain form; BF16 and FP16 round the
+ * centred guide and landmarks to 16 bits and accumulate in FP32, with the
+ * squared norms kept in FP32/FP64.  Spatial convolutions are FP32 always. */
+enum { NKF_PREC_FP32 = 0, NKF_PREC_BF16 = 1, NKF_PREC_FP16 = 2 };
+
+typedef struct {
+  double sigma_s;          /* spatial Gaussian width, > 0 (ignored by BOX except for radius = -1) */
+  double sigma_r;          /* range kernel width, > 0; +INFINITY means k == 1                     */
+  int r;                   /* landmarks, 1 <= r <= min(N, 256)                                  */
+  int radius;              /* window radius S, 0 <= S <= 16; -1 means ceil(3 sigma_s)           */
+  int spatial;             /* NKF_SPATIAL_*                                                      */
+  int guide;               /* NKF_GUIDE_*                                                        */
+  int patch_radius;        /* PATCH guide only: pr >= 0, D must equal C (2pr+1)^2                */
+  int prec;                /* NKF_PREC_*                                                         */
+  int kmeans_iters;        /* Lloyd iterations, >= 0                                             */
+  uint64_t seed;           /* SplitMix64 seed of the k-means initialisation                      */
+  double eig_rel_tol;      /* tau: eigenvalues alpha <= tau * max(alpha) are dropped (>= 0)      */
+  double center;           /* f0 subtracted before and added after the filter (exact by affine
+                              equivariance); NAN means per-channel (min + max) / 2 of f          */
+} nkf_params;
+
+/* Fills defaults: sigma_s 3, sigma_r 30, r 16, radius -1, Gaussian, SELF
+ * guide, pr 3, FP32, 10 iterations, seed 0, tau 1e-10, center NAN. */
+void nkf_params_default(nkf_params *p);
+
+/* Library version string (static storage). */
+const char *nkf_version(void);
+
+/* Create a context bound to `hip_stream` (a hipStream_t; NULL = default stream)
+ * on the current device.  The context owns a growable device workspace. */
+nkf_status nkf_create(nkf_ctx **out, void *hip_stream);
+nkf_status nkf_set_stream(nkf_ctx *ctx, void *hip_stream);
+/* Waits for the context's stream, frees the workspace and the context. */
+nkf_status nkf_destroy(nkf_ctx *ctx);
+/* Message of the last failing call on `ctx` (or of the last failing
+ * nkf_create / host-only call when ctx is NULL).  Valid until the next call. */
+const char *nkf_last_error(const nkf_ctx *ctx);
+/* Cap on the workspace size in bytes (0 = no cap).  A call that would need
+ * more fails with NKF_ERR_OUT_OF_MEMORY before enqueuing work. */
+nkf_status nkf_set_workspace_limit(nkf_ctx *ctx, size_t bytes);
+/* Bytes of workspace currently held by the context. */
+size_t nkf_workspace_bytes(const nkf_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * One-shot forward (Algorithm 1): k-means landmarks -> landmark factor ->
+ * embedding -> r_eff (C+1) convolutions -> contraction and normalisation.
+ * f [H, W, C]; p [H, W, D] for EXPLICIT, NULL for SELF / PATCH.
+ * out [H, W, C] receives g_hat; eta_out (nullable) [H, W] receives eta_hat.
+ * Pixels with eta_hat <= 0 or non-finite output f (the paper leaves this case
+ * open).  Synchronises the stream once: the landmarks are copied to the host
+ * for the FP64 eigendecomposition of A.  r_eff_out (nullable, host) receives
+ * the number of kept eigenpairs.
+ */
+nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, const float *p,
+                      const nkf_params *prm, float *out, float *eta_out, int *r_eff_out);
+
+/* k-means landmarks (Section III): r distinct pixels drawn by SplitMix64
+ * (prm->seed) give the initial centroids, then prm->kmeans_iters Lloyd
+ * iterations (ties to the lowest index; an empty cluster keeps its centroid).
+ * centroids [r, D] float32 (output); labels (nullable) [N] int32 receives the
+ * assignment of the last iteration (left untouched when kmeans_iters == 0).
+ * Asynchronous. */
+nkf_status nkf_kmeans(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, const float *p,
+                      const nkf_params *prm, float *centroids, int *labels);
+
+/* `iters` Lloyd iterations starting from the centroids already in
+ * `centroids` [r, D] (in/out).  labels as in nkf_kmeans.  Asynchronous. */
+nkf_status nkf_kmeans_iterate(nkf_ctx *ctx, int H, int W, int C, const float *f, int D,
+                              const float *p, const nkf_params *prm, float *centroids, int iters,
+                              int *labels);
+
+/* Host-only, synchronous, FP64.  Landmark Gram matrix A(i,j) = k(c_i, c_j)
+ * (Eq. (defA)), its eigendecomposition A = Q diag(alpha) Q^T (Eq. (eigA)) by
+ * cyclic Jacobi, truncation of alpha <= tau * max(alpha), and the factor
+ * F = Q_keep diag(alpha_keep^{-1/2}) so that u(x) = F^T b(x) gives
+ * u(x).u(y) = b(x)^T A^+ b(y) = K_hat(x, y) (Eqs. (hatK), (vk)).
+ * centroids_host [r, D]; eigvecs_host (nullable) [r, r], column j = q_j;
+ * eigvals_host (nullable) [r] ascending; F_host [r, r] of which the first
+ * *r_eff columns are written (columns follow ascending kept alpha).
+ * Returns NKF_ERR_NUMERICAL when r_eff would be 0. */
+nkf_status nkf_landmark_factor(int r, int D, const double *centroids_host, double sigma_r,
+                               double tau, double *eigvecs_host, double *eigvals_host,
+                               double *F_host, int *r_eff);
+
+/* Forward with given landmarks: embedding, convolutions, contraction.
+ * centroids [r, D] float32 device; F [r, r_eff] float64 device (row-major, the
+ * F of nkf_landmark_factor restricted to its first r_eff columns).
+ * Fully asynchronous.  Other arguments as in nkf_filter. */
+nkf_status nkf_filter_landmarks(nkf_ctx *ctx, int H, int W, int C, const float *f, int D,
+                                const float *p, const nkf_params *prm, const float *centroids,
+                                const double *F, int r_eff, float *out, float *eta_out);
+
+/* Backward of nkf_filter_landmarks for L with dL/dg_hat = grad_out [H, W, C],
+ * landmarks held fixed and the window radius S held fixed.
+ * eigvecs_host [r, r] / eigvals_host [r] as returned by nkf_landmark_factor
+ * for the same centroids and sigma_r; r_eff must equal r when
+ * grad_sigma_r_host is requested (else NKF_ERR_UNSUPPORTED).
+ * Outputs (each nullable): grad_f [H, W, C], grad_p [H, W, D] (EXPLICIT or
+ * SELF guide; for SELF the caller adds grad_f and grad_p to get the total),
+ * grad_sigma_r_host, grad_sigma_s_host (host doubles; sigma_s only for the
+ * Gaussian window).  Recomputes the embedding and convolutions instead of
+ * storing r_eff (C+1) planes.  Synchronises the stream once (the r x r_eff
+ * reduction for the sigma_r gradient is finished on the host in FP64). */
+nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f, int D,
+                               const float *p, const nkf_params *prm, const float *centroids,
+                               const double *eigvecs_host, const double *eigvals_host, int r_eff,
+                               const float *grad_out, float *grad_f, float *grad_p,
+                               double *grad_sigma_r_host, double *grad_sigma_s_host);
+
+/* Stage timing.  When enabled, every stage a call enqueues is bracketed by
+ * HIP events on the context's stream (host-side stages by the host clock).
+ * Stages: 0 seeding, 1 k-means iterations, 2 landmark factor (host FP64,
+ * including the wait for the landmarks), 3 centring + embedding,
+ * 4 convolutions + contraction, 5 backward. */
+enum { NKF_STAGE_SEED = 0, NKF_STAGE_KMEANS = 1, NKF_STAGE_FACTOR = 2, NKF_STAGE_EMBED = 3,
+       NKF_STAGE_CONV = 4, NKF_STAGE_BACKWARD = 5, NKF_STAGE_COUNT = 6 };
+nkf_status nkf_enable_timing(nkf_ctx *ctx, int enable);
+/* Waits for the stream, then writes the summed milliseconds per stage to
+ * ms_host[NKF_STAGE_COUNT] and (nullable) the number of timed intervals to
+ * count_host[NKF_STAGE_COUNT] since the last reset; reset != 0 clears them. */
+nkf_status nkf_stage_times(nkf_ctx *ctx, double *ms_host, int *count_host, int reset);
+
+/* Host-only: the r distinct pixel indices (draw order) that initialise
+ * k-means for (N, r, seed): partial Fisher-Yates over [0, N) driven by
+ * SplitMix64.  idx_host [r].  Exposed so the draw can be checked. */
+nkf_status nkf_seed_indices(int64_t N, int r, uint64_t seed, int64_t *idx_host);
+
+/* Host-only: the window radius the library uses for (radius, sigma_s) and
+ * the one-dimensional taps w1[0 .. 2S] (float32, as uploaded).  taps_host
+ * nullable; returns S via *S_out. */
+nkf_status nkf_spatial_taps(int radius, double sigma_s, int spatial, int *S_out, float *taps_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NKF_H */

@@ -1,0 +1,54 @@
+// Device helpers shared by the HIP kernels (guide access, wave reductions,
+// XCD-aware block order).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nkf_internal.h"
+
+namespace nkf {
+
+constexpr int kWave = 64;
+
+// numpy-style symmetric padding index: -1 -> 0, n -> n-1 (valid for |pad| <= n).
+__device__ __forceinline__ int sym_index(int i, int n) {
+  if (i < 0) return -i - 1;
+  if (i >= n) return 2 * n - i - 1;
+  return i;
+}
+
+// Guide value p(x)[d] for pixel x (linear index).
+__device__ __forceinline__ float guide_elem(const Guide &g, int64_t x, int d) {
+  if (g.kind == GUIDE_EXPLICIT) return g.p[x * g.D + d];
+  if (g.kind == GUIDE_SELF) return g.f[x * g.C + d];
+  const int T = 2 * g.pr + 1;
+  const int c = d % g.C;
+  const int q = d / g.C;
+  const int dx = q % T - g.pr;
+  const int dy = q / T - g.pr;
+  const int y = (int)(x / g.W), xx = (int)(x - (int64_t)y * g.W);
+  const int yy = sym_index(y + dy, g.H), xq = sym_index(xx + dx, g.W);
+  return g.f[((int64_t)yy * g.W + xq) * g.C + c];
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+  return v;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  Map the hardware block id to a logical tile id so that each XCD
+// receives a contiguous range of logical tiles; neighbouring tiles then share
+// halo rows through the same L2.
+__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
+  constexpr int kXcd = 8;
+  const int per = nb / kXcd, rem = nb % kXcd;
+  const int xcd = b % kXcd, idx = b / kXcd;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+}  // namespace nkf

@@ -1,0 +1,653 @@
+// Host runtime of the Nystrom kernel filtering library: the C ABI of
+// include/nkf.h, argument validation, the device workspace, the k-means
+// seeding draw, the FP64 landmark factor and the stream-ordered launch
+// sequence of Algorithm 1.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/nkf.h"
+#include "nkf_internal.h"
+
+namespace nkf {
+int sym_eig(int n, const double *A, double *w, double *V);
+}
+
+using namespace nkf;
+
+struct nkf_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t ws_limit = 0;
+  char *pinned = nullptr;  // host staging for landmarks / factor
+  size_t pinned_bytes = 0;
+  std::string err;
+  // stage timing
+  bool timing = false;
+  struct Interval {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Interval> pending;
+  std::vector<hipEvent_t> event_pool;
+  double host_ms[NKF_STAGE_COUNT] = {0};
+  int host_count[NKF_STAGE_COUNT] = {0};
+};
+
+namespace {
+
+hipEvent_t take_event(nkf_ctx *ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets the device work enqueued during its lifetime with two events.
+struct StageTimer {
+  nkf_ctx *ctx;
+  int stage;
+  hipEvent_t a = nullptr;
+  StageTimer(nkf_ctx *c, int s) : ctx(c), stage(s) {
+    if (ctx->timing && (a = take_event(ctx))) (void)hipEventRecord(a, ctx->stream);
+  }
+  ~StageTimer() {
+    if (!a) return;
+    hipEvent_t b = take_event(ctx);
+    if (!b) return;
+    (void)hipEventRecord(b, ctx->stream);
+    ctx->pending.push_back({stage, a, b});
+  }
+};
+
+struct HostTimer {
+  nkf_ctx *ctx;
+  int stage;
+  std::chrono::steady_clock::time_point t0;
+  HostTimer(nkf_ctx *c, int s) : ctx(c), stage(s), t0(std::chrono::steady_clock::now()) {}
+  ~HostTimer() {
+    if (!ctx || !ctx->timing) return;
+    ctx->host_ms[stage] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    ctx->host_count[stage] += 1;
+  }
+};
+
+}  // namespace
+
+namespace {
+
+thread_local std::string g_err;
+
+nkf_status fail(nkf_ctx *ctx, nkf_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+nkf_status fail(nkf_ctx *ctx, nkf_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx)
+    ctx->err = buf;
+  else
+    g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(ctx, NKF_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+// Sub-allocation of the workspace: the same sequence of take() calls is run
+// once to size the arena and once to hand out pointers.
+struct Carve {
+  char *base;
+  size_t off = 0;
+  template <class T>
+  T *take(size_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+nkf_status ensure_workspace(nkf_ctx *ctx, size_t bytes) {
+  if (bytes <= ctx->ws_bytes) return NKF_OK;
+  if (ctx->ws_limit && bytes > ctx->ws_limit)
+    return fail(ctx, NKF_ERR_OUT_OF_MEMORY, "workspace of %zu bytes exceeds the limit of %zu", bytes,
+                ctx->ws_limit);
+  if (ctx->ws) {
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  size_t want = bytes + bytes / 8;
+  if (ctx->ws_limit && want > ctx->ws_limit) want = ctx->ws_limit;
+  void *p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, NKF_ERR_OUT_OF_MEMORY, "hipMalloc of %zu workspace bytes failed", want);
+  }
+  ctx->ws = static_cast<char *>(p);
+  ctx->ws_bytes = want;
+  return NKF_OK;
+}
+
+nkf_status ensure_pinned(nkf_ctx *ctx, size_t bytes) {
+  if (bytes <= ctx->pinned_bytes) return NKF_OK;
+  if (ctx->pinned) {
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, hipHostFree(ctx->pinned));
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+  }
+  void *p = nullptr;
+  if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, NKF_ERR_OUT_OF_MEMORY, "hipHostMalloc of %zu bytes failed", bytes);
+  }
+  ctx->pinned = static_cast<char *>(p);
+  ctx->pinned_bytes = bytes;
+  return NKF_OK;
+}
+
+uint64_t splitmix_next(uint64_t &s) {
+  s += 0x9E3779B97F4A7C15ull;
+  uint64_t z = s;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void draw_indices(int64_t N, int r, uint64_t seed, int64_t *idx) {
+  uint64_t s = seed;
+  std::unordered_map<int64_t, int64_t> sw;
+  sw.reserve(2 * (size_t)r + 8);
+  for (int i = 0; i < r; ++i) {
+    const int64_t j = i + (int64_t)(splitmix_next(s) % (uint64_t)(N - i));
+    auto ai = sw.find(i);
+    auto aj = sw.find(j);
+    const int64_t vi = ai == sw.end() ? i : ai->second;
+    const int64_t vj = aj == sw.end() ? j : aj->second;
+    sw[i] = vj;
+    sw[j] = vi;
+    idx[i] = vj;
+  }
+}
+
+int resolve_radius(int radius, double sigma_s) {
+  if (radius >= 0) return radius;
+  return (int)ceil(3.0 * sigma_s);
+}
+
+struct Resolved {
+  int H, W, C, D, S;
+  int64_t N;
+  Guide g;
+  Taps taps;
+};
+
+// Validation shared by every device entry point.
+nkf_status validate(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, const float *p,
+                    const nkf_params *prm, Resolved &rs) {
+  if (!ctx) return fail(nullptr, NKF_ERR_INVALID_ARG, "ctx is NULL");
+  if (!prm) return fail(ctx, NKF_ERR_INVALID_ARG, "params is NULL");
+  if (H < 1 || W < 1 || C < 1 || D < 1)
+    return fail(ctx, NKF_ERR_INVALID_ARG, "sizes must be >= 1 (H=%d W=%d C=%d D=%d)", H, W, C, D);
+  if ((int64_t)H * W > (int64_t)1 << 31)
+    return fail(ctx, NKF_ERR_INVALID_ARG, "H*W exceeds 2^31");
+  if (!f) return fail(ctx, NKF_ERR_INVALID_ARG, "f is NULL");
+  if (D > 256) return fail(ctx, NKF_ERR_UNSUPPORTED, "guide dimension D=%d exceeds 256", D);
+  if (C > 1024) return fail(ctx, NKF_ERR_UNSUPPORTED, "C=%d exceeds 1024", C);
+  if (!(prm->sigma_r > 0.0) || isnan(prm->sigma_r))
+    return fail(ctx, NKF_ERR_INVALID_ARG, "sigma_r must be > 0 (got %g)", prm->sigma_r);
+  if (prm->spatial != NKF_SPATIAL_GAUSSIAN && prm->spatial != NKF_SPATIAL_BOX)
+    return fail(ctx, NKF_ERR_INVALID_ARG, "unknown spatial kernel %d", prm->spatial);
+  if (prm->spatial == NKF_SPATIAL_GAUSSIAN || prm->radius < 0) {
+    if (!(prm->sigma_s > 0.0) || !isfinite(prm->sigma_s))
+      return fail(ctx, NKF_ERR_INVALID_ARG, "sigma_s must be finite and > 0 (got %g)", prm->sigma_s);
+  }
+  if (prm->radius < -1) return fail(ctx, NKF_ERR_INVALID_ARG, "radius must be >= -1");
+  const int S = resolve_radius(prm->radius, prm->sigma_s);
+  if (S > kMaxRadius)
+    return fail(ctx, NKF_ERR_UNSUPPORTED, "window radius %d exceeds %d", S, kMaxRadius);
+  const int64_t N = (int64_t)H * W;
+  if (prm->r < 1 || prm->r > kMaxLandmarks || prm->r > N)
+    return fail(ctx, NKF_ERR_INVALID_ARG, "r=%d must satisfy 1 <= r <= min(N, %d)", prm->r,
+                kMaxLandmarks);
+  if (prm->kmeans_iters < 0) return fail(ctx, NKF_ERR_INVALID_ARG, "kmeans_iters must be >= 0");
+  if (!(prm->eig_rel_tol >= 0.0)) return fail(ctx, NKF_ERR_INVALID_ARG, "eig_rel_tol must be >= 0");
+  if (prm->prec != NKF_PREC_FP32 && prm->prec != NKF_PREC_BF16 && prm->prec != NKF_PREC_FP16)
+    return fail(ctx, NKF_ERR_INVALID_ARG, "unknown precision %d", prm->prec);
+  Guide g{};
+  g.H = H;
+  g.W = W;
+  g.C = C;
+  g.D = D;
+  g.f = f;
+  switch (prm->guide) {
+    case NKF_GUIDE_EXPLICIT:
+      if (!p) return fail(ctx, NKF_ERR_INVALID_ARG, "explicit guide needs p");
+      g.kind = GUIDE_EXPLICIT;
+      g.p = p;
+      break;
+    case NKF_GUIDE_SELF:
+      if (D != C) return fail(ctx, NKF_ERR_INVALID_ARG, "self guide needs D == C (D=%d C=%d)", D, C);
+      g.kind = GUIDE_SELF;
+      break;
+    case NKF_GUIDE_PATCH: {
+      const int pr = prm->patch_radius;
+      if (pr < 0) return fail(ctx, NKF_ERR_INVALID_ARG, "patch_radius must be >= 0");
+      if (pr > H || pr > W) return fail(ctx, NKF_ERR_INVALID_ARG, "patch_radius exceeds the image");
+      if (D != C * (2 * pr + 1) * (2 * pr + 1))
+        return fail(ctx, NKF_ERR_INVALID_ARG, "patch guide needs D == C (2pr+1)^2 (D=%d)", D);
+      g.kind = GUIDE_PATCH;
+      g.pr = pr;
+      break;
+    }
+    default:
+      return fail(ctx, NKF_ERR_INVALID_ARG, "unknown guide kind %d", prm->guide);
+  }
+  rs.H = H;
+  rs.W = W;
+  rs.C = C;
+  rs.D = D;
+  rs.S = S;
+  rs.N = N;
+  rs.g = g;
+  for (int t = 0; t < 2 * kMaxRadius + 1; ++t) rs.taps.w[t] = 0.0f;
+  for (int t = -S; t <= S; ++t)
+    rs.taps.w[t + S] = prm->spatial == NKF_SPATIAL_BOX
+                           ? 1.0f
+                           : (float)exp(-(double)t * t / (2.0 * prm->sigma_s * prm->sigma_s));
+  return NKF_OK;
+}
+
+// ---- host FP64 landmark factor ----------------------------------------------
+nkf_status factor(nkf_ctx *ctx, int r, int D, const double *c, double sigma_r, double tau, double *Q,
+                  double *alpha, double *F, int *r_eff) {
+  std::vector<double> A((size_t)r * r), Qv((size_t)r * r), al(r);
+  const double inv = isinf(sigma_r) ? 0.0 : 1.0 / (2.0 * sigma_r * sigma_r);
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < r; ++j) {
+      double d2 = 0.0;
+      for (int k = 0; k < D; ++k) {
+        const double t = c[i * D + k] - c[j * D + k];
+        d2 += t * t;
+      }
+      A[i * r + j] = exp(-d2 * inv);
+    }
+  if (sym_eig(r, A.data(), al.data(), Qv.data()) != 0)
+    return fail(ctx, NKF_ERR_NUMERICAL, "eigendecomposition of A did not converge");
+  const double amax = al[r - 1];
+  int keep = 0;
+  for (int j = 0; j < r; ++j)
+    if (al[j] > tau * amax && al[j] > 0.0) ++keep;
+  if (Q) memcpy(Q, Qv.data(), sizeof(double) * r * r);
+  if (alpha) memcpy(alpha, al.data(), sizeof(double) * r);
+  if (keep == 0) {
+    if (r_eff) *r_eff = 0;
+    return fail(ctx, NKF_ERR_NUMERICAL, "every eigenvalue of A was truncated");
+  }
+  // kept eigenvalues are the largest ones; columns in ascending order
+  const int first = r - keep;
+  if (F) {
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < r; ++j) F[i * r + j] = 0.0;
+    for (int j = 0; j < keep; ++j) {
+      const double s = 1.0 / sqrt(al[first + j]);
+      for (int i = 0; i < r; ++i) F[i * r + j] = Qv[i * r + first + j] * s;
+    }
+  }
+  if (r_eff) *r_eff = keep;
+  return NKF_OK;
+}
+
+// Workspace of the forward path after the landmarks are known.
+struct FwdBufs {
+  float *f0;
+  unsigned *mm;
+  float *u;
+  float *eta_buf;
+};
+
+void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b) {
+  b.f0 = cv.take<float>(rs.C);
+  b.mm = cv.take<unsigned>(2 * (size_t)rs.C);
+  b.u = cv.take<float>((size_t)r_eff * rs.N);
+  b.eta_buf = cv.take<float>(rs.C > 3 ? rs.N : 1);
+}
+
+nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, const float *c, const double *F,
+                   int r_eff, float *out, float *eta_out, const FwdBufs &b) {
+  {
+    StageTimer tm(ctx, NKF_STAGE_EMBED);
+    HIP_TRY(ctx, launch_center(rs.g.f, rs.N, rs.C, prm->center, b.f0, b.mm, ctx->stream));
+    HIP_TRY(ctx, launch_embed(rs.g, c, prm->r, F, r_eff, prm->sigma_r, b.u, ctx->stream));
+  }
+  ConvProblem pb{};
+  pb.H = rs.H;
+  pb.W = rs.W;
+  pb.C = rs.C;
+  pb.S = rs.S;
+  pb.r_eff = r_eff;
+  pb.f = rs.g.f;
+  pb.f0 = b.f0;
+  pb.u = b.u;
+  pb.taps = rs.taps;
+  pb.out = out;
+  pb.eta_out = eta_out;
+  pb.eta_buf = b.eta_buf;
+  StageTimer tm(ctx, NKF_STAGE_CONV);
+  HIP_TRY(ctx, launch_conv_contract(pb, ctx->stream));
+  return NKF_OK;
+}
+
+struct KmBufs {
+  double *sums;
+  int *lab_scratch;
+};
+
+void carve_km(Carve &cv, const Resolved &rs, int r, KmBufs &b) {
+  b.sums = cv.take<double>((size_t)r * (rs.D + 1));
+  b.lab_scratch = cv.take<int>(rs.N);
+}
+
+nkf_status run_lloyd(nkf_ctx *ctx, const Resolved &rs, int r, float *c, int iters, int *labels,
+                     const KmBufs &b) {
+  StageTimer tm(ctx, NKF_STAGE_KMEANS);
+  for (int it = 0; it < iters; ++it) {
+    HIP_TRY(ctx, launch_fill_f64(b.sums, (int64_t)r * (rs.D + 1), 0.0, ctx->stream));
+    HIP_TRY(ctx, launch_kmeans_assign(rs.g, c, r, b.sums, it + 1 == iters ? labels : nullptr,
+                                      b.lab_scratch, ctx->stream));
+    HIP_TRY(ctx, launch_kmeans_update(b.sums, r, rs.D, c, ctx->stream));
+  }
+  return NKF_OK;
+}
+
+nkf_status run_seed(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, float *c, int64_t *idx_dev) {
+  const int r = prm->r;
+  nkf_status st = ensure_pinned(ctx, 64 * 1024 + sizeof(int64_t) * r);
+  if (st != NKF_OK) return st;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // pinned buffer may still feed an earlier copy
+  int64_t *idx = reinterpret_cast<int64_t *>(ctx->pinned);
+  draw_indices(rs.N, r, prm->seed, idx);
+  StageTimer tm(ctx, NKF_STAGE_SEED);
+  HIP_TRY(ctx, hipMemcpyAsync(idx_dev, idx, sizeof(int64_t) * r, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, launch_gather_landmarks(rs.g, idx_dev, r, c, ctx->stream));
+  return NKF_OK;
+}
+
+}  // namespace
+
+// =============================================================================
+extern "C" {
+
+void nkf_params_default(nkf_params *p) {
+  if (!p) return;
+  p->sigma_s = 3.0;
+  p->sigma_r = 30.0;
+  p->r = 16;
+  p->radius = -1;
+  p->spatial = NKF_SPATIAL_GAUSSIAN;
+  p->guide = NKF_GUIDE_SELF;
+  p->patch_radius = 3;
+  p->prec = NKF_PREC_FP32;
+  p->kmeans_iters = 10;
+  p->seed = 0;
+  p->eig_rel_tol = 1e-10;
+  p->center = NAN;
+}
+
+const char *nkf_version(void) { return "nkf 0.1 (gfx950)"; }
+
+nkf_status nkf_create(nkf_ctx **out, void *hip_stream) {
+  if (!out) return fail(nullptr, NKF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  nkf_ctx *c = new (std::nothrow) nkf_ctx();
+  if (!c) return fail(nullptr, NKF_ERR_OUT_OF_MEMORY, "context allocation failed");
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return fail(nullptr, NKF_ERR_HIP, "hipGetDevice failed (no GPU?)");
+  }
+  *out = c;
+  return NKF_OK;
+}
+
+nkf_status nkf_set_stream(nkf_ctx *ctx, void *hip_stream) {
+  if (!ctx) return fail(nullptr, NKF_ERR_INVALID_ARG, "ctx is NULL");
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return NKF_OK;
+}
+
+nkf_status nkf_enable_timing(nkf_ctx *ctx, int enable) {
+  if (!ctx) return fail(nullptr, NKF_ERR_INVALID_ARG, "ctx is NULL");
+  ctx->timing = enable != 0;
+  return NKF_OK;
+}
+
+nkf_status nkf_stage_times(nkf_ctx *ctx, double *ms_host, int *count_host, int reset) {
+  if (!ctx) return fail(nullptr, NKF_ERR_INVALID_ARG, "ctx is NULL");
+  if (!ms_host) return fail(ctx, NKF_ERR_INVALID_ARG, "ms_host is NULL");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  double ms[NKF_STAGE_COUNT];
+  int cnt[NKF_STAGE_COUNT];
+  for (int i = 0; i < NKF_STAGE_COUNT; ++i) {
+    ms[i] = ctx->host_ms[i];
+    cnt[i] = ctx->host_count[i];
+  }
+  for (auto &iv : ctx->pending) {
+    float e = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&e, iv.a, iv.b));
+    ms[iv.stage] += e;
+    cnt[iv.stage] += 1;
+  }
+  for (int i = 0; i < NKF_STAGE_COUNT; ++i) {
+    ms_host[i] = ms[i];
+    if (count_host) count_host[i] = cnt[i];
+  }
+  if (reset) {
+    for (auto &iv : ctx->pending) {
+      ctx->event_pool.push_back(iv.a);
+      ctx->event_pool.push_back(iv.b);
+    }
+    ctx->pending.clear();
+    for (int i = 0; i < NKF_STAGE_COUNT; ++i) {
+      ctx->host_ms[i] = 0.0;
+      ctx->host_count[i] = 0;
+    }
+  }
+  return NKF_OK;
+}
+
+nkf_status nkf_destroy(nkf_ctx *ctx) {
+  if (!ctx) return NKF_OK;
+  nkf_status st = NKF_OK;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) st = NKF_ERR_HIP;
+  for (auto &iv : ctx->pending) {
+    (void)hipEventDestroy(iv.a);
+    (void)hipEventDestroy(iv.b);
+  }
+  for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+  return st;
+}
+
+const char *nkf_last_error(const nkf_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+nkf_status nkf_set_workspace_limit(nkf_ctx *ctx, size_t bytes) {
+  if (!ctx) return fail(nullptr, NKF_ERR_INVALID_ARG, "ctx is NULL");
+  ctx->ws_limit = bytes;
+  return NKF_OK;
+}
+
+size_t nkf_workspace_bytes(const nkf_ctx *ctx) { return ctx ? ctx->ws_bytes : 0; }
+
+nkf_status nkf_seed_indices(int64_t N, int r, uint64_t seed, int64_t *idx_host) {
+  if (!idx_host) return fail(nullptr, NKF_ERR_INVALID_ARG, "idx_host is NULL");
+  if (N < 1 || r < 1 || r > N) return fail(nullptr, NKF_ERR_INVALID_ARG, "need 1 <= r <= N");
+  draw_indices(N, r, seed, idx_host);
+  return NKF_OK;
+}
+
+nkf_status nkf_spatial_taps(int radius, double sigma_s, int spatial, int *S_out, float *taps_host) {
+  if (!S_out) return fail(nullptr, NKF_ERR_INVALID_ARG, "S_out is NULL");
+  if (radius < -1) return fail(nullptr, NKF_ERR_INVALID_ARG, "radius must be >= -1");
+  if ((spatial == NKF_SPATIAL_GAUSSIAN || radius < 0) && !(sigma_s > 0.0 && isfinite(sigma_s)))
+    return fail(nullptr, NKF_ERR_INVALID_ARG, "sigma_s must be finite and > 0");
+  if (spatial != NKF_SPATIAL_GAUSSIAN && spatial != NKF_SPATIAL_BOX)
+    return fail(nullptr, NKF_ERR_INVALID_ARG, "unknown spatial kernel");
+  const int S = resolve_radius(radius, sigma_s);
+  if (S > kMaxRadius) return fail(nullptr, NKF_ERR_UNSUPPORTED, "window radius %d exceeds %d", S, kMaxRadius);
+  *S_out = S;
+  if (taps_host)
+    for (int t = -S; t <= S; ++t)
+      taps_host[t + S] = spatial == NKF_SPATIAL_BOX ? 1.0f : (float)exp(-(double)t * t / (2.0 * sigma_s * sigma_s));
+  return NKF_OK;
+}
+
+nkf_status nkf_landmark_factor(int r, int D, const double *centroids_host, double sigma_r, double tau,
+                               double *eigvecs_host, double *eigvals_host, double *F_host, int *r_eff) {
+  if (r < 1 || r > kMaxLandmarks || D < 1) return fail(nullptr, NKF_ERR_INVALID_ARG, "need 1 <= r <= 256, D >= 1");
+  if (!centroids_host || !F_host || !r_eff) return fail(nullptr, NKF_ERR_INVALID_ARG, "NULL pointer");
+  if (!(sigma_r > 0.0)) return fail(nullptr, NKF_ERR_INVALID_ARG, "sigma_r must be > 0");
+  if (!(tau >= 0.0)) return fail(nullptr, NKF_ERR_INVALID_ARG, "tau must be >= 0");
+  return factor(nullptr, r, D, centroids_host, sigma_r, tau, eigvecs_host, eigvals_host, F_host, r_eff);
+}
+
+nkf_status nkf_kmeans_iterate(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, const float *p,
+                              const nkf_params *prm, float *centroids, int iters, int *labels) {
+  Resolved rs;
+  nkf_status st = validate(ctx, H, W, C, f, D, p, prm, rs);
+  if (st != NKF_OK) return st;
+  if (!centroids) return fail(ctx, NKF_ERR_INVALID_ARG, "centroids is NULL");
+  if (iters < 0) return fail(ctx, NKF_ERR_INVALID_ARG, "iters must be >= 0");
+  Carve dry{nullptr};
+  KmBufs kb;
+  carve_km(dry, rs, prm->r, kb);
+  if ((st = ensure_workspace(ctx, dry.off)) != NKF_OK) return st;
+  Carve cv{ctx->ws};
+  carve_km(cv, rs, prm->r, kb);
+  return run_lloyd(ctx, rs, prm->r, centroids, iters, labels, kb);
+}
+
+nkf_status nkf_kmeans(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, const float *p,
+                      const nkf_params *prm, float *centroids, int *labels) {
+  Resolved rs;
+  nkf_status st = validate(ctx, H, W, C, f, D, p, prm, rs);
+  if (st != NKF_OK) return st;
+  if (!centroids) return fail(ctx, NKF_ERR_INVALID_ARG, "centroids is NULL");
+  Carve dry{nullptr};
+  KmBufs kb;
+  carve_km(dry, rs, prm->r, kb);
+  int64_t *idx = dry.take<int64_t>(prm->r);
+  if ((st = ensure_workspace(ctx, dry.off)) != NKF_OK) return st;
+  Carve cv{ctx->ws};
+  carve_km(cv, rs, prm->r, kb);
+  idx = cv.take<int64_t>(prm->r);
+  if ((st = run_seed(ctx, rs, prm, centroids, idx)) != NKF_OK) return st;
+  return run_lloyd(ctx, rs, prm->r, centroids, prm->kmeans_iters, labels, kb);
+}
+
+nkf_status nkf_filter_landmarks(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, const float *p,
+                                const nkf_params *prm, const float *centroids, const double *F, int r_eff,
+                                float *out, float *eta_out) {
+  Resolved rs;
+  nkf_status st = validate(ctx, H, W, C, f, D, p, prm, rs);
+  if (st != NKF_OK) return st;
+  if (!centroids || !F || !out) return fail(ctx, NKF_ERR_INVALID_ARG, "centroids, F and out are required");
+  if (r_eff < 1 || r_eff > prm->r) return fail(ctx, NKF_ERR_INVALID_ARG, "need 1 <= r_eff <= r");
+  Carve dry{nullptr};
+  FwdBufs fb;
+  carve_fwd(dry, rs, r_eff, fb);
+  if ((st = ensure_workspace(ctx, dry.off)) != NKF_OK) return st;
+  Carve cv{ctx->ws};
+  carve_fwd(cv, rs, r_eff, fb);
+  return run_fwd(ctx, rs, prm, centroids, F, r_eff, out, eta_out, fb);
+}
+
+nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, const float *p,
+                      const nkf_params *prm, float *out, float *eta_out, int *r_eff_out) {
+  Resolved rs;
+  nkf_status st = validate(ctx, H, W, C, f, D, p, prm, rs);
+  if (st != NKF_OK) return st;
+  if (!out) return fail(ctx, NKF_ERR_INVALID_ARG, "out is NULL");
+  const int r = prm->r;
+  // workspace: k-means buffers and landmark state first, forward buffers sized for r_eff = r
+  auto carve_all = [&](Carve &cv, KmBufs &kb, float *&c, int64_t *&idx, double *&Fd, FwdBufs &fb) {
+    carve_km(cv, rs, r, kb);
+    c = cv.take<float>((size_t)r * rs.D);
+    idx = cv.take<int64_t>(r);
+    Fd = cv.take<double>((size_t)r * r);
+    carve_fwd(cv, rs, r, fb);
+  };
+  KmBufs kb;
+  FwdBufs fb;
+  float *c;
+  int64_t *idx;
+  double *Fd;
+  Carve dry{nullptr};
+  carve_all(dry, kb, c, idx, Fd, fb);
+  if ((st = ensure_workspace(ctx, dry.off)) != NKF_OK) return st;
+  const size_t host_bytes = sizeof(double) * ((size_t)r * rs.D + 3 * (size_t)r * r + r) + sizeof(float) * r * rs.D;
+  if ((st = ensure_pinned(ctx, 64 * 1024 + host_bytes)) != NKF_OK) return st;
+  Carve cv{ctx->ws};
+  carve_all(cv, kb, c, idx, Fd, fb);
+
+  if ((st = run_seed(ctx, rs, prm, c, idx)) != NKF_OK) return st;
+  if ((st = run_lloyd(ctx, rs, r, c, prm->kmeans_iters, nullptr, kb)) != NKF_OK) return st;
+  // the one host round trip: landmarks to the host for the FP64 factor
+  int r_eff = 0;
+  if (ctx->timing) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // keep k-means time out of the factor stage
+  {
+    HostTimer ht(ctx, NKF_STAGE_FACTOR);
+    float *c_host = reinterpret_cast<float *>(ctx->pinned);
+    HIP_TRY(ctx, hipMemcpyAsync(c_host, c, sizeof(float) * r * rs.D, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<double> cd((size_t)r * rs.D);
+    for (size_t i = 0; i < cd.size(); ++i) cd[i] = c_host[i];
+    double *F_host = reinterpret_cast<double *>(ctx->pinned + ((sizeof(float) * r * rs.D + 255) & ~(size_t)255));
+    std::vector<double> Fr((size_t)r * r);
+    if ((st = factor(ctx, r, rs.D, cd.data(), prm->sigma_r, prm->eig_rel_tol, nullptr, nullptr, Fr.data(),
+                     &r_eff)) != NKF_OK)
+      return st;
+    // pack F [r, r_eff]
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < r_eff; ++j) F_host[i * r_eff + j] = Fr[i * r + j];
+    HIP_TRY(ctx, hipMemcpyAsync(Fd, F_host, sizeof(double) * r * r_eff, hipMemcpyHostToDevice, ctx->stream));
+  }
+  if (r_eff_out) *r_eff_out = r_eff;
+  return run_fwd(ctx, rs, prm, c, Fd, r_eff, out, eta_out, fb);
+}
+
+nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, const float *p,
+                               const nkf_params *prm, const float *centroids, const double *eigvecs_host,
+                               const double *eigvals_host, int r_eff, const float *grad_out, float *grad_f,
+                               float *grad_p, double *grad_sigma_r_host, double *grad_sigma_s_host) {
+  (void)H; (void)W; (void)C; (void)f; (void)D; (void)p; (void)prm; (void)centroids; (void)eigvecs_host;
+  (void)eigvals_host; (void)r_eff; (void)grad_out; (void)grad_f; (void)grad_p; (void)grad_sigma_r_host;
+  (void)grad_sigma_s_host;
+  return fail(ctx, NKF_ERR_UNSUPPORTED, "backward not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,158 @@
+// Range embedding (Section III): the cross kernel B(i, x) = k(c_i, p(x))
+// (Eq. (defB)) mixed by the FP64 landmark factor F = Q diag(alpha^{-1/2}),
+//     u_k(x) = sum_i F[i][k] exp(-|p(x) - c_i|^2 / (2 sigma_r^2)),
+// so that u(x).u(y) = b(x)^T A^+ b(y) = K_hat(x, y) (Eqs. (hatK), (vk)).  The
+// planes u_k are written planar ([r_eff][N] float32) for the convolution pass.
+// Also the per-channel centring offset f0 of the image.
+//
+// Precision: squared distances are formed in FP64 from the FP32 guide and
+// landmarks (exact differences), and the exponential takes an exact FP64
+// argument reduction exp(-z) = 2^-n * 2^-fr, so the relative error of b does
+// not grow with the exponent; the r x r_eff mix accumulates in FP64.
+#include <hip/hip_runtime.h>
+#include <float.h>
+#include <math.h>
+
+#include "device_common.h"
+
+namespace nkf {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kTilePx = 64;
+
+// exp(-z) for z >= 0 with relative error independent of z.
+__device__ __forceinline__ float exp_neg(double z) {
+  const double y = z * 1.4426950408889634074;  // log2(e)
+  if (y > 160.0) return 0.0f;
+  const double n = floor(y);
+  const float fr = (float)(y - n);
+  return ldexpf(exp2f(-fr), -(int)n);
+}
+
+__global__ __launch_bounds__(kBlock) void embed_kernel(Guide g, int64_t N, const float *__restrict__ c,
+                                                       int r, const double *__restrict__ F, int r_eff,
+                                                       double inv2s2, float *__restrict__ u) {
+  extern __shared__ float smem[];
+  const int D = g.D;
+  float *pt = smem;                          // [D][64]
+  float *bs = smem + (size_t)D * kTilePx;    // [r][64]
+  const int tid = threadIdx.x;
+  const int px = tid & (kTilePx - 1);
+  const int kg = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int64_t base = (int64_t)blockIdx.x * kTilePx; base < N; base += (int64_t)gridDim.x * kTilePx) {
+    __syncthreads();
+    for (int e = tid; e < D * kTilePx; e += kBlock) {
+      const int d = e / kTilePx, q = e - d * kTilePx;
+      const int64_t x = base + q;
+      pt[e] = x < N ? guide_elem(g, x, d) : 0.0f;
+    }
+    __syncthreads();
+    for (int k = kg; k < r; k += 4) {
+      double acc = 0.0;
+      for (int d = 0; d < D; ++d) {
+        const double t = (double)pt[d * kTilePx + px] - (double)c[k * D + d];
+        acc = fma(t, t, acc);
+      }
+      bs[k * kTilePx + px] = exp_neg(acc * inv2s2);
+    }
+    __syncthreads();
+    const int64_t x = base + px;
+    for (int kk = kg; kk < r_eff; kk += 4) {
+      double acc = 0.0;
+      for (int k = 0; k < r; ++k) acc = fma(F[k * r_eff + kk], (double)bs[k * kTilePx + px], acc);
+      if (x < N) u[(int64_t)kk * N + x] = (float)acc;
+    }
+  }
+}
+
+__device__ __forceinline__ unsigned ord_encode(float v) {
+  const unsigned b = __float_as_uint(v);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float ord_decode(unsigned k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+__global__ void mm_init_kernel(unsigned *mm, int C) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < C) {
+    mm[i] = 0xffffffffu;  // running min (encoded)
+    mm[C + i] = 0u;       // running max (encoded)
+  }
+}
+
+// Block size is a multiple of C, so a thread's channel is fixed.
+__global__ void minmax_kernel(const float *__restrict__ f, int64_t total, int C, unsigned *mm) {
+  extern __shared__ unsigned sm[];
+  const int B = blockDim.x;
+  const int tid = threadIdx.x;
+  unsigned lo = 0xffffffffu, hi = 0u;
+  for (int64_t e = (int64_t)blockIdx.x * B + tid; e < total; e += (int64_t)gridDim.x * B) {
+    const unsigned k = ord_encode(f[e]);
+    lo = min(lo, k);
+    hi = max(hi, k);
+  }
+  sm[tid] = lo;
+  sm[B + tid] = hi;
+  __syncthreads();
+  if (tid < C) {
+    for (int m = tid + C; m < B; m += C) {
+      lo = min(lo, sm[m]);
+      hi = max(hi, sm[B + m]);
+    }
+    atomicMin(&mm[tid], lo);
+    atomicMax(&mm[C + tid], hi);
+  }
+}
+
+__global__ void center_final_kernel(const unsigned *mm, int C, float *f0, int use_value, float value) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= C) return;
+  if (use_value) {
+    f0[i] = value;
+  } else {
+    const double lo = ord_decode(mm[i]), hi = ord_decode(mm[C + i]);
+    f0[i] = (float)(0.5 * (lo + hi));
+  }
+}
+
+}  // namespace
+
+hipError_t launch_center(const float *f, int64_t N, int C, double center, float *f0, unsigned *mm,
+                         hipStream_t s) {
+  const int cb = (C + 255) / 256;
+  if (isfinite(center)) {
+    hipLaunchKernelGGL(center_final_kernel, dim3(cb), dim3(256), 0, s, mm, C, f0, 1, (float)center);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(mm_init_kernel, dim3(cb), dim3(256), 0, s, mm, C);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int B = C <= 256 ? C * (256 / C) : C;
+  const int64_t total = N * C;
+  int64_t blocks = (total + (int64_t)B * 16 - 1) / ((int64_t)B * 16);
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(minmax_kernel, dim3((int)blocks), dim3(B), 2 * B * sizeof(unsigned), s, f, total, C, mm);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(center_final_kernel, dim3(cb), dim3(256), 0, s, mm, C, f0, 0, 0.0f);
+  return hipGetLastError();
+}
+
+hipError_t launch_embed(const Guide &g, const float *c, int r, const double *F, int r_eff, double sigma_r,
+                        float *u, hipStream_t s) {
+  const int64_t N = (int64_t)g.H * g.W;
+  const double inv2s2 = isinf(sigma_r) ? 0.0 : 1.0 / (2.0 * sigma_r * sigma_r);
+  const size_t sm = sizeof(float) * ((size_t)g.D + r) * kTilePx;
+  int64_t blocks = (N + kTilePx - 1) / kTilePx;
+  if (blocks > 16384) blocks = 16384;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(embed_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(embed_kernel, dim3((int)blocks), dim3(kBlock), sm, s, g, N, c, r, F, r_eff, inv2s2, u);
+  return hipGetLastError();
+}
+
+}  // namespace nkf

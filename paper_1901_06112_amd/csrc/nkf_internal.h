@@ -1,0 +1,61 @@
+// Internal declarations shared by the host runtime and the HIP kernels of the
+// Nystrom kernel filtering library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nkf {
+
+enum GuideKind { GUIDE_EXPLICIT = 0, GUIDE_SELF = 1, GUIDE_PATCH = 2 };
+
+// Where the guide value p(x)[d] comes from: an explicit [N, D] array, the
+// image itself (D == C), or the (2pr+1)^2 C patch of f read with symmetric
+// padding in (dy, dx, c) order.
+struct Guide {
+  int kind;
+  const float *p;   // EXPLICIT
+  const float *f;   // SELF / PATCH
+  int H, W, C, D, pr;
+};
+
+// Window radius limit of the convolution kernels (T = 2S+1 <= 33 taps).
+constexpr int kMaxRadius = 16;
+constexpr int kMaxLandmarks = 256;
+
+struct Taps {
+  float w[2 * kMaxRadius + 1];
+};
+
+// ---- kernels_kmeans.hip -----------------------------------------------------
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+hipError_t launch_gather_landmarks(const Guide &g, const int64_t *idx, int r, float *c,
+                                   hipStream_t s);
+// One Lloyd assignment: labels (nullable) and per-cluster sums/counts
+// accumulated into sums [r, D+1] (column D holds the count); sums must be zero.
+hipError_t launch_kmeans_assign(const Guide &g, const float *c, int r, double *sums, int *labels,
+                                int *label_scratch, hipStream_t s);
+hipError_t launch_kmeans_update(const double *sums, int r, int D, float *c, hipStream_t s);
+
+// ---- kernels_embed.hip ------------------------------------------------------
+// f0[c] = center (finite) or (min_c + max_c) / 2 over f.
+hipError_t launch_center(const float *f, int64_t N, int C, double center, float *f0,
+                         unsigned *scratch /*[2C]*/, hipStream_t s);
+// u[k][x] = sum_j F[j][k] exp(-|p(x) - c_j|^2 / (2 sigma_r^2)), planar [r_eff][N] float32.
+hipError_t launch_embed(const Guide &g, const float *c, int r, const double *F, int r_eff,
+                        double sigma_r, float *u, hipStream_t s);
+
+// ---- kernels_conv.hip -------------------------------------------------------
+struct ConvProblem {
+  int H, W, C, S, r_eff;
+  const float *f;     // [H, W, C]
+  const float *f0;    // [C] centring offsets
+  const float *u;     // [r_eff][N]
+  Taps taps;
+  float *out;         // [H, W, C]
+  float *eta_out;     // nullable [N]
+  float *eta_buf;     // [N] scratch used when C > 3 (eta pass, then channel chunks)
+};
+hipError_t launch_conv_contract(const ConvProblem &pb, hipStream_t s);
+
+}  // namespace nkf
