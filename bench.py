@@ -60,7 +60,7 @@ def _traffic(n_launch_px):
         return None
 
 
-def cpu_baseline(crop=384):
+def cpu_baseline(crop=1024):
     """The FP64 oracle (k-means + Algorithm 1) on a crop x crop centre crop
     of the workload image, single-threaded BLAS."""
     import numpy as np
@@ -90,7 +90,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-crop", type=int, default=384)
+    ap.add_argument("--cpu-crop", type=int, default=1024)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (the filter has no multi-GPU path); got --gpus {a.gpus}",

@@ -160,3 +160,41 @@ def nystrom_kernel_matrix(P, c, sigma_r, tau=DEFAULT_TAU):
     """K_hat = sum_k alpha_k v_k v_k^T of Eq. (hatK) (tiny inputs only)."""
     alpha, V = extrapolated_eigvecs(c, P, sigma_r, tau)
     return (V * alpha[None, :]) @ V.T
+
+
+def storage_error_bound(f, p, c, sigma_s, sigma_r, S, spatial="gaussian", tau=DEFAULT_TAU, center=None):
+    """First-order sensitivity of g_hat(x) to a relative perturbation of every
+    stored intermediate (the embedding planes u_k, the products u_k f~ and the
+    convolved planes), used to derive per-pixel tolerances for reduced
+    precision evaluations of Algorithm 1:
+
+        B(x, c) = ( sum_k |u_k(x)| (w * |u_k f~_c|)(x)
+                    + |g~_c(x)| sum_k |u_k(x)| (w * |u_k|)(x) ) / |eta_hat(x)|
+
+    with u = F^T b (u(x).u(y) = K_hat(x, y)), f~ = f - f0.  A relative error
+    delta in each stored value moves g_hat(x) by at most about delta B(x, c).
+    Returns B as [H, W, C]."""
+    f = np.asarray(f, np.float64)
+    p = np.asarray(p, np.float64)
+    H, W, C = f.shape
+    f0 = 0.5 * (f.min(axis=(0, 1)) + f.max(axis=(0, 1))) if center is None else center
+    fc = f - f0
+    w1 = spatial_taps(sigma_s, S, spatial)
+    alpha, Wv = landmark_eig(c, sigma_r, tau)
+    U = (cross_kernel_sr(c, p.reshape(H * W, -1), sigma_r) @ Wv) / np.sqrt(alpha)[None, :]
+    eta = np.zeros((H, W))
+    eabs = np.zeros((H, W))
+    zeta = np.zeros((H, W, C))
+    zabs = np.zeros((H, W, C))
+    for k in range(U.shape[1]):
+        uk = U[:, k].reshape(H, W)
+        ua = np.abs(uk)
+        eta += uk * conv_zero(uk, w1)
+        eabs += ua * conv_zero(ua, w1)
+        zeta += uk[:, :, None] * conv_zero(uk[:, :, None] * fc, w1)
+        zabs += ua[:, :, None] * conv_zero(ua[:, :, None] * np.abs(fc), w1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        gt = zeta / eta[:, :, None]
+        B = (zabs + np.abs(gt) * eabs[:, :, None]) / np.abs(eta)[:, :, None]
+    B[~np.isfinite(B)] = np.inf
+    return B

@@ -16,6 +16,10 @@
 //           acc += u_k * Z in registers.
 // The r_eff (C+1) convolved planes never reach HBM.  After the k loop the
 // epilogue divides by eta and writes g.
+//
+// Precision: each FIR pass accumulates its taps in FP64 (FP64 FMA issues at
+// the FP32 rate on CDNA4 without packed math) and stores its result as FP32,
+// so each convolved value carries one rounding instead of 2S+1.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -39,7 +43,7 @@ struct ConvArgs {
   float *out;
   float *eta_out;   // nullable
   float *eta_buf;   // eta written (HAS_E, NP == 1) or read (!HAS_E)
-  float w[2 * kMaxRadius + 1];
+  double w[2 * kMaxRadius + 1];  // FP32 taps widened to FP64
 };
 
 template <int S, int NP, bool HAS_E, int RC>
@@ -152,24 +156,25 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
           // at slot + RING so that column windows never wrap
           const int slot = (ic % (1 + LAG)) * RC + r_rr;
           const bool mirror = slot < 2 * S;
-          float win[K::WIN];
+          double win[K::WIN];
           const float4 *src = reinterpret_cast<const float4 *>(&stg[(r_p * RC + r_rr) * SW + r_sg * RUN]);
 #pragma unroll
           for (int v4 = 0; v4 < K::WIN / 4; ++v4) {
             const float4 q = src[v4];
-            win[4 * v4 + 0] = q.x;
-            win[4 * v4 + 1] = q.y;
-            win[4 * v4 + 2] = q.z;
-            win[4 * v4 + 3] = q.w;
+            win[4 * v4 + 0] = (double)q.x;
+            win[4 * v4 + 1] = (double)q.y;
+            win[4 * v4 + 2] = (double)q.z;
+            win[4 * v4 + 3] = (double)q.w;
           }
           float *dst = &ring[(r_p * RINGX + slot) * kTW + r_sg * RUN];
 #pragma unroll
           for (int i = 0; i < RUN; ++i) {
-            float s = 0.0f;
+            double s = 0.0;
 #pragma unroll
-            for (int t = 0; t < T; ++t) s = fmaf(a.w[t], win[i + t], s);
-            dst[i] = s;
-            if (mirror) dst[RING * kTW + i] = s;
+            for (int t = 0; t < T; ++t) s = fma(a.w[t], win[i + t], s);
+            const float sf = (float)s;
+            dst[i] = sf;
+            if (mirror) dst[RING * kTW + i] = sf;
           }
           if (r_p == 0) {
             // raw u_k at the tile's own columns, for the contraction
@@ -192,15 +197,15 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
           const int b0 = (oc * RC) % RING + c_sub * RUN;   // < RING, window ends < RINGX
           const float *col = &ring[(c_p * RINGX + b0) * kTW + c_x];
           const float *ucol = &uring[(b0 + S) * kTW + c_x];
-          float win[RUN + 2 * S];
+          double win[RUN + 2 * S];
 #pragma unroll
           for (int j = 0; j < RUN + 2 * S; ++j) win[j] = col[j * kTW];
 #pragma unroll
           for (int i = 0; i < RUN; ++i) {
-            float z = 0.0f;
+            double z = 0.0;
 #pragma unroll
-            for (int t = 0; t < T; ++t) z = fmaf(a.w[t], win[i + t], z);
-            acc[oc][i] = fmaf(ucol[i * kTW], z, acc[oc][i]);
+            for (int t = 0; t < T; ++t) z = fma(a.w[t], win[i + t], z);
+            acc[oc][i] = fmaf(ucol[i * kTW], (float)z, acc[oc][i]);
           }
           (void)o0;
         }
@@ -320,7 +325,7 @@ hipError_t launch_conv_contract(const ConvProblem &pb, hipStream_t s) {
   a.out = pb.out;
   a.eta_out = pb.eta_out;
   a.eta_buf = pb.eta_buf;
-  for (int t = 0; t < 2 * kMaxRadius + 1; ++t) a.w[t] = pb.taps.w[t];
+  for (int t = 0; t < 2 * kMaxRadius + 1; ++t) a.w[t] = (double)pb.taps.w[t];
   switch (pb.S) {
 #define NKF_CASE(SV) \
   case SV:           \
