@@ -365,19 +365,16 @@ struct KmBufs {
 };
 
 void carve_km(Carve &cv, const Resolved &rs, int r, KmBufs &b) {
-  b.sums = cv.take<double>((size_t)r * (rs.D + 1));
+  b.sums = cv.take<double>(kmeans_partials_doubles(r, rs.D));
   b.lab_scratch = cv.take<int>(rs.N);
 }
 
 nkf_status run_lloyd(nkf_ctx *ctx, const Resolved &rs, int r, float *c, int iters, int *labels,
                      const KmBufs &b) {
   StageTimer tm(ctx, NKF_STAGE_KMEANS);
-  for (int it = 0; it < iters; ++it) {
-    HIP_TRY(ctx, launch_fill_f64(b.sums, (int64_t)r * (rs.D + 1), 0.0, ctx->stream));
-    HIP_TRY(ctx, launch_kmeans_assign(rs.g, c, r, b.sums, it + 1 == iters ? labels : nullptr,
-                                      b.lab_scratch, ctx->stream));
-    HIP_TRY(ctx, launch_kmeans_update(b.sums, r, rs.D, c, ctx->stream));
-  }
+  for (int it = 0; it < iters; ++it)
+    HIP_TRY(ctx, launch_kmeans_step(rs.g, c, r, b.sums, it + 1 == iters ? labels : nullptr, b.lab_scratch,
+                                    ctx->stream));
   return NKF_OK;
 }
 

@@ -31,6 +31,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kTW = 32;
+constexpr int kTWP = kTW + 4;  // ring row stride (floats): rows shift by 4 banks
 
 struct ConvArgs {
   int H, W, C, r_eff;
@@ -49,7 +50,10 @@ struct ConvArgs {
 template <int S, int NP, bool HAS_E, int RC>
 struct Cfg {
   static constexpr int T = 2 * S + 1;
-  static constexpr int SW = ((kTW + 2 * S + 3) / 4) * 4;
+  // staging row stride: a multiple of 4 floats (16-byte rows) that is 4 mod 8,
+  // so the b128 reads of neighbouring rows land in disjoint LDS banks
+  static constexpr int SW0 = ((kTW + 2 * S + 3) / 4) * 4;
+  static constexpr int SW = (SW0 % 8 == 0) ? SW0 + 4 : SW0;
   static constexpr int RUN = RC * NP * kTW / kBlock;          // outputs per thread per pass
   static constexpr int SEGS = kTW / RUN;                      // row-pass segments per row
   static constexpr int SUBS = kBlock / (kTW * NP);            // column-pass row groups
@@ -62,8 +66,8 @@ struct Cfg {
   static constexpr int UPL = HAS_E ? 0 : NP;                  // index of the raw-u staged plane
   static constexpr int WIN = ((RUN + 2 * S + 3) / 4) * 4;
   static constexpr int STG = NPU * RC * SW;                   // staging floats
-  static constexpr int RINGF = NP * RINGX * kTW;              // convolved-row ring floats
-  static constexpr int URINGF = RINGX * kTW;                  // raw-u ring floats
+  static constexpr int RINGF = NP * RINGX * kTWP;             // convolved-row ring floats
+  static constexpr int URINGF = RINGX * kTWP;                 // raw-u ring floats
   static constexpr int ETAB = NCH_MAX * RC * kTW;             // epilogue eta tile
   static constexpr int SMEM = (STG + RINGF + URINGF) > ETAB ? (STG + RINGF + URINGF) : ETAB;
   static_assert(RUN * SEGS == kTW, "row pass split");
@@ -87,8 +91,8 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
   constexpr int RINGX = K::RINGX, NCH_MAX = K::NCH_MAX, NCHAN = K::NCHAN, UPL = K::UPL;
   __shared__ __attribute__((aligned(16))) float smem[K::SMEM];
   float *stg = smem;                        // [NPU][RC][SW]
-  float *ring = smem + K::STG;              // [NP][RINGX][32]
-  float *uring = ring + K::RINGF;           // [RINGX][32]
+  float *ring = smem + K::STG;              // [NP][RINGX][kTWP]
+  float *uring = ring + K::RINGF;           // [RINGX][kTWP]
 
   const int tid = threadIdx.x;
   const int L = xcd_swizzle(blockIdx.x, a.nblocks);
@@ -102,14 +106,18 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
   const int H = a.H, W = a.W, C = a.C;
   const int64_t N = (int64_t)H * W;
 
-  // row-pass role
+  // row-pass role (segment fastest, then row: a quarter-wave covers all banks)
   const int r_sg = tid % SEGS;
-  const int r_p = (tid / SEGS) % NP;
-  const int r_rr = tid / (SEGS * NP);
+  const int r_rr = (tid / SEGS) % RC;
+  const int r_p = tid / (SEGS * RC);
   // column-pass role
   const int c_x = tid % kTW;
   const int c_p = (tid / kTW) % NP;
   const int c_sub = tid / (kTW * NP);
+
+  float f0c[NCHAN > 0 ? NCHAN : 1];
+#pragma unroll
+  for (int ch = 0; ch < NCHAN; ++ch) f0c[ch] = c0 + ch < C ? a.f0[c0 + ch] : 0.0f;
 
   float acc[NCH_MAX][RUN];
 #pragma unroll
@@ -131,25 +139,20 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
         for (int e = tid; e < RC * SW; e += kBlock) {
           const int rr = e / SW, j = e - rr * SW;
           const int gy = gy0 + rr, gx = tx0 - S + j;
-          float v = 0.0f;
-          if (j < kTW + 2 * S && gy >= 0 && gy < H && gx >= 0 && gx < W) v = uk[gy * W + gx];
-          stg[(UPL * RC + rr) * SW + j] = v;
+          const bool in = j < kTW + 2 * S && gy >= 0 && gy < H && gx >= 0 && gx < W;
+          const float uv = in ? uk[gy * W + gx] : 0.0f;
+          stg[(UPL * RC + rr) * SW + j] = uv;
+          if constexpr (NCHAN > 0) {
+            const float *fp = fk + (int64_t)(in ? gy * W + gx : 0) * C + c0;
+#pragma unroll
+            for (int ch = 0; ch < NCHAN; ++ch) {
+              float v = 0.0f;
+              if (in && uv != 0.0f && c0 + ch < C) v = (fp[ch] - f0c[ch]) * uv;
+              stg[(((HAS_E ? 1 : 0) + ch) * RC + rr) * SW + j] = v;
+            }
+          }
         }
         __syncthreads();
-        if constexpr (NCHAN > 0) {
-          for (int e = tid; e < RC * SW * NCHAN; e += kBlock) {
-            const int ch = e % NCHAN;
-            const int rest = e / NCHAN;
-            const int j = rest % SW, rr = rest / SW;
-            const int gy = gy0 + rr, gx = tx0 - S + j, gc = c0 + ch;
-            const float uv = stg[(UPL * RC + rr) * SW + j];
-            float v = 0.0f;
-            if (uv != 0.0f && gc < C && j < kTW + 2 * S && gy >= 0 && gy < H && gx >= 0 && gx < W)
-              v = (fk[(int64_t)(gy * W + gx) * C + gc] - a.f0[gc]) * uv;
-            stg[(((HAS_E ? 1 : 0) + ch) * RC + rr) * SW + j] = v;
-          }
-          __syncthreads();
-        }
         // ---- row pass: horizontal FIR into the ring ---------------------------
         {
           // ring slot of R row q = ic*RC + rr; rows with slot < 2S are mirrored
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
             win[4 * v4 + 2] = (double)q.z;
             win[4 * v4 + 3] = (double)q.w;
           }
-          float *dst = &ring[(r_p * RINGX + slot) * kTW + r_sg * RUN];
+          float *dst = &ring[(r_p * RINGX + slot) * kTWP + r_sg * RUN];
 #pragma unroll
           for (int i = 0; i < RUN; ++i) {
             double s = 0.0;
@@ -174,17 +177,17 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
             for (int t = 0; t < T; ++t) s = fma(a.w[t], win[i + t], s);
             const float sf = (float)s;
             dst[i] = sf;
-            if (mirror) dst[RING * kTW + i] = sf;
+            if (mirror) dst[RING * kTWP + i] = sf;
           }
           if (r_p == 0) {
             // raw u_k at the tile's own columns, for the contraction
             const float *us = &stg[(UPL * RC + r_rr) * SW + S + r_sg * RUN];
-            float *ud = &uring[slot * kTW + r_sg * RUN];
+            float *ud = &uring[slot * kTWP + r_sg * RUN];
 #pragma unroll
             for (int i = 0; i < RUN; ++i) {
               const float uv = us[i];
               ud[i] = uv;
-              if (mirror) ud[RING * kTW + i] = uv;
+              if (mirror) ud[RING * kTWP + i] = uv;
             }
           }
         }
@@ -195,17 +198,17 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
           // local output rows o0 .. o0+RUN-1 need R rows o0 .. o0+RUN+2S-1
           const int o0 = oc * RC + c_sub * RUN;
           const int b0 = (oc * RC) % RING + c_sub * RUN;   // < RING, window ends < RINGX
-          const float *col = &ring[(c_p * RINGX + b0) * kTW + c_x];
-          const float *ucol = &uring[(b0 + S) * kTW + c_x];
+          const float *col = &ring[(c_p * RINGX + b0) * kTWP + c_x];
+          const float *ucol = &uring[(b0 + S) * kTWP + c_x];
           double win[RUN + 2 * S];
 #pragma unroll
-          for (int j = 0; j < RUN + 2 * S; ++j) win[j] = col[j * kTW];
+          for (int j = 0; j < RUN + 2 * S; ++j) win[j] = col[j * kTWP];
 #pragma unroll
           for (int i = 0; i < RUN; ++i) {
             double z = 0.0;
 #pragma unroll
             for (int t = 0; t < T; ++t) z = fma(a.w[t], win[i + t], z);
-            acc[oc][i] = fmaf(ucol[i * kTW], (float)z, acc[oc][i]);
+            acc[oc][i] = fmaf(ucol[i * kTWP], (float)z, acc[oc][i]);
           }
           (void)o0;
         }

@@ -16,6 +16,8 @@ namespace nkf {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kMaxPartials = 1024;        // blocks of the small-D assignment
+constexpr int kMaxPartialsGeneric = 256;  // blocks of the generic accumulation
 
 __global__ void fill_f64_kernel(double *p, int64_t n, double v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -32,68 +34,57 @@ __global__ void gather_kernel(Guide g, const int64_t *__restrict__ idx, int r,
   }
 }
 
-// Adds the guide values (and a count of 1) of the lanes whose label is shared
-// with the wave leader into acc[label][0..D], one distinct label at a time.
-// All 64 lanes of the wave must call this together.
-template <int D>
-__device__ __forceinline__ void wave_accumulate_small(bool valid, int lab, const float (&pv)[D],
-                                                      double *acc) {
-  bool active = valid;
-  while (true) {
-    const uint64_t m = __ballot(active);
-    if (m == 0) break;
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    const int L = __shfl(lab, leader, kWave);
-    const bool mine = active && lab == L;
-    float s[D + 1];
-#pragma unroll
-    for (int j = 0; j < D; ++j) s[j] = wave_sum(mine ? pv[j] : 0.0f);
-    s[D] = wave_sum(mine ? 1.0f : 0.0f);
-    if (lane_id() == 0) {
-#pragma unroll
-      for (int j = 0; j <= D; ++j) atomicAdd(&acc[L * (D + 1) + j], (double)s[j]);
-    }
-    active = active && !mine;
-  }
-}
-
+// Block b writes its per-cluster sums to partials[b][r][D+1] (every entry,
+// zeros included); the update kernel reduces the partials in block order.
+// Distances in the GEMM form |c|^2 - 2 p.c (|p|^2 is common to all clusters
+// and drops out of the argmin); each lane adds its pixel to the block's FP64
+// accumulators with native LDS atomics.
 template <int D>
 __global__ __launch_bounds__(kBlock) void assign_small_kernel(const float *__restrict__ P, int64_t N,
                                                               const float *__restrict__ c, int r,
-                                                              double *__restrict__ sums,
+                                                              double *__restrict__ partials,
                                                               int *__restrict__ labels) {
-  __shared__ float sc[kMaxLandmarks * D];
+  constexpr int DS = D + 1;  // stored per cluster: -2 c (D values), |c|^2
+  __shared__ __attribute__((aligned(16))) float sc[kMaxLandmarks * DS];
   __shared__ double sacc[kMaxLandmarks * (D + 1)];
   const int tid = threadIdx.x;
-  for (int i = tid; i < r * D; i += kBlock) sc[i] = c[i];
+  for (int k = tid; k < r; k += kBlock) {
+    float n2 = 0.0f;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const float v = c[k * D + j];
+      sc[k * DS + j] = -2.0f * v;
+      n2 = fmaf(v, v, n2);
+    }
+    sc[k * DS + D] = n2;
+  }
   for (int i = tid; i < r * (D + 1); i += kBlock) sacc[i] = 0.0;
   __syncthreads();
   for (int64_t base = (int64_t)blockIdx.x * kBlock; base < N; base += (int64_t)gridDim.x * kBlock) {
     const int64_t x = base + tid;
-    const bool valid = x < N;
+    if (x >= N) continue;
     float pv[D];
 #pragma unroll
-    for (int j = 0; j < D; ++j) pv[j] = valid ? P[x * D + j] : 0.0f;
+    for (int j = 0; j < D; ++j) pv[j] = P[x * D + j];
     float best = FLT_MAX;
     int bi = 0;
     for (int k = 0; k < r; ++k) {
-      float d2 = 0.0f;
+      float d2 = sc[k * DS + D];
 #pragma unroll
-      for (int j = 0; j < D; ++j) {
-        const float t = pv[j] - sc[k * D + j];
-        d2 = fmaf(t, t, d2);
-      }
+      for (int j = 0; j < D; ++j) d2 = fmaf(pv[j], sc[k * DS + j], d2);
       if (d2 < best) {
         best = d2;
         bi = k;
       }
     }
-    if (valid && labels) labels[x] = bi;
-    wave_accumulate_small<D>(valid, bi, pv, sacc);
+    if (labels) labels[x] = bi;
+#pragma unroll
+    for (int j = 0; j < D; ++j) atomicAdd(&sacc[bi * (D + 1) + j], (double)pv[j]);
+    atomicAdd(&sacc[bi * (D + 1) + D], 1.0);
   }
   __syncthreads();
-  for (int i = tid; i < r * (D + 1); i += kBlock)
-    if (sacc[i] != 0.0) atomicAdd(&sums[i], sacc[i]);
+  double *dst = partials + (size_t)blockIdx.x * r * (D + 1);
+  for (int i = tid; i < r * (D + 1); i += kBlock) dst[i] = sacc[i];
 }
 
 // ---- generic D: labels from a pixel tile in LDS ----------------------------
@@ -166,20 +157,24 @@ __global__ __launch_bounds__(kBlock) void assign_generic_kernel(Guide g, int64_t
   }
 }
 
-// Per-cluster sums of the guide values given labels.  acc in LDS when it fits,
-// otherwise straight to the global FP64 sums.
+// Per-cluster sums of the guide values given labels, into this block's slot
+// partials[b][r][D+1]: accumulated in LDS when it fits, otherwise directly in
+// the slot (which is zeroed first).
 __global__ __launch_bounds__(kBlock) void accumulate_generic_kernel(Guide g, int64_t N,
                                                                     const int *__restrict__ labels,
-                                                                    int r, double *__restrict__ sums,
+                                                                    int r, double *__restrict__ partials,
                                                                     int use_lds) {
   extern __shared__ float sacc[];  // [r][D+1] when use_lds
   const int tid = threadIdx.x;
   const int D = g.D;
   const int stride = D + 1;
+  double *sums = partials + (size_t)blockIdx.x * r * stride;
   if (use_lds) {
     for (int i = tid; i < r * stride; i += kBlock) sacc[i] = 0.0f;
-    __syncthreads();
+  } else {
+    for (int i = tid; i < r * stride; i += kBlock) sums[i] = 0.0;
   }
+  __syncthreads();
   for (int64_t base = (int64_t)blockIdx.x * kBlock; base < N; base += (int64_t)gridDim.x * kBlock) {
     const int64_t x = base + tid;
     const bool valid = x < N;
@@ -212,17 +207,36 @@ __global__ __launch_bounds__(kBlock) void accumulate_generic_kernel(Guide g, int
   }
   if (use_lds) {
     __syncthreads();
-    for (int i = tid; i < r * stride; i += kBlock)
-      if (sacc[i] != 0.0f) atomicAdd(&sums[i], (double)sacc[i]);
+    for (int i = tid; i < r * stride; i += kBlock) sums[i] = (double)sacc[i];
   }
 }
 
-__global__ void update_kernel(const double *__restrict__ sums, int r, int D, float *__restrict__ c) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= r * D) return;
-  const int k = e / D, d = e - k * D;
-  const double cnt = sums[k * (D + 1) + D];
-  if (cnt > 0.0) c[e] = (float)(sums[k * (D + 1) + d] / cnt);
+// c_k = (sum of members) / count.  One block per cluster reduces the
+// per-block partials with a fixed-shape tree (deterministic); an empty
+// cluster keeps its centroid.
+__global__ __launch_bounds__(kBlock) void update_kernel(const double *__restrict__ partials, int nparts,
+                                                        int r, int D, float *__restrict__ c) {
+  __shared__ double red[kBlock];
+  __shared__ double cnt_s;
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const size_t stride = (size_t)r * (D + 1);
+  for (int d = D; d >= 0; --d) {  // the count (d == D) first
+    double s = 0.0;
+    for (int b = tid; b < nparts; b += kBlock) s += partials[b * stride + (size_t)k * (D + 1) + d];
+    red[tid] = s;
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+      if (tid < h) red[tid] += red[tid + h];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      if (d == D)
+        cnt_s = red[0];
+      else if (cnt_s > 0.0)
+        c[k * D + d] = (float)(red[0] / cnt_s);
+    }
+    __syncthreads();
+  }
 }
 
 int grid_for(int64_t n, int per_block, int cap) {
@@ -233,11 +247,12 @@ int grid_for(int64_t n, int per_block, int cap) {
 }
 
 template <int D>
-hipError_t launch_small(const Guide &g, const float *c, int r, double *sums, int *labels, hipStream_t s) {
+hipError_t launch_small(const Guide &g, const float *c, int r, double *partials, int *labels, int *nparts,
+                        hipStream_t s) {
   const int64_t N = (int64_t)g.H * g.W;
   const float *P = g.kind == GUIDE_EXPLICIT ? g.p : g.f;
-  hipLaunchKernelGGL(assign_small_kernel<D>, dim3(grid_for(N, kBlock * 4, 2048)), dim3(kBlock), 0, s,
-                     P, N, c, r, sums, labels);
+  *nparts = grid_for(N, kBlock * 8, kMaxPartials);
+  hipLaunchKernelGGL(assign_small_kernel<D>, dim3(*nparts), dim3(kBlock), 0, s, P, N, c, r, partials, labels);
   return hipGetLastError();
 }
 
@@ -254,15 +269,15 @@ hipError_t launch_gather_landmarks(const Guide &g, const int64_t *idx, int r, fl
   return hipGetLastError();
 }
 
-hipError_t launch_kmeans_assign(const Guide &g, const float *c, int r, double *sums, int *labels,
-                                int *label_scratch, hipStream_t s) {
+static hipError_t assign_accumulate(const Guide &g, const float *c, int r, double *partials, int *labels,
+                                    int *label_scratch, int *nparts, hipStream_t s) {
   const bool contiguous = g.kind != GUIDE_PATCH || g.pr == 0;
   if (contiguous) {
     switch (g.D) {
-      case 1: return launch_small<1>(g, c, r, sums, labels, s);
-      case 2: return launch_small<2>(g, c, r, sums, labels, s);
-      case 3: return launch_small<3>(g, c, r, sums, labels, s);
-      case 4: return launch_small<4>(g, c, r, sums, labels, s);
+      case 1: return launch_small<1>(g, c, r, partials, labels, nparts, s);
+      case 2: return launch_small<2>(g, c, r, partials, labels, nparts, s);
+      case 3: return launch_small<3>(g, c, r, partials, labels, nparts, s);
+      case 4: return launch_small<4>(g, c, r, partials, labels, nparts, s);
       default: break;
     }
   }
@@ -283,13 +298,23 @@ hipError_t launch_kmeans_assign(const Guide &g, const float *c, int r, double *s
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)acc_bytes);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(accumulate_generic_kernel, dim3(grid_for(N, kBlock * 16, 1024)), dim3(kBlock),
-                     use_lds ? acc_bytes : 0, s, g, N, lab, r, sums, use_lds);
+  *nparts = grid_for(N, kBlock * 16, kMaxPartialsGeneric);
+  hipLaunchKernelGGL(accumulate_generic_kernel, dim3(*nparts), dim3(kBlock), use_lds ? acc_bytes : 0, s, g, N,
+                     lab, r, partials, use_lds);
   return hipGetLastError();
 }
 
-hipError_t launch_kmeans_update(const double *sums, int r, int D, float *c, hipStream_t s) {
-  hipLaunchKernelGGL(update_kernel, dim3((r * D + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sums, r, D, c);
+size_t kmeans_partials_doubles(int r, int D) {
+  const int parts = D <= 4 ? kMaxPartials : kMaxPartialsGeneric;
+  return (size_t)parts * r * (D + 1);
+}
+
+hipError_t launch_kmeans_step(const Guide &g, float *c, int r, double *partials, int *labels, int *label_scratch,
+                              hipStream_t s) {
+  int nparts = 0;
+  hipError_t e = assign_accumulate(g, c, r, partials, labels, label_scratch, &nparts, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(update_kernel, dim3(r), dim3(kBlock), 0, s, partials, nparts, r, g.D, c);
   return hipGetLastError();
 }
 

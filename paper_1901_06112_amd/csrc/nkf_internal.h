@@ -31,11 +31,12 @@ struct Taps {
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_gather_landmarks(const Guide &g, const int64_t *idx, int r, float *c,
                                    hipStream_t s);
-// One Lloyd assignment: labels (nullable) and per-cluster sums/counts
-// accumulated into sums [r, D+1] (column D holds the count); sums must be zero.
-hipError_t launch_kmeans_assign(const Guide &g, const float *c, int r, double *sums, int *labels,
-                                int *label_scratch, hipStream_t s);
-hipError_t launch_kmeans_update(const double *sums, int r, int D, float *c, hipStream_t s);
+// Size (doubles) of the per-block partial-sum buffer of one Lloyd step.
+size_t kmeans_partials_doubles(int r, int D);
+// One Lloyd iteration in place on c [r, D]: assignment (labels nullable),
+// per-block cluster sums into `partials`, ordered reduction and mean update.
+hipError_t launch_kmeans_step(const Guide &g, float *c, int r, double *partials, int *labels,
+                              int *label_scratch, hipStream_t s);
 
 // ---- kernels_embed.hip ------------------------------------------------------
 // f0[c] = center (finite) or (min_c + max_c) / 2 over f.
