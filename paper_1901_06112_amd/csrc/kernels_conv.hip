@@ -80,8 +80,19 @@ struct Cfg {
 // (hoisting them keeps hundreds of registers live).
 template <class V>
 __device__ __forceinline__ V opaque(V v) {
-  asm volatile("" : "+s"(v));
+  asm volatile("" : "+v"(v));
   return v;
+}
+
+// sum_t w[t] x[t] for a symmetric window (w[t] == w[2S - t]): the mirrored
+// pair x[t] + x[2S - t] of two FP32 values is exact in FP64, so folding halves
+// the taps held in scalar registers without changing the VALU operation count.
+template <int S>
+__device__ __forceinline__ double fir_sym(const double *w, const double *x) {
+  double s = w[S] * x[S];
+#pragma unroll
+  for (int t = 0; t < S; ++t) s = fma(w[t], x[t] + x[2 * S - t], s);
+  return s;
 }
 
 template <int S, int NP, bool HAS_E, int RC>
@@ -126,32 +137,52 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
     for (int i = 0; i < RUN; ++i) acc[j][i] = 0.0f;
 
   const int nin = a.nch + LAG;
-  for (int k = 0; k < a.r_eff; ++k) {
-    const int ty0 = opaque(ty * TH);
-    const float *uk = a.u + (int64_t)k * N;
+  // Staging data of one input chunk lives in registers between its global
+  // loads and its LDS store: the loads of chunk i+1 are issued right after
+  // chunk i is stored, so their latency hides behind chunk i's FIR passes.
+  constexpr int NPOS = (RC * SW + kBlock - 1) / kBlock;
+  constexpr int NCH1 = NCHAN > 0 ? NCHAN : 1;
+  float pu[NPOS], pf[NPOS][NCH1];
+  auto fetch = [&](int kk, int icc) {
+    const int ty0k = opaque(ty * TH);
+    const float *uk = a.u + (int64_t)kk * N;
     const float *fk = opaque(a.f);
+    const int gy0 = ty0k - S + icc * RC;
+#pragma unroll
+    for (int q = 0; q < NPOS; ++q) {
+      const int e = tid + q * kBlock;
+      const int rr = e / SW, j = e - rr * SW;
+      const int gy = gy0 + rr, gx = tx0 - S + j;
+      const bool in = e < RC * SW && j < kTW + 2 * S && gy >= 0 && gy < H && gx >= 0 && gx < W;
+      pu[q] = in ? uk[gy * W + gx] : 0.0f;
+      const float *fp = fk + (int64_t)(in ? gy * W + gx : 0) * C + c0;
+#pragma unroll
+      for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = (in && c0 + ch < C) ? fp[ch] - f0c[ch] : 0.0f;
+    }
+  };
+  fetch(0, 0);
+  for (int k = 0; k < a.r_eff; ++k) {
 #pragma unroll
     for (int ic = 0; ic < NCH_MAX + LAG; ++ic) {
       if (ic < nin) {
         // ---- stage u_k and u_k f~ for R rows [ic*RC, ic*RC + RC) --------------
-        const int gy0 = ty0 - S + ic * RC;
-        __syncthreads();
-        for (int e = tid; e < RC * SW; e += kBlock) {
-          const int rr = e / SW, j = e - rr * SW;
-          const int gy = gy0 + rr, gx = tx0 - S + j;
-          const bool in = j < kTW + 2 * S && gy >= 0 && gy < H && gx >= 0 && gx < W;
-          const float uv = in ? uk[gy * W + gx] : 0.0f;
-          stg[(UPL * RC + rr) * SW + j] = uv;
-          if constexpr (NCHAN > 0) {
-            const float *fp = fk + (int64_t)(in ? gy * W + gx : 0) * C + c0;
+        // (the previous row pass finished reading the staging buffer before the
+        // barrier that preceded the previous column pass)
 #pragma unroll
-            for (int ch = 0; ch < NCHAN; ++ch) {
-              float v = 0.0f;
-              if (in && uv != 0.0f && c0 + ch < C) v = (fp[ch] - f0c[ch]) * uv;
-              stg[(((HAS_E ? 1 : 0) + ch) * RC + rr) * SW + j] = v;
-            }
+        for (int q = 0; q < NPOS; ++q) {
+          const int e = tid + q * kBlock;
+          if (e < RC * SW) {
+            const int rr = e / SW, j = e - rr * SW;
+            stg[(UPL * RC + rr) * SW + j] = pu[q];
+#pragma unroll
+            for (int ch = 0; ch < NCHAN; ++ch)
+              stg[(((HAS_E ? 1 : 0) + ch) * RC + rr) * SW + j] = pf[q][ch] * pu[q];
           }
         }
+        if (ic + 1 < nin)
+          fetch(k, ic + 1);
+        else if (k + 1 < a.r_eff)
+          fetch(k + 1, 0);
         __syncthreads();
         // ---- row pass: horizontal FIR into the ring ---------------------------
         {
@@ -172,9 +203,7 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
           float *dst = &ring[(r_p * RINGX + slot) * kTWP + r_sg * RUN];
 #pragma unroll
           for (int i = 0; i < RUN; ++i) {
-            double s = 0.0;
-#pragma unroll
-            for (int t = 0; t < T; ++t) s = fma(a.w[t], win[i + t], s);
+            const double s = fir_sym<S>(a.w, &win[i]);
             const float sf = (float)s;
             dst[i] = sf;
             if (mirror) dst[RING * kTWP + i] = sf;
@@ -205,9 +234,7 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
           for (int j = 0; j < RUN + 2 * S; ++j) win[j] = col[j * kTWP];
 #pragma unroll
           for (int i = 0; i < RUN; ++i) {
-            double z = 0.0;
-#pragma unroll
-            for (int t = 0; t < T; ++t) z = fma(a.w[t], win[i + t], z);
+            const double z = fir_sym<S>(a.w, &win[i]);
             acc[oc][i] = fmaf(ucol[i * kTWP], (float)z, acc[oc][i]);
           }
           (void)o0;
