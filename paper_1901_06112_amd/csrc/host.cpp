@@ -641,10 +641,178 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
                                const nkf_params *prm, const float *centroids, const double *eigvecs_host,
                                const double *eigvals_host, int r_eff, const float *grad_out, float *grad_f,
                                float *grad_p, double *grad_sigma_r_host, double *grad_sigma_s_host) {
-  (void)H; (void)W; (void)C; (void)f; (void)D; (void)p; (void)prm; (void)centroids; (void)eigvecs_host;
-  (void)eigvals_host; (void)r_eff; (void)grad_out; (void)grad_f; (void)grad_p; (void)grad_sigma_r_host;
-  (void)grad_sigma_s_host;
-  return fail(ctx, NKF_ERR_UNSUPPORTED, "backward not built yet");
+  Resolved rs;
+  nkf_status st = validate(ctx, H, W, C, f, D, p, prm, rs);
+  if (st != NKF_OK) return st;
+  const int r = prm->r;
+  if (!centroids || !eigvecs_host || !eigvals_host || !grad_out)
+    return fail(ctx, NKF_ERR_INVALID_ARG, "centroids, eigvecs_host, eigvals_host and grad_out are required");
+  if (r_eff < 1 || r_eff > r) return fail(ctx, NKF_ERR_INVALID_ARG, "need 1 <= r_eff <= r");
+  if (C > 3) return fail(ctx, NKF_ERR_UNSUPPORTED, "backward supports C <= 3 (got %d)", C);
+  if (r > 64) return fail(ctx, NKF_ERR_UNSUPPORTED, "backward supports r <= 64 (got %d)", r);
+  if (grad_p && rs.g.kind == GUIDE_PATCH)
+    return fail(ctx, NKF_ERR_UNSUPPORTED, "guide gradient of the patch guide is not implemented");
+  if (grad_sigma_r_host && (r_eff != r || isinf(prm->sigma_r)))
+    return fail(ctx, NKF_ERR_UNSUPPORTED, "sigma_r gradient needs r_eff == r and finite sigma_r");
+  if (grad_sigma_s_host && prm->spatial != NKF_SPATIAL_GAUSSIAN)
+    return fail(ctx, NKF_ERR_UNSUPPORTED, "sigma_s gradient needs the Gaussian window");
+  // F = Q_keep diag(alpha_keep^{-1/2}), kept = the r_eff largest eigenvalues
+  std::vector<double> Fh((size_t)r * r_eff);
+  for (int k = 0; k < r_eff; ++k) {
+    const int idx = r - r_eff + k;
+    const double al = eigvals_host[idx];
+    if (!(al > 0.0)) return fail(ctx, NKF_ERR_NUMERICAL, "kept eigenvalue %d is not positive", idx);
+    for (int j = 0; j < r; ++j) Fh[(size_t)j * r_eff + k] = eigvecs_host[(size_t)j * r + idx] / sqrt(al);
+  }
+  const bool want_R = grad_sigma_r_host != nullptr;
+  const bool want_S = grad_sigma_s_host != nullptr;
+  const int nR = want_R ? r * r_eff : 0;
+  const int nred = bwd_reduce_blocks(rs.N);
+  const int nsig = bwd_conv_max_blocks(H, W);
+  if (bwd_reduce_lds(r, r_eff, rs.D, want_R) > 160 * 1024)
+    return fail(ctx, NKF_ERR_UNSUPPORTED, "backward reduction tile does not fit in LDS (r=%d, D=%d)", r, rs.D);
+
+  FwdBufs fb;
+  float *out_s, *eta_s, *ab, *dud, *du, *df_s;
+  double *Fd, *red, *sig;
+  auto carve_all = [&](Carve &cv) {
+    carve_fwd(cv, rs, r_eff, fb);
+    out_s = cv.take<float>((size_t)rs.N * C);
+    eta_s = cv.take<float>(rs.N);
+    ab = cv.take<float>((size_t)rs.N * 4);
+    dud = cv.take<float>((size_t)r_eff * rs.N);
+    du = cv.take<float>((size_t)r_eff * rs.N);
+    df_s = cv.take<float>(grad_f ? 1 : (size_t)rs.N * C);
+    Fd = cv.take<double>((size_t)r * r_eff);
+    red = cv.take<double>((size_t)nred * (nR + 1));
+    sig = cv.take<double>(2 * (size_t)nsig);
+  };
+  Carve dry{nullptr};
+  carve_all(dry);
+  if ((st = ensure_workspace(ctx, dry.off)) != NKF_OK) return st;
+  const size_t host_doubles = (size_t)r * r_eff + (size_t)nred * (nR + 1) + 2 * (size_t)nsig + (size_t)r * rs.D;
+  if ((st = ensure_pinned(ctx, 64 * 1024 + sizeof(double) * host_doubles)) != NKF_OK) return st;
+  Carve cv{ctx->ws};
+  carve_all(cv);
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the pinned buffer may feed an earlier copy
+  double *hF = reinterpret_cast<double *>(ctx->pinned);
+  double *hred = hF + (size_t)r * r_eff;
+  double *hsig = hred + (size_t)nred * (nR + 1);
+  float *hc = reinterpret_cast<float *>(hsig + 2 * (size_t)nsig);
+  memcpy(hF, Fh.data(), sizeof(double) * Fh.size());
+  int nb1 = 0, nb2 = 0;
+  {
+    StageTimer tm(ctx, NKF_STAGE_BACKWARD);
+    HIP_TRY(ctx, hipMemcpyAsync(Fd, hF, sizeof(double) * r * r_eff, hipMemcpyHostToDevice, ctx->stream));
+    if ((st = run_fwd(ctx, rs, prm, centroids, Fd, r_eff, out_s, eta_s, fb)) != NKF_OK) return st;
+    HIP_TRY(ctx, launch_bwd_ab(rs.N, C, grad_out, out_s, eta_s, fb.f0, ab, ctx->stream));
+    BwdConvProblem bp{};
+    bp.H = H;
+    bp.W = W;
+    bp.C = C;
+    bp.S = rs.S;
+    bp.r_eff = r_eff;
+    bp.f = f;
+    bp.f0 = fb.f0;
+    bp.u = fb.u;
+    bp.ab = ab;
+    bp.G = grad_out;
+    bp.eta = eta_s;
+    bp.wr = rs.taps;
+    bp.wc = rs.taps;
+    bp.mode = 1;
+    bp.plane_out = dud;
+    HIP_TRY(ctx, launch_bwd_conv(bp, ctx->stream));
+    if (want_S) {
+      // dw/dsigma_s = w1' (x) w1 + w1 (x) w1', w1'(t) = w1(t) t^2 / sigma_s^3
+      Taps dt = rs.taps;
+      const double s3 = prm->sigma_s * prm->sigma_s * prm->sigma_s;
+      for (int t = -rs.S; t <= rs.S; ++t)
+        dt.w[t + rs.S] = (float)(exp(-(double)t * t / (2.0 * prm->sigma_s * prm->sigma_s)) * t * t / s3);
+      bp.mode = 2;
+      bp.plane_out = nullptr;
+      bp.partials = sig;
+      bp.wr = dt;
+      bp.wc = rs.taps;
+      bp.nblocks_out = &nb1;
+      HIP_TRY(ctx, launch_bwd_conv(bp, ctx->stream));
+      bp.partials = sig + nsig;
+      bp.wr = rs.taps;
+      bp.wc = dt;
+      bp.nblocks_out = &nb2;
+      HIP_TRY(ctx, launch_bwd_conv(bp, ctx->stream));
+      bp.wr = bp.wc = rs.taps;
+      bp.nblocks_out = nullptr;
+      bp.partials = nullptr;
+    }
+    bp.mode = 3;
+    bp.plane_in = dud;
+    bp.plane_out = du;
+    bp.df = grad_f ? grad_f : df_s;
+    HIP_TRY(ctx, launch_bwd_conv(bp, ctx->stream));
+    HIP_TRY(ctx, launch_bwd_reduce(rs.g, centroids, r, Fd, r_eff, prm->sigma_r, du, dud, grad_p, want_R ? 1 : 0,
+                                   red, ctx->stream));
+  }
+  if (!want_R && !want_S) return NKF_OK;
+  HIP_TRY(ctx, hipMemcpyAsync(hred, red, sizeof(double) * nred * (nR + 1), hipMemcpyDeviceToHost, ctx->stream));
+  if (want_S) {
+    HIP_TRY(ctx, hipMemcpyAsync(hsig, sig, sizeof(double) * nb1, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(hsig + nsig, sig + nsig, sizeof(double) * nb2, hipMemcpyDeviceToHost, ctx->stream));
+  }
+  if (want_R)
+    HIP_TRY(ctx, hipMemcpyAsync(hc, centroids, sizeof(float) * r * rs.D, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (want_S) {
+    double s = 0.0;
+    for (int b = 0; b < nb1; ++b) s += hsig[b];
+    for (int b = 0; b < nb2; ++b) s += hsig[nsig + b];
+    *grad_sigma_s_host = s;
+  }
+  if (want_R) {
+    // sigma_r through b, and through M = A^{-1}:  dL/dM = R diag(alpha^{1/2}) Q^T,
+    // dL/dA = -M (dL/dM) M,  dA_ij/dsigma_r = A_ij D_ij / sigma_r^3
+    double sr_b = 0.0;
+    std::vector<double> R((size_t)r * r, 0.0);
+    for (int b = 0; b < nred; ++b) {
+      const double *pb = hred + (size_t)b * (nR + 1);
+      sr_b += pb[0];
+      for (int e = 0; e < nR; ++e) R[e] += pb[1 + e];
+    }
+    const double *Q = eigvecs_host, *al = eigvals_host;
+    std::vector<double> GM((size_t)r * r, 0.0), M((size_t)r * r, 0.0), T1((size_t)r * r, 0.0);
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < r; ++j) {
+        double gm = 0.0, m = 0.0;
+        for (int k = 0; k < r; ++k) {
+          gm += R[(size_t)i * r + k] * sqrt(al[k]) * Q[(size_t)j * r + k];
+          m += Q[(size_t)i * r + k] * Q[(size_t)j * r + k] / al[k];
+        }
+        GM[(size_t)i * r + j] = gm;
+        M[(size_t)i * r + j] = m;
+      }
+    for (int i = 0; i < r; ++i)  // T1 = M GM
+      for (int j = 0; j < r; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < r; ++k) s += M[(size_t)i * r + k] * GM[(size_t)k * r + j];
+        T1[(size_t)i * r + j] = s;
+      }
+    double sr_a = 0.0;
+    const double inv2 = 1.0 / (2.0 * prm->sigma_r * prm->sigma_r);
+    const double s3 = prm->sigma_r * prm->sigma_r * prm->sigma_r;
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < r; ++j) {
+        double ga = 0.0;  // (M GM M)_ij
+        for (int k = 0; k < r; ++k) ga += T1[(size_t)i * r + k] * M[(size_t)k * r + j];
+        double d2 = 0.0;
+        for (int d = 0; d < rs.D; ++d) {
+          const double t = (double)hc[i * rs.D + d] - (double)hc[j * rs.D + d];
+          d2 += t * t;
+        }
+        sr_a += -ga * exp(-d2 * inv2) * d2 / s3;
+      }
+    *grad_sigma_r_host = sr_b + sr_a;
+  }
+  return NKF_OK;
 }
 
 }  // extern "C"

@@ -1,344 +1,29 @@
-// Spatial convolutions and contraction of the fast filter (Section III,
-// Eqs. (finalnum), (finalden); Algorithm 1 accumulation loop), in embedding
-// form: with u_k the planes of the range embedding and f~ = f - f0,
-//     Z_kc = w * (u_k f~_c),   E_k = w * u_k,
-//     zeta_c(x) = sum_k u_k(x) Z_kc(x),   eta(x) = sum_k u_k(x) E_k(x),
-//     g(x) = zeta(x) / eta(x) + f0        (f(x) where eta <= 0 or not finite).
-// w(z) = w1(z1) w1(z2) on the (2S+1)^2 window intersected with the image.
-//
-// One block owns a 32-column x TH-row output tile and a set of NP planes
-// (E and/or up to NP channels).  For each k it streams the tile's input rows
-// (plus S-row halos) through LDS in chunks of RC rows:
-//   stage   u_k and u_k f~_c for RC rows x (32 + 2S) columns into LDS;
-//   row     horizontal FIR of those rows (register sliding window) into a
-//           ring of RC (1 + ceil(2S/RC)) rows in LDS;
-//   column  vertical FIR down the ring for the previous output chunk, then
-//           acc += u_k * Z in registers.
-// The r_eff (C+1) convolved planes never reach HBM.  After the k loop the
-// epilogue divides by eta and writes g.
-//
-// Precision: each FIR pass accumulates its taps in FP64 (FP64 FMA issues at
-// the FP32 rate on CDNA4 without packed math) and stores its result as FP32,
-// so each convolved value carries one rounding instead of 2S+1.
+// Forward convolutions + contraction + normalisation (Section III,
+// Eqs. (finalnum), (finalden); Algorithm 1 accumulation loop).  The kernel
+// body is in conv_core.h; this file instantiates it for every window radius
+// and picks the plane grouping from the channel count.
 #include <hip/hip_runtime.h>
-#include <math.h>
 
-#include "device_common.h"
+#include "conv_core.h"
 
 namespace nkf {
 
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kTW = 32;
-constexpr int kTWP = kTW + 4;  // ring row stride (floats): rows shift by 4 banks
-
-struct ConvArgs {
-  int H, W, C, r_eff;
-  int nch;          // output chunks (of RC rows) per tile
-  int tiles_x, tiles_y, nblocks;
-  int ch_per_block; // channel planes per block
-  const float *f;
-  const float *f0;
-  const float *u;
-  float *out;
-  float *eta_out;   // nullable
-  float *eta_buf;   // eta written (HAS_E, NP == 1) or read (!HAS_E)
-  double w[2 * kMaxRadius + 1];  // FP32 taps widened to FP64
-};
-
-template <int S, int NP, bool HAS_E, int RC>
-struct Cfg {
-  static constexpr int T = 2 * S + 1;
-  // staging row stride: a multiple of 4 floats (16-byte rows) that is 4 mod 8,
-  // so the b128 reads of neighbouring rows land in disjoint LDS banks
-  static constexpr int SW0 = ((kTW + 2 * S + 3) / 4) * 4;
-  static constexpr int SW = (SW0 % 8 == 0) ? SW0 + 4 : SW0;
-  static constexpr int RUN = RC * NP * kTW / kBlock;          // outputs per thread per pass
-  static constexpr int SEGS = kTW / RUN;                      // row-pass segments per row
-  static constexpr int SUBS = kBlock / (kTW * NP);            // column-pass row groups
-  static constexpr int LAG = (2 * S + RC - 1) / RC;           // input chunks ahead of output
-  static constexpr int RING = RC * (1 + LAG);
-  static constexpr int RINGX = RING + 2 * S;                  // ring rows + mirrored head
-  static constexpr int NCH_MAX = 64 / RUN;                    // accumulator budget: 64 floats
-  static constexpr int NCHAN = NP - (HAS_E ? 1 : 0);          // channel planes
-  static constexpr int NPU = NP + (HAS_E ? 0 : 1);            // staged planes (+u when no E)
-  static constexpr int UPL = HAS_E ? 0 : NP;                  // index of the raw-u staged plane
-  static constexpr int WIN = ((RUN + 2 * S + 3) / 4) * 4;
-  static constexpr int STG = NPU * RC * SW;                   // staging floats
-  static constexpr int RINGF = NP * RINGX * kTWP;             // convolved-row ring floats
-  static constexpr int URINGF = RINGX * kTWP;                 // raw-u ring floats
-  static constexpr int ETAB = NCH_MAX * RC * kTW;             // epilogue eta tile
-  static constexpr int SMEM = (STG + RINGF + URINGF) > ETAB ? (STG + RINGF + URINGF) : ETAB;
-  static_assert(RUN * SEGS == kTW, "row pass split");
-  static_assert(SUBS * RUN == RC, "column pass split");
-  static_assert(RC * NP * SEGS == kBlock, "row pass threads");
-};
-
-// Hides a value from the optimiser so that address arithmetic and loads that
-// depend on it are redone each k instead of being hoisted out of the k loop
-// (hoisting them keeps hundreds of registers live).
-template <class V>
-__device__ __forceinline__ V opaque(V v) {
-  asm volatile("" : "+v"(v));
-  return v;
-}
-
-// sum_t w[t] x[t] for a symmetric window (w[t] == w[2S - t]): the mirrored
-// pair x[t] + x[2S - t] of two FP32 values is exact in FP64, so folding halves
-// the taps held in scalar registers without changing the VALU operation count.
-template <int S>
-__device__ __forceinline__ double fir_sym(const double *w, const double *x) {
-  double s = w[S] * x[S];
-#pragma unroll
-  for (int t = 0; t < S; ++t) s = fma(w[t], x[t] + x[2 * S - t], s);
-  return s;
-}
-
-template <int S, int NP, bool HAS_E, int RC>
-__global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
-  using K = Cfg<S, NP, HAS_E, RC>;
-  constexpr int T = K::T, SW = K::SW, RUN = K::RUN, SEGS = K::SEGS, LAG = K::LAG, RING = K::RING;
-  constexpr int RINGX = K::RINGX, NCH_MAX = K::NCH_MAX, NCHAN = K::NCHAN, UPL = K::UPL;
-  __shared__ __attribute__((aligned(16))) float smem[K::SMEM];
-  float *stg = smem;                        // [NPU][RC][SW]
-  float *ring = smem + K::STG;              // [NP][RINGX][kTWP]
-  float *uring = ring + K::RINGF;           // [RINGX][kTWP]
-
-  const int tid = threadIdx.x;
-  const int L = xcd_swizzle(blockIdx.x, a.nblocks);
-  const int per_chunk = a.tiles_x * a.tiles_y;
-  const int cchunk = L / per_chunk;
-  const int rem = L - cchunk * per_chunk;
-  const int ty = rem / a.tiles_x, tx = rem - ty * a.tiles_x;
-  const int TH = a.nch * RC;
-  const int tx0 = tx * kTW;
-  const int c0 = cchunk * a.ch_per_block;
-  const int H = a.H, W = a.W, C = a.C;
-  const int64_t N = (int64_t)H * W;
-
-  // row-pass role (segment fastest, then row: a quarter-wave covers all banks)
-  const int r_sg = tid % SEGS;
-  const int r_rr = (tid / SEGS) % RC;
-  const int r_p = tid / (SEGS * RC);
-  // column-pass role
-  const int c_x = tid % kTW;
-  const int c_p = (tid / kTW) % NP;
-  const int c_sub = tid / (kTW * NP);
-
-  float f0c[NCHAN > 0 ? NCHAN : 1];
-#pragma unroll
-  for (int ch = 0; ch < NCHAN; ++ch) f0c[ch] = c0 + ch < C ? a.f0[c0 + ch] : 0.0f;
-
-  float acc[NCH_MAX][RUN];
-#pragma unroll
-  for (int j = 0; j < NCH_MAX; ++j)
-#pragma unroll
-    for (int i = 0; i < RUN; ++i) acc[j][i] = 0.0f;
-
-  const int nin = a.nch + LAG;
-  // Staging data of one input chunk lives in registers between its global
-  // loads and its LDS store: the loads of chunk i+1 are issued right after
-  // chunk i is stored, so their latency hides behind chunk i's FIR passes.
-  constexpr int NPOS = (RC * SW + kBlock - 1) / kBlock;
-  constexpr int NCH1 = NCHAN > 0 ? NCHAN : 1;
-  float pu[NPOS], pf[NPOS][NCH1];
-  auto fetch = [&](int kk, int icc) {
-    const int ty0k = opaque(ty * TH);
-    const float *uk = a.u + (int64_t)kk * N;
-    const float *fk = opaque(a.f);
-    const int gy0 = ty0k - S + icc * RC;
-#pragma unroll
-    for (int q = 0; q < NPOS; ++q) {
-      const int e = tid + q * kBlock;
-      const int rr = e / SW, j = e - rr * SW;
-      const int gy = gy0 + rr, gx = tx0 - S + j;
-      const bool in = e < RC * SW && j < kTW + 2 * S && gy >= 0 && gy < H && gx >= 0 && gx < W;
-      pu[q] = in ? uk[gy * W + gx] : 0.0f;
-      const float *fp = fk + (int64_t)(in ? gy * W + gx : 0) * C + c0;
-#pragma unroll
-      for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = (in && c0 + ch < C) ? fp[ch] - f0c[ch] : 0.0f;
-    }
-  };
-  fetch(0, 0);
-  for (int k = 0; k < a.r_eff; ++k) {
-#pragma unroll
-    for (int ic = 0; ic < NCH_MAX + LAG; ++ic) {
-      if (ic < nin) {
-        // ---- stage u_k and u_k f~ for R rows [ic*RC, ic*RC + RC) --------------
-        // (the previous row pass finished reading the staging buffer before the
-        // barrier that preceded the previous column pass)
-#pragma unroll
-        for (int q = 0; q < NPOS; ++q) {
-          const int e = tid + q * kBlock;
-          if (e < RC * SW) {
-            const int rr = e / SW, j = e - rr * SW;
-            stg[(UPL * RC + rr) * SW + j] = pu[q];
-#pragma unroll
-            for (int ch = 0; ch < NCHAN; ++ch)
-              stg[(((HAS_E ? 1 : 0) + ch) * RC + rr) * SW + j] = pf[q][ch] * pu[q];
-          }
-        }
-        if (ic + 1 < nin)
-          fetch(k, ic + 1);
-        else if (k + 1 < a.r_eff)
-          fetch(k + 1, 0);
-        __syncthreads();
-        // ---- row pass: horizontal FIR into the ring ---------------------------
-        {
-          // ring slot of R row q = ic*RC + rr; rows with slot < 2S are mirrored
-          // at slot + RING so that column windows never wrap
-          const int slot = (ic % (1 + LAG)) * RC + r_rr;
-          const bool mirror = slot < 2 * S;
-          double win[K::WIN];
-          const float4 *src = reinterpret_cast<const float4 *>(&stg[(r_p * RC + r_rr) * SW + r_sg * RUN]);
-#pragma unroll
-          for (int v4 = 0; v4 < K::WIN / 4; ++v4) {
-            const float4 q = src[v4];
-            win[4 * v4 + 0] = (double)q.x;
-            win[4 * v4 + 1] = (double)q.y;
-            win[4 * v4 + 2] = (double)q.z;
-            win[4 * v4 + 3] = (double)q.w;
-          }
-          float *dst = &ring[(r_p * RINGX + slot) * kTWP + r_sg * RUN];
-#pragma unroll
-          for (int i = 0; i < RUN; ++i) {
-            const double s = fir_sym<S>(a.w, &win[i]);
-            const float sf = (float)s;
-            dst[i] = sf;
-            if (mirror) dst[RING * kTWP + i] = sf;
-          }
-          if (r_p == 0) {
-            // raw u_k at the tile's own columns, for the contraction
-            const float *us = &stg[(UPL * RC + r_rr) * SW + S + r_sg * RUN];
-            float *ud = &uring[slot * kTWP + r_sg * RUN];
-#pragma unroll
-            for (int i = 0; i < RUN; ++i) {
-              const float uv = us[i];
-              ud[i] = uv;
-              if (mirror) ud[RING * kTWP + i] = uv;
-            }
-          }
-        }
-        __syncthreads();
-        // ---- column pass for output chunk oc = ic - LAG -----------------------
-        if (ic >= LAG) {
-          const int oc = ic - LAG;
-          // local output rows o0 .. o0+RUN-1 need R rows o0 .. o0+RUN+2S-1
-          const int o0 = oc * RC + c_sub * RUN;
-          const int b0 = (oc * RC) % RING + c_sub * RUN;   // < RING, window ends < RINGX
-          const float *col = &ring[(c_p * RINGX + b0) * kTWP + c_x];
-          const float *ucol = &uring[(b0 + S) * kTWP + c_x];
-          double win[RUN + 2 * S];
-#pragma unroll
-          for (int j = 0; j < RUN + 2 * S; ++j) win[j] = col[j * kTWP];
-#pragma unroll
-          for (int i = 0; i < RUN; ++i) {
-            const double z = fir_sym<S>(a.w, &win[i]);
-            acc[oc][i] = fmaf(ucol[i * kTWP], (float)z, acc[oc][i]);
-          }
-          (void)o0;
-        }
-      }
-    }
-  }
-
-  // ---- epilogue: g = zeta / eta + f0 --------------------------------------
-  const int ty0 = ty * TH;
-  const int gx = tx0 + c_x;
-  if constexpr (HAS_E && NP == 1) {
-#pragma unroll
-    for (int oc = 0; oc < NCH_MAX; ++oc)
-#pragma unroll
-      for (int i = 0; i < RUN; ++i) {
-        const int gy = ty0 + oc * RC + c_sub * RUN + i;
-        if (oc < a.nch && gy < H && gx < W) {
-          const int64_t pix = (int64_t)gy * W + gx;
-          if (a.eta_buf) a.eta_buf[pix] = acc[oc][i];
-          if (a.eta_out) a.eta_out[pix] = acc[oc][i];
-        }
-      }
-    return;
-  } else {
-    float *etab = smem;  // [TH][32], reuses the staging and ring buffers
-    if constexpr (HAS_E) {
-      __syncthreads();
-      if (c_p == 0) {
-#pragma unroll
-        for (int oc = 0; oc < NCH_MAX; ++oc)
-#pragma unroll
-          for (int i = 0; i < RUN; ++i) {
-            const int o = oc * RC + c_sub * RUN + i;
-            if (oc < a.nch) {
-              etab[o * kTW + c_x] = acc[oc][i];
-              const int gy = ty0 + o;
-              if (a.eta_out && gy < H && gx < W) a.eta_out[(int64_t)gy * W + gx] = acc[oc][i];
-            }
-          }
-      }
-      __syncthreads();
-    }
-    const int ch = c_p - (HAS_E ? 1 : 0);
-    const int gc = c0 + ch;
-    if (ch >= 0 && gc < C && gx < W) {
-      const float f0 = a.f0[gc];
-#pragma unroll
-      for (int oc = 0; oc < NCH_MAX; ++oc)
-#pragma unroll
-        for (int i = 0; i < RUN; ++i) {
-          const int o = oc * RC + c_sub * RUN + i;
-          const int gy = ty0 + o;
-          if (oc < a.nch && gy < H) {
-            const int64_t pix = (int64_t)gy * W + gx;
-            const float eta = HAS_E ? etab[o * kTW + c_x] : a.eta_buf[pix];
-            float g;
-            if (eta > 0.0f && isfinite(eta))
-              g = acc[oc][i] / eta + f0;
-            else
-              g = a.f[pix * C + gc];
-            a.out[pix * C + gc] = g;
-          }
-        }
-    }
-  }
-}
-
-template <int S, int NP, bool HAS_E, int RC>
-hipError_t launch_one(ConvArgs a, hipStream_t s, int ch_per_block, int nchunks_c) {
-  using K = Cfg<S, NP, HAS_E, RC>;
-  a.ch_per_block = ch_per_block;
-  a.tiles_x = (a.W + kTW - 1) / kTW;
-  // largest chunk count (<= NCH_MAX) that still gives >= 512 blocks
-  int nch = K::NCH_MAX;
-  auto blocks = [&](int n) {
-    const int th = n * RC;
-    return (int64_t)a.tiles_x * ((a.H + th - 1) / th) * nchunks_c;
-  };
-  while (nch > 1 && blocks(nch) < 512) --nch;
-  // do not use more chunks than the image needs
-  const int need = (a.H + RC - 1) / RC;
-  if (nch > need) nch = need;
-  a.nch = nch;
-  a.tiles_y = (a.H + nch * RC - 1) / (nch * RC);
-  const int64_t nb = (int64_t)a.tiles_x * a.tiles_y * nchunks_c;
-  if (nb > 0x7fffffff) return hipErrorInvalidValue;
-  a.nblocks = (int)nb;
-  hipLaunchKernelGGL((conv_kernel<S, NP, HAS_E, RC>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
+using namespace conv;
 
 template <int S>
 hipError_t launch_S(ConvArgs a, hipStream_t s) {
   const int C = a.C;
-  if (C == 1) return launch_one<S, 2, true, 32>(a, s, 1, 1);
-  if (C <= 3) return launch_one<S, 4, true, 16>(a, s, 3, 1);
+  if (C == 1) return launch_one<S, 2, true, 32, MODE_FWD>(a, s, 1, 1);
+  if (C <= 3) return launch_one<S, 4, true, 16, MODE_FWD>(a, s, 3, 1);
   // eta pass, then channel chunks that read eta
-  hipError_t e = launch_one<S, 1, true, 32>(a, s, 0, 1);
+  hipError_t e = launch_one<S, 1, true, 32, MODE_FWD>(a, s, 0, 1);
   if (e != hipSuccess) return e;
   ConvArgs b = a;
   b.eta_out = nullptr;
-  if (C < 8) return launch_one<S, 4, false, 16>(b, s, 4, (C + 3) / 4);
-  return launch_one<S, 8, false, 16>(b, s, 8, (C + 7) / 8);
+  if (C < 8) return launch_one<S, 4, false, 16, MODE_FWD>(b, s, 4, (C + 3) / 4);
+  return launch_one<S, 8, false, 16, MODE_FWD>(b, s, 8, (C + 7) / 8);
 }
 
 }  // namespace
@@ -355,7 +40,7 @@ hipError_t launch_conv_contract(const ConvProblem &pb, hipStream_t s) {
   a.out = pb.out;
   a.eta_out = pb.eta_out;
   a.eta_buf = pb.eta_buf;
-  for (int t = 0; t < 2 * kMaxRadius + 1; ++t) a.w[t] = (double)pb.taps.w[t];
+  for (int t = 0; t < 2 * kMaxRadius + 1; ++t) a.wr[t] = a.wc[t] = (double)pb.taps.w[t];
   switch (pb.S) {
 #define NKF_CASE(SV) \
   case SV:           \

@@ -59,4 +59,28 @@ struct ConvProblem {
 };
 hipError_t launch_conv_contract(const ConvProblem &pb, hipStream_t s);
 
+// ---- kernels_bwd.hip --------------------------------------------------------
+// Backward passes (C <= 3).  mode 1: du_dir planes; 2: sigma_s partial sums
+// (one double per block, with row taps wr and column taps wc); 3: adjoint
+// convolutions -> du planes and df.
+struct BwdConvProblem {
+  int mode, H, W, C, S, r_eff;
+  const float *f, *f0, *u, *ab, *plane_in, *G, *eta;
+  float *plane_out, *df;
+  double *partials;
+  Taps wr, wc;
+  int *nblocks_out;
+};
+int bwd_conv_max_blocks(int H, int W);
+hipError_t launch_bwd_ab(int64_t N, int C, const float *G, const float *out, const float *eta,
+                         const float *f0, float *ab, hipStream_t s);
+hipError_t launch_bwd_conv(const BwdConvProblem &pb, hipStream_t s);
+int bwd_reduce_blocks(int64_t N);
+size_t bwd_reduce_lds(int r, int r_eff, int D, int want_R);
+// db = F du, dp (nullable), and per-block partials [blocks][1 + r*r_eff]:
+// the sigma_r-through-b sum, then R = sum_x b du_dir^T (when want_R).
+hipError_t launch_bwd_reduce(const Guide &g, const float *c, int r, const double *F, int r_eff,
+                             double sigma_r, const float *du, const float *dud, float *dp, int want_R,
+                             double *partials, hipStream_t s);
+
 }  // namespace nkf

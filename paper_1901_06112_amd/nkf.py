@@ -315,3 +315,81 @@ def stage_times(t, reset=True):
     _check(load_library().nkf_stage_times(ctx, ms.ctypes.data_as(ct.c_void_p), cnt.ctypes.data_as(ct.c_void_p),
                                           1 if reset else 0), ctx)
     return {s: (float(m), int(c)) for s, m, c in zip(STAGES, ms, cnt)}
+
+
+def filter_backward(f, centroids, Q, alpha, r_eff, grad_out, p=None, *, sigma_s=3.0, sigma_r=30.0,
+                    radius=-1, spatial="gaussian", guide=None, patch_radius=3, center=None,
+                    need_f=True, need_p=True, need_sigma_r=True, need_sigma_s=True):
+    """Gradients of L with dL/dg = grad_out through the filter with given
+    landmarks (held fixed).  Q [r, r] / alpha [r] are the eigenpairs returned
+    by landmark_factor for the same landmarks and sigma_r.  Returns
+    (df, dp, dsigma_r, dsigma_s); entries not requested are None.  dp is the
+    gradient w.r.t. the guide (for guide='self' add it to df)."""
+    if guide is None:
+        guide = "explicit" if p is not None else "self"
+    H, W, C = f.shape
+    D = _guide_dim(f, p, guide, patch_radius)
+    r = centroids.shape[0]
+    prm = make_params(sigma_s=sigma_s, sigma_r=sigma_r, r=r, radius=radius, spatial=spatial, guide=guide,
+                      patch_radius=patch_radius, center=center)
+    Qh = np.ascontiguousarray(np.asarray(Q, np.float64))
+    ah = np.ascontiguousarray(np.asarray(alpha, np.float64))
+    go = grad_out.contiguous()
+    df = torch.empty_like(f) if need_f else None
+    dp = torch.empty((H, W, D), dtype=torch.float32, device=f.device) if need_p else None
+    dsr = ct.c_double(0.0)
+    dss = ct.c_double(0.0)
+    ctx = _cur_ctx(f)
+    _check(load_library().nkf_filter_backward(
+        ctx, H, W, C, _dev_f32(f, "f"), D, _dev_f32(p, "p") if guide == "explicit" else ct.c_void_p(0),
+        ct.byref(prm), _dev_f32(centroids, "centroids"), Qh.ctypes.data_as(ct.c_void_p),
+        ah.ctypes.data_as(ct.c_void_p), int(r_eff), _dev_f32(go, "grad_out"), _ptr(df), _ptr(dp),
+        ct.byref(dsr) if need_sigma_r else None, ct.byref(dss) if need_sigma_s else None), ctx)
+    return (df, dp, dsr.value if need_sigma_r else None, dss.value if need_sigma_s else None)
+
+
+class NystromFilter(torch.autograd.Function):
+    """Differentiable Nystrom filter with fixed landmarks.
+
+    apply(f, p, sigma_r, sigma_s, landmarks, radius, spatial, center, tau):
+    f [H, W, C] float32 CUDA; p [H, W, D] or None (the image guides itself);
+    sigma_r, sigma_s 0-d float64 tensors (or floats); landmarks [r, D] float32
+    CUDA.  Gradients flow to f, p, sigma_r and sigma_s; the landmarks and the
+    window radius are held fixed.  The backward recomputes the embedding and
+    the convolutions instead of storing them."""
+
+    @staticmethod
+    def forward(ctx, f, p, sigma_r, sigma_s, landmarks, radius=-1, spatial="gaussian", center=None, tau=1e-10):
+        sr = float(sigma_r)
+        ss = float(sigma_s)
+        Q, al, F, reff = landmark_factor(landmarks, sr, tau)
+        out = filter_landmarks(f, landmarks, F, p, sigma_s=ss, sigma_r=sr, radius=radius, spatial=spatial,
+                               center=center)
+        ctx.save_for_backward(f, p if p is not None else f, landmarks)
+        ctx.self_guided = p is None
+        ctx.factor = (Q, al, reff)
+        ctx.cfg = dict(sigma_s=ss, sigma_r=sr, radius=radius, spatial=spatial, center=center)
+        ctx.sigma_types = (sigma_r, sigma_s)
+        return out
+
+    @staticmethod
+    def backward(ctx, G):
+        f, p, landmarks = ctx.saved_tensors
+        Q, al, reff = ctx.factor
+        need_p = ctx.self_guided or ctx.needs_input_grad[1]
+        sr_t, ss_t = ctx.sigma_types
+        need_sr = ctx.needs_input_grad[2]
+        need_ss = ctx.needs_input_grad[3] and ctx.cfg["spatial"] == "gaussian"
+        df, dp, dsr, dss = filter_backward(
+            f, landmarks, Q, al, reff, G, None if ctx.self_guided else p, need_f=True, need_p=need_p,
+            need_sigma_r=need_sr, need_sigma_s=need_ss, **ctx.cfg)
+        if ctx.self_guided:
+            df = df + dp
+            dp = None
+
+        def as_grad(v, like):
+            if v is None or not isinstance(like, torch.Tensor):
+                return None
+            return torch.tensor(v, dtype=like.dtype, device=like.device)
+
+        return (df, dp, as_grad(dsr, sr_t), as_grad(dss, ss_t), None, None, None, None, None)
