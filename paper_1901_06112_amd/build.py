@@ -29,6 +29,7 @@ SOURCES = [
     "kernels_embed.hip",
     "kernels_conv.hip",
     "kernels_bwd.hip",
+    "kernels_mfma.hip",
 ]
 
 COMMON = [

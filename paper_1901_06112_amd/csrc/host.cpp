@@ -325,13 +325,17 @@ struct FwdBufs {
   unsigned *mm;
   float *u;
   float *eta_buf;
+  float *mu;   // [D] centring of the 16-bit distance path
+  float *F32;  // [r][r_eff] FP32 factor for the MFMA mix
 };
 
-void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b) {
+void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r = kMaxLandmarks) {
   b.f0 = cv.take<float>(rs.C);
   b.mm = cv.take<unsigned>(2 * (size_t)rs.C);
   b.u = cv.take<float>((size_t)r_eff * rs.N);
   b.eta_buf = cv.take<float>(rs.C > 3 ? rs.N : 1);
+  b.mu = cv.take<float>(rs.D);
+  b.F32 = cv.take<float>((size_t)r * r_eff);
 }
 
 nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, const float *c, const double *F,
@@ -339,7 +343,13 @@ nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, cons
   {
     StageTimer tm(ctx, NKF_STAGE_EMBED);
     HIP_TRY(ctx, launch_center(rs.g.f, rs.N, rs.C, prm->center, b.f0, b.mm, ctx->stream));
-    HIP_TRY(ctx, launch_embed(rs.g, c, prm->r, F, r_eff, prm->sigma_r, b.u, ctx->stream));
+    if (use_mfma_distance(rs.g, prm->prec)) {
+      HIP_TRY(ctx, launch_guide_mean(rs.g, b.mu, ctx->stream));
+      HIP_TRY(ctx, launch_embed_mfma(rs.g, c, prm->r, b.mu, F, b.F32, r_eff, prm->sigma_r, prm->prec, b.u,
+                                     ctx->stream));
+    } else {
+      HIP_TRY(ctx, launch_embed(rs.g, c, prm->r, F, r_eff, prm->sigma_r, b.u, ctx->stream));
+    }
   }
   ConvProblem pb{};
   pb.H = rs.H;
@@ -362,16 +372,25 @@ nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, cons
 struct KmBufs {
   double *sums;
   int *lab_scratch;
+  float *mu;
 };
 
 void carve_km(Carve &cv, const Resolved &rs, int r, KmBufs &b) {
   b.sums = cv.take<double>(kmeans_partials_doubles(r, rs.D));
   b.lab_scratch = cv.take<int>(rs.N);
+  b.mu = cv.take<float>(rs.D);
 }
 
 nkf_status run_lloyd(nkf_ctx *ctx, const Resolved &rs, int r, float *c, int iters, int *labels,
-                     const KmBufs &b) {
+                     const KmBufs &b, int prec) {
   StageTimer tm(ctx, NKF_STAGE_KMEANS);
+  if (use_mfma_distance(rs.g, prec)) {
+    if (iters > 0) HIP_TRY(ctx, launch_guide_mean(rs.g, b.mu, ctx->stream));
+    for (int it = 0; it < iters; ++it)
+      HIP_TRY(ctx, launch_kmeans_step_mfma(rs.g, c, r, b.mu, prec, b.sums,
+                                           it + 1 == iters && labels ? labels : b.lab_scratch, ctx->stream));
+    return NKF_OK;
+  }
   for (int it = 0; it < iters; ++it)
     HIP_TRY(ctx, launch_kmeans_step(rs.g, c, r, b.sums, it + 1 == iters ? labels : nullptr, b.lab_scratch,
                                     ctx->stream));
@@ -545,7 +564,7 @@ nkf_status nkf_kmeans_iterate(nkf_ctx *ctx, int H, int W, int C, const float *f,
   if ((st = ensure_workspace(ctx, dry.off)) != NKF_OK) return st;
   Carve cv{ctx->ws};
   carve_km(cv, rs, prm->r, kb);
-  return run_lloyd(ctx, rs, prm->r, centroids, iters, labels, kb);
+  return run_lloyd(ctx, rs, prm->r, centroids, iters, labels, kb, prm->prec);
 }
 
 nkf_status nkf_kmeans(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, const float *p,
@@ -563,7 +582,7 @@ nkf_status nkf_kmeans(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
   carve_km(cv, rs, prm->r, kb);
   idx = cv.take<int64_t>(prm->r);
   if ((st = run_seed(ctx, rs, prm, centroids, idx)) != NKF_OK) return st;
-  return run_lloyd(ctx, rs, prm->r, centroids, prm->kmeans_iters, labels, kb);
+  return run_lloyd(ctx, rs, prm->r, centroids, prm->kmeans_iters, labels, kb, prm->prec);
 }
 
 nkf_status nkf_filter_landmarks(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, const float *p,
@@ -612,7 +631,7 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
   carve_all(cv, kb, c, idx, Fd, fb);
 
   if ((st = run_seed(ctx, rs, prm, c, idx)) != NKF_OK) return st;
-  if ((st = run_lloyd(ctx, rs, r, c, prm->kmeans_iters, nullptr, kb)) != NKF_OK) return st;
+  if ((st = run_lloyd(ctx, rs, r, c, prm->kmeans_iters, nullptr, kb, prm->prec)) != NKF_OK) return st;
   // the one host round trip: landmarks to the host for the FP64 factor
   int r_eff = 0;
   if (ctx->timing) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // keep k-means time out of the factor stage

@@ -305,8 +305,28 @@ static hipError_t assign_accumulate(const Guide &g, const float *c, int r, doubl
 }
 
 size_t kmeans_partials_doubles(int r, int D) {
-  const int parts = D <= 4 ? kMaxPartials : kMaxPartialsGeneric;
+  const int parts = D <= 4 ? kMaxPartials : kMaxPartialsGeneric;  // (the MFMA path uses the generic count)
   return (size_t)parts * r * (D + 1);
+}
+
+hipError_t launch_kmeans_step_mfma(const Guide &g, float *c, int r, const float *mu, int prec, double *partials,
+                                   int *lab, hipStream_t s) {
+  hipError_t e = launch_assign_mfma(g, c, r, mu, prec, lab, s);
+  if (e != hipSuccess) return e;
+  const int64_t N = (int64_t)g.H * g.W;
+  const size_t acc_bytes = sizeof(float) * (size_t)r * (g.D + 1);
+  const int use_lds = acc_bytes <= 96 * 1024;
+  if (use_lds) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(accumulate_generic_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)acc_bytes);
+    if (e != hipSuccess) return e;
+  }
+  const int nparts = grid_for(N, kBlock * 16, kMaxPartialsGeneric);
+  hipLaunchKernelGGL(accumulate_generic_kernel, dim3(nparts), dim3(kBlock), use_lds ? acc_bytes : 0, s, g, N, lab,
+                     r, partials, use_lds);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(update_kernel, dim3(r), dim3(kBlock), 0, s, partials, nparts, r, g.D, c);
+  return hipGetLastError();
 }
 
 hipError_t launch_kmeans_step(const Guide &g, float *c, int r, double *partials, int *labels, int *label_scratch,

@@ -38,6 +38,19 @@ size_t kmeans_partials_doubles(int r, int D);
 hipError_t launch_kmeans_step(const Guide &g, float *c, int r, double *partials, int *labels,
                               int *label_scratch, hipStream_t s);
 
+// ---- kernels_mfma.hip -------------------------------------------------------
+// Distance step on MFMA with 16-bit centred operands (prec 1 = BF16, 2 = FP16).
+hipError_t launch_guide_mean(const Guide &g, float *mu, hipStream_t s);
+hipError_t launch_assign_mfma(const Guide &g, const float *c, int r, const float *mu, int prec, int *labels,
+                              hipStream_t s);
+hipError_t launch_embed_mfma(const Guide &g, const float *c, int r, const float *mu, const double *F,
+                             float *F32, int r_eff, double sigma_r, int prec, float *u, hipStream_t s);
+// Lloyd step whose assignment runs on MFMA (labels into `lab`, required).
+hipError_t launch_kmeans_step_mfma(const Guide &g, float *c, int r, const float *mu, int prec, double *partials,
+                                   int *lab, hipStream_t s);
+// Whether the 16-bit MFMA distance path serves this guide / precision.
+inline bool use_mfma_distance(const Guide &g, int prec) { return prec != 0 && g.D > 8; }
+
 // ---- kernels_embed.hip ------------------------------------------------------
 // f0[c] = center (finite) or (min_c + max_c) / 2 over f.
 hipError_t launch_center(const float *f, int64_t N, int C, double center, float *f0,
