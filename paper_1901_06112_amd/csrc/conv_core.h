@@ -73,19 +73,25 @@ struct ConvArgs {
   double wc[2 * kMaxRadius + 1];  // column-pass taps
 };
 
-template <int S, int NP, bool HAS_E, int RC, int MODE>
+template <int S, int NP, bool HAS_E, int RC, int MODE, int BT = kBlock>
 struct Cfg {
   static constexpr int T = 2 * S + 1;
-  // staging row stride: a multiple of 4 floats (16-byte rows) that is 4 mod 8,
-  // so the b128 reads of neighbouring rows land in disjoint LDS banks
+  // LDS has 64 banks of 4 bytes; a b128 access is served 16 lanes at a time.
+  // The row-pass lanes of one such group are 4 segments (8 floats apart) x 2
+  // rows x 2 planes, so rows are offset by 4 mod 32 floats and planes by
+  // 32 mod 64 floats: the 16 lanes then cover all 64 banks.
   static constexpr int SW0 = ((kTW + 2 * S + 3) / 4) * 4;
-  static constexpr int SW = (SW0 % 8 == 0) ? SW0 + 4 : SW0;
-  static constexpr int RUN = RC * NP * kTW / kBlock;          // outputs per thread per pass
+  static constexpr int SW = SW0 + ((4 - SW0 % 32) + 32) % 32;   // >= 32 + 2S, == 4 mod 32
+  static constexpr int PSTG0 = RC * SW;
+  static constexpr int PSTG = PSTG0 + ((32 - PSTG0 % 64) + 64) % 64;  // plane stride, == 32 mod 64
+  static constexpr int RUN = RC * NP * kTW / BT;              // outputs per thread per pass
   static constexpr int SEGS = kTW / RUN;                      // row-pass segments per row
-  static constexpr int SUBS = kBlock / (kTW * NP);            // column-pass row groups
+  static constexpr int SUBS = BT / (kTW * NP);                // column-pass row groups
   static constexpr int LAG = (2 * S + RC - 1) / RC;           // input chunks ahead of output
   static constexpr int RING = RC * (1 + LAG);
   static constexpr int RINGX = RING + 2 * S;                  // ring rows + mirrored head
+  static constexpr int PR0 = RINGX * kTWP;
+  static constexpr int PR = PR0 + ((32 - PR0 % 64) + 64) % 64;     // ring plane stride, == 32 mod 64
   static constexpr int NCH_MAX = 64 / RUN;                    // accumulator budget: 64 floats
   static constexpr int NCHAN = NP - (HAS_E ? 1 : 0);          // channel planes
   static constexpr bool FWD = MODE == MODE_FWD;
@@ -93,8 +99,8 @@ struct Cfg {
   static constexpr int NPU = NP + (RAWU_SEP ? 1 : 0);         // staged planes
   static constexpr int UPL = RAWU_SEP ? NP : 0;               // index of the raw-u staged plane
   static constexpr int WIN = ((RUN + 2 * S + 3) / 4) * 4;
-  static constexpr int STG = NPU * RC * SW;                   // staging floats
-  static constexpr int RINGF = NP * RINGX * kTWP;             // convolved-row ring floats
+  static constexpr int STG = NPU * PSTG;                      // staging floats
+  static constexpr int RINGF = NP * PR;                       // convolved-row ring floats
   static constexpr int URINGF = FWD ? RINGX * kTWP : 0;       // raw-u ring floats (forward)
   static constexpr int EXF = (MODE == MODE_DUDIR || MODE == MODE_ADJ) ? NP * RC * kTW : 0;
   static constexpr int ETAB = FWD ? NCH_MAX * RC * kTW : 0;   // epilogue eta tile
@@ -102,7 +108,7 @@ struct Cfg {
   static constexpr int SMEM = MAIN > ETAB ? MAIN : ETAB;
   static_assert(RUN * SEGS == kTW, "row pass split");
   static_assert(SUBS * RUN == RC, "column pass split");
-  static_assert(RC * NP * SEGS == kBlock, "row pass threads");
+  static_assert(RC * NP * SEGS == BT, "row pass threads");
   static_assert(FWD || (NP == 4 && HAS_E), "backward modes use the E plane + 3 channel planes");
 };
 
@@ -126,16 +132,16 @@ __device__ __forceinline__ double fir_sym(const double *w, const double *x) {
   return s;
 }
 
-template <int S, int NP, bool HAS_E, int RC, int MODE>
-__global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
-  using K = Cfg<S, NP, HAS_E, RC, MODE>;
+template <int S, int NP, bool HAS_E, int RC, int MODE, int BT = kBlock>
+__global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
+  using K = Cfg<S, NP, HAS_E, RC, MODE, BT>;
   constexpr int SW = K::SW, RUN = K::RUN, SEGS = K::SEGS, LAG = K::LAG, RING = K::RING;
   constexpr int RINGX = K::RINGX, NCH_MAX = K::NCH_MAX, NCHAN = K::NCHAN, UPL = K::UPL;
   constexpr bool FWD = K::FWD;
   constexpr bool BWD_AB = MODE == MODE_DUDIR || MODE == MODE_SIGS;  // contraction weights a, beta
   __shared__ __attribute__((aligned(16))) float smem[K::SMEM];
-  float *stg = smem;                        // [NPU][RC][SW]
-  float *ring = smem + K::STG;              // [NP][RINGX][kTWP]
+  float *stg = smem;                        // [NPU][RC][SW], plane stride PSTG
+  float *ring = smem + K::STG;              // [NP][RINGX][kTWP], plane stride PR
   float *uring = ring + K::RINGF;           // [RINGX][kTWP] (forward)
   float *ex = uring + K::URINGF;            // [NP][RC][32] (DUDIR, ADJ)
 
@@ -151,10 +157,23 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
   const int H = a.H, W = a.W, C = a.C;
   const int64_t N = (int64_t)H * W;
 
-  // row-pass role (segment fastest, then row: a quarter-wave covers all banks)
-  const int r_sg = tid % SEGS;
-  const int r_rr = (tid / SEGS) % RC;
-  const int r_p = tid / (SEGS * RC);
+  // row-pass role: tid bits = [segment][row bit 0][plane bit 0][row bits 1..][plane bits 1..]
+  int r_sg, r_rr, r_p;
+  {
+    int t = tid;
+    r_sg = t % SEGS;
+    t /= SEGS;
+    const int rr0 = t & 1;
+    t >>= 1;
+    int p0 = 0;
+    if constexpr (NP >= 2) {
+      p0 = t & 1;
+      t >>= 1;
+    }
+    r_rr = rr0 + 2 * (t % (RC / 2));
+    t /= RC / 2;
+    r_p = NP >= 2 ? p0 + 2 * t : t;
+  }
   // column-pass role
   const int c_x = tid % kTW;
   const int c_p = (tid / kTW) % NP;
@@ -176,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
   // loads and its LDS store: the loads of chunk i+1 are issued right after
   // chunk i is stored, so their latency hides behind chunk i's FIR passes.
   // pm[q][p] is the multiplier of plane p (forward: 1, f~_c; adjoint: beta, a_c).
-  constexpr int NPOS = (RC * SW + kBlock - 1) / kBlock;
+  constexpr int NPOS = (RC * SW + BT - 1) / BT;
   constexpr int NCH1 = NCHAN > 0 ? NCHAN : 1;
   float pu[NPOS], pf[NPOS][NCH1], pb[NPOS];
   auto fetch = [&](int kk, int icc) {
@@ -186,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
     const int gy0 = ty0k - S + icc * RC;
 #pragma unroll
     for (int q = 0; q < NPOS; ++q) {
-      const int e = tid + q * kBlock;
+      const int e = tid + q * BT;
       const int rr = e / SW, j = e - rr * SW;
       const int gy = gy0 + rr, gx = tx0 - S + j;
       const bool in = e < RC * SW && j < kTW + 2 * S && gy >= 0 && gy < H && gx >= 0 && gx < W;
@@ -213,16 +232,16 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
         // barrier that preceded the previous column pass)
 #pragma unroll
         for (int q = 0; q < NPOS; ++q) {
-          const int e = tid + q * kBlock;
+          const int e = tid + q * BT;
           if (e < RC * SW) {
             const int rr = e / SW, j = e - rr * SW;
             if constexpr (MODE == MODE_ADJ)
               stg[rr * SW + j] = pb[q] * pu[q];  // plane 0: beta u_k
             else
-              stg[(UPL * RC + rr) * SW + j] = pu[q];
+              stg[UPL * K::PSTG + rr * SW + j] = pu[q];
 #pragma unroll
             for (int ch = 0; ch < NCHAN; ++ch)
-              stg[(((HAS_E ? 1 : 0) + ch) * RC + rr) * SW + j] = pf[q][ch] * pu[q];
+              stg[((HAS_E ? 1 : 0) + ch) * K::PSTG + rr * SW + j] = pf[q][ch] * pu[q];
           }
         }
         if (ic + 1 < nin)
@@ -237,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
           const int slot = (ic % (1 + LAG)) * RC + r_rr;
           const bool mirror = slot < 2 * S;
           double win[K::WIN];
-          const float4 *src = reinterpret_cast<const float4 *>(&stg[(r_p * RC + r_rr) * SW + r_sg * RUN]);
+          const float4 *src = reinterpret_cast<const float4 *>(&stg[r_p * K::PSTG + r_rr * SW + r_sg * RUN]);
 #pragma unroll
           for (int v4 = 0; v4 < K::WIN / 4; ++v4) {
             const float4 q = src[v4];
@@ -246,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
             win[4 * v4 + 2] = (double)q.z;
             win[4 * v4 + 3] = (double)q.w;
           }
-          float *dst = &ring[(r_p * RINGX + slot) * kTWP + r_sg * RUN];
+          float *dst = &ring[r_p * K::PR + slot * kTWP + r_sg * RUN];
 #pragma unroll
           for (int i = 0; i < RUN; ++i) {
             const double s = fir_sym<S>(a.wr, &win[i]);
@@ -257,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
           if constexpr (FWD) {
             if (r_p == 0) {
               // raw u_k at the tile's own columns, for the contraction
-              const float *us = &stg[(UPL * RC + r_rr) * SW + S + r_sg * RUN];
+              const float *us = &stg[UPL * K::PSTG + r_rr * SW + S + r_sg * RUN];
               float *ud = &uring[slot * kTWP + r_sg * RUN];
 #pragma unroll
               for (int i = 0; i < RUN; ++i) {
@@ -275,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
           // local output rows o0 .. o0+RUN-1 need R rows o0 .. o0+RUN+2S-1
           const int o0 = oc * RC + c_sub * RUN;
           const int b0 = (oc * RC) % RING + c_sub * RUN;   // < RING, window ends < RINGX
-          const float *col = &ring[(c_p * RINGX + b0) * kTWP + c_x];
+          const float *col = &ring[c_p * K::PR + b0 * kTWP + c_x];
           double win[RUN + 2 * S];
 #pragma unroll
           for (int j = 0; j < RUN + 2 * S; ++j) win[j] = col[j * kTWP];
@@ -324,8 +343,8 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
             const int ty0k = opaque(ty * TH);
             float *outk = a.plane_out + (int64_t)k * N;
 #pragma unroll
-            for (int m = 0; m < RC * kTW / kBlock; ++m) {
-              const int pl = tid + m * kBlock;
+            for (int m = 0; m < RC * kTW / BT; ++m) {
+              const int pl = tid + m * BT;
               const int row = pl / kTW, cx = pl % kTW;
               const int gy = ty0k + oc * RC + row, gx = tx0 + cx;
               if (oc < a.nch && gy < H && gx < W) {
@@ -354,7 +373,7 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
     double *red = reinterpret_cast<double *>(smem);
     red[tid] = sacc;
     __syncthreads();
-    for (int h = kBlock / 2; h > 0; h >>= 1) {
+    for (int h = BT / 2; h > 0; h >>= 1) {
       if (tid < h) red[tid] += red[tid + h];
       __syncthreads();
     }
@@ -438,10 +457,10 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(ConvArgs a) {
 }
 
 // Tile geometry and launch of one kernel instantiation.
-template <int S, int NP, bool HAS_E, int RC, int MODE>
+template <int S, int NP, bool HAS_E, int RC, int MODE, int BT = kBlock>
 hipError_t launch_one(ConvArgs a, hipStream_t s, int ch_per_block, int nchunks_c, int min_blocks = 512,
                       int *nblocks_out = nullptr) {
-  using K = Cfg<S, NP, HAS_E, RC, MODE>;
+  using K = Cfg<S, NP, HAS_E, RC, MODE, BT>;
   a.ch_per_block = ch_per_block;
   a.tiles_x = (a.W + kTW - 1) / kTW;
   // largest chunk count (<= NCH_MAX) that still gives >= min_blocks blocks
@@ -460,7 +479,7 @@ hipError_t launch_one(ConvArgs a, hipStream_t s, int ch_per_block, int nchunks_c
   if (nb > 0x7fffffff) return hipErrorInvalidValue;
   a.nblocks = (int)nb;
   if (nblocks_out) *nblocks_out = a.nblocks;
-  hipLaunchKernelGGL((conv_kernel<S, NP, HAS_E, RC, MODE>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL((conv_kernel<S, NP, HAS_E, RC, MODE, BT>), dim3(a.nblocks), dim3(BT), 0, s, a);
   return hipGetLastError();
 }
 

@@ -59,10 +59,23 @@ __global__ __launch_bounds__(kBlock) void embed_kernel(Guide g, int64_t N, const
     }
     __syncthreads();
     const int64_t x = base + px;
-    for (int kk = kg; kk < r_eff; kk += 4) {
-      double acc = 0.0;
-      for (int k = 0; k < r; ++k) acc = fma(F[k * r_eff + kk], (double)bs[k * kTilePx + px], acc);
-      if (x < N) u[(int64_t)kk * N + x] = (float)acc;
+    // four outputs per thread share each b read and give four independent chains
+    for (int kb = 0; kb < r_eff; kb += 16) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      int kk[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int v = kb + kg + 4 * q;
+        kk[q] = v < r_eff ? v : r_eff - 1;
+      }
+      for (int k = 0; k < r; ++k) {
+        const double bv = (double)bs[k * kTilePx + px];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = fma(F[k * r_eff + kk[q]], bv, acc[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (kb + kg + 4 * q < r_eff && x < N) u[(int64_t)(kb + kg + 4 * q) * N + x] = (float)acc[q];
     }
   }
 }

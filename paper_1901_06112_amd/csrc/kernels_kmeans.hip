@@ -60,27 +60,49 @@ __global__ __launch_bounds__(kBlock) void assign_small_kernel(const float *__res
   }
   for (int i = tid; i < r * (D + 1); i += kBlock) sacc[i] = 0.0;
   __syncthreads();
-  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < N; base += (int64_t)gridDim.x * kBlock) {
-    const int64_t x = base + tid;
-    if (x >= N) continue;
-    float pv[D];
+  // two pixels per thread per pass share each centroid read and interleave
+  // two independent distance chains
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t x0 = (int64_t)blockIdx.x * kBlock + tid; x0 < N; x0 += 2 * stride) {
+    const int64_t x1 = x0 + stride;
+    const bool v1 = x1 < N;
+    float pv0[D], pv1[D];
 #pragma unroll
-    for (int j = 0; j < D; ++j) pv[j] = P[x * D + j];
-    float best = FLT_MAX;
-    int bi = 0;
+    for (int j = 0; j < D; ++j) {
+      pv0[j] = P[x0 * D + j];
+      pv1[j] = v1 ? P[x1 * D + j] : 0.0f;
+    }
+    float b0 = FLT_MAX, b1 = FLT_MAX;
+    int i0 = 0, i1 = 0;
     for (int k = 0; k < r; ++k) {
-      float d2 = sc[k * DS + D];
+      float d0 = sc[k * DS + D], d1 = d0;
 #pragma unroll
-      for (int j = 0; j < D; ++j) d2 = fmaf(pv[j], sc[k * DS + j], d2);
-      if (d2 < best) {
-        best = d2;
-        bi = k;
+      for (int j = 0; j < D; ++j) {
+        const float cj = sc[k * DS + j];
+        d0 = fmaf(pv0[j], cj, d0);
+        d1 = fmaf(pv1[j], cj, d1);
+      }
+      if (d0 < b0) {
+        b0 = d0;
+        i0 = k;
+      }
+      if (d1 < b1) {
+        b1 = d1;
+        i1 = k;
       }
     }
-    if (labels) labels[x] = bi;
+    if (labels) {
+      labels[x0] = i0;
+      if (v1) labels[x1] = i1;
+    }
 #pragma unroll
-    for (int j = 0; j < D; ++j) atomicAdd(&sacc[bi * (D + 1) + j], (double)pv[j]);
-    atomicAdd(&sacc[bi * (D + 1) + D], 1.0);
+    for (int j = 0; j < D; ++j) atomicAdd(&sacc[i0 * (D + 1) + j], (double)pv0[j]);
+    atomicAdd(&sacc[i0 * (D + 1) + D], 1.0);
+    if (v1) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) atomicAdd(&sacc[i1 * (D + 1) + j], (double)pv1[j]);
+      atomicAdd(&sacc[i1 * (D + 1) + D], 1.0);
+    }
   }
   __syncthreads();
   double *dst = partials + (size_t)blockIdx.x * r * (D + 1);
@@ -158,8 +180,9 @@ __global__ __launch_bounds__(kBlock) void assign_generic_kernel(Guide g, int64_t
 }
 
 // Per-cluster sums of the guide values given labels, into this block's slot
-// partials[b][r][D+1]: accumulated in LDS when it fits, otherwise directly in
-// the slot (which is zeroed first).
+// partials[b][r][D+1]: accumulated in FP32 LDS when it fits (each block sums
+// at most a few thousand pixels), otherwise in FP64 directly in the slot
+// (which is zeroed first).
 __global__ __launch_bounds__(kBlock) void accumulate_generic_kernel(Guide g, int64_t N,
                                                                     const int *__restrict__ labels,
                                                                     int r, double *__restrict__ partials,
@@ -175,35 +198,36 @@ __global__ __launch_bounds__(kBlock) void accumulate_generic_kernel(Guide g, int
     for (int i = tid; i < r * stride; i += kBlock) sums[i] = 0.0;
   }
   __syncthreads();
-  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < N; base += (int64_t)gridDim.x * kBlock) {
-    const int64_t x = base + tid;
-    const bool valid = x < N;
-    const int lab = valid ? labels[x] : 0;
-    bool active = valid;
-    while (true) {
-      const uint64_t m = __ballot(active);
-      if (m == 0) break;
-      const int leader = __ffsll((unsigned long long)m) - 1;
-      const int L = __shfl(lab, leader, kWave);
-      const bool mine = active && lab == L;
-      for (int d = 0; d < D; ++d) {
-        const float s = wave_sum(mine ? guide_elem(g, x, d) : 0.0f);
-        if (lane_id() == 0) {
-          if (use_lds)
-            atomicAdd(&sacc[L * stride + d], s);
-          else
-            atomicAdd(&sums[L * stride + d], (double)s);
+  // Each lane adds its pixel's guide vector to its cluster's row: lanes of a
+  // wave that share a label hit the same LDS word and are serialised by the
+  // LDS unit, which is still far cheaper than reducing across the wave once
+  // per distinct label.
+  auto add = [&](int L, int d, float v) {
+    if (use_lds)
+      atomicAdd(&sacc[L * stride + d], v);
+    else
+      atomicAdd(&sums[L * stride + d], (double)v);
+  };
+  for (int64_t x = (int64_t)blockIdx.x * kBlock + tid; x < N; x += (int64_t)gridDim.x * kBlock) {
+    const int L = labels[x];
+    if (g.kind == GUIDE_PATCH) {
+      // walk the patch as (dy, dx, c) with incremental addressing
+      const int T = 2 * g.pr + 1;
+      const int y = (int)(x / g.W), xx = (int)(x - (int64_t)y * g.W);
+      int d = 0;
+      for (int dy = 0; dy < T; ++dy) {
+        const int yy = sym_index(y + dy - g.pr, g.H);
+        const float *row = g.f + (int64_t)yy * g.W * g.C;
+        for (int dx = 0; dx < T; ++dx) {
+          const float *px = row + (int64_t)sym_index(xx + dx - g.pr, g.W) * g.C;
+          for (int c = 0; c < g.C; ++c, ++d) add(L, d, px[c]);
         }
       }
-      const float cnt = wave_sum(mine ? 1.0f : 0.0f);
-      if (lane_id() == 0) {
-        if (use_lds)
-          atomicAdd(&sacc[L * stride + D], cnt);
-        else
-          atomicAdd(&sums[L * stride + D], (double)cnt);
-      }
-      active = active && !mine;
+    } else {
+      const float *px = g.kind == GUIDE_EXPLICIT ? g.p + x * D : g.f + x * g.C;
+      for (int d = 0; d < D; ++d) add(L, d, px[d]);
     }
+    add(L, D, 1.0f);
   }
   if (use_lds) {
     __syncthreads();

@@ -74,16 +74,47 @@ __device__ __forceinline__ void stage_pixels(const MArgs &a, int64_t base, typen
   const int tid = threadIdx.x, px = tid & (kTP - 1), q = tid >> 6;
   const int64_t x = base + px;
   const bool valid = x < a.N;
-  const int D = a.g.D;
+  const Guide &g = a.g;
+  const int D = g.D;
   float s2 = 0.0f;
-  for (int m = q; m < a.Dp / 8; m += 4) {
+  if (g.kind == GUIDE_PATCH) {
+    // element d = (dy T + dx) C + c of the patch around (y, xx), walked with
+    // incremental (dy, dx, c) counters from the start of each 8-element chunk
+    const int PW = 2 * g.pr + 1;  // patch width
+    const int y = valid ? (int)(x / g.W) : 0, xx = valid ? (int)(x - (int64_t)y * g.W) : 0;
+    for (int m = q; m < a.Dp / 8; m += 4) {
+      int d = 8 * m;
+      int c = d % g.C, qd = d / g.C;
+      int dx = qd % PW, dy = qd / PW;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int d = 8 * m + e;
-      float v = 0.0f;
-      if (valid && d < D) v = guide_elem(a.g, x, d) - a.mu[d];
-      s2 = fmaf(v, v, s2);
-      pt[px * a.DS + d] = (T)v;
+      for (int e = 0; e < 8; ++e, ++d) {
+        float v = 0.0f;
+        if (valid && d < D) {
+          const int yy = sym_index(y + dy - g.pr, g.H), xs = sym_index(xx + dx - g.pr, g.W);
+          v = g.f[((int64_t)yy * g.W + xs) * g.C + c] - a.mu[d];
+        }
+        s2 = fmaf(v, v, s2);
+        pt[px * a.DS + d] = (T)v;
+        if (++c == g.C) {
+          c = 0;
+          if (++dx == PW) {
+            dx = 0;
+            ++dy;
+          }
+        }
+      }
+    }
+  } else {
+    const float *src = g.kind == GUIDE_EXPLICIT ? g.p + x * D : g.f + x * g.C;
+    for (int m = q; m < a.Dp / 8; m += 4) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int d = 8 * m + e;
+        float v = 0.0f;
+        if (valid && d < D) v = src[d] - a.mu[d];
+        s2 = fmaf(v, v, s2);
+        pt[px * a.DS + d] = (T)v;
+      }
     }
   }
   red[q * kTP + px] = s2;
