@@ -16,7 +16,7 @@ template <int S>
 hipError_t launch_S(ConvArgs a, hipStream_t s) {
   const int C = a.C;
   if (C == 1) return launch_one<S, 2, true, 32, MODE_FWD>(a, s, 1, 1);
-  if (C <= 3) return launch_one<S, 4, true, 16, MODE_FWD>(a, s, 3, 1);
+  if (C <= 3) return launch_one<S, 4, true, 32, MODE_FWD, 512>(a, s, 3, 1);
   // eta pass, then channel chunks that read eta
   hipError_t e = launch_one<S, 1, true, 32, MODE_FWD>(a, s, 0, 1);
   if (e != hipSuccess) return e;
