@@ -13,7 +13,13 @@ HBM before the timed region.
 
 Prints one JSON line; ``roofline`` describes the convolution + contraction
 kernel, timed with HIP events on the stream it runs on; ``cpu_baseline`` is
-the FP64 oracle on a bounded crop of the same image.
+the FP64 oracle on a bounded crop of the same image.  ``workloads`` holds the
+other configurations, each timed the same way (whole calls, inputs resident):
+the hyperspectral BLF (512 x 512 x 128, d = 128) in the plain FP32 form and
+the BF16 precision form, the colour NLM (1024 x 1024, 7 x 7 x 3 patches,
+d = 147, 21 x 21 box) in FP32 and FP16, and the differentiation batch (eight
+384..1024-sided images, fixed landmarks) forward and forward + backward.
+``--leg NAME`` runs one of those legs alone (for profiling).
 """
 from __future__ import annotations
 
@@ -30,6 +36,7 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "color_blf_2048"
 PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
+PEAK_MFMA16_TFLOPS = 2500.0       # MI355X dense BF16 / FP16 matrix peak
 
 
 def conv_flops_per_pixel(r_eff, C, T):
@@ -47,17 +54,42 @@ def conv_bytes_per_pixel(r_eff, C):
     return 4 * (r_eff + 2 * C)
 
 
-def _traffic(n_launch_px):
+CONV_SOURCES = ("kernels_conv.hip", "conv_core.h", "device_common.h")
+
+
+def conv_source_hash():
+    """SHA-256 over the sources of the convolution kernel, so that a stored
+    counter reading is used only for the kernel it was taken from."""
+    h = hashlib.sha256()
+    for name in CONV_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1901_06112_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def _traffic():
+    """HBM bytes per launch of the convolution kernel from the committed
+    FETCH_SIZE / WRITE_SIZE readings (already scaled by the copy-kernel
+    calibration), or None when the kernel has changed since."""
     path = os.path.join(ROOT, "profiles", "conv_color_blf_2048_traffic.json")
-    src = os.path.join(ROOT, "paper_1901_06112_amd", "csrc", "kernels_conv.hip")
     try:
         rec = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if rec.get("kernels_conv_sha256") != sha:
+        if rec.get("conv_sources_sha256") != conv_source_hash():
             return None
         return rec["hbm_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         return None
+
+
+def copy_calibration(nbytes, reps):
+    """Device-to-device copies of a known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters: each copy reads and writes nbytes."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
 def cpu_baseline(crop=1024):
@@ -84,6 +116,123 @@ def cpu_baseline(crop=1024):
                       f"(seeding, {prm['iters']} Lloyd iterations, Algorithm 1 in FP64), {dt:.1f} s"}
 
 
+def _timed(fn, steps, warmup, timing_tensor=None):
+    import torch
+
+    from paper_1901_06112_amd import nkf
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    if timing_tensor is not None:
+        nkf.enable_timing(timing_tensor, True)
+        nkf.stage_times(timing_tensor, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = fn()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    st = None
+    if timing_tensor is not None:
+        st = nkf.stage_times(timing_tensor, reset=True)
+        nkf.enable_timing(timing_tensor, False)
+        st = {k: round(v[0] / steps, 4) for k, v in st.items() if v[1] > 0}
+    return ms, st, res
+
+
+def _psnr(a, b, peak):
+    import torch
+    mse = torch.mean((a.double() - b.double()) ** 2).item()
+    return float("inf") if mse == 0 else 10.0 * __import__("math").log10(peak * peak / mse)
+
+
+def leg_precision(name, steps, warmup):
+    """Plain FP32 form against the 16-bit precision form on one high-d workload.
+    MFMA fractions count the algorithmic GEMM flops of the stage: 2 d r per
+    pixel per Lloyd iteration (assignment) and 2 d r + 2 r r_eff per pixel
+    (embedding), against the dense 16-bit MFMA peak."""
+    import torch
+
+    from paper_1901_06112_amd import nkf, synth
+    f, prm = synth.workload(name)
+    H, W, C = f.shape
+    N = H * W
+    ft = torch.from_numpy(f).cuda()
+    if name.startswith("hyper"):
+        kw = dict(sigma_s=prm["sigma_s"], sigma_r=prm["sigma_r"], r=prm["r"], radius=prm["S"],
+                  iters=prm["iters"], seed=prm["landmark_seed"])
+        D, peak, forms = C, 1.0, ("fp32", "bf16")
+    else:
+        kw = dict(sigma_s=1.0, sigma_r=prm["sigma_r"], r=prm["r"], radius=prm["S"], spatial="box",
+                  guide="patch", patch_radius=prm["patch_radius"], iters=prm["iters"],
+                  seed=prm["landmark_seed"])
+        D, peak, forms = C * (2 * prm["patch_radius"] + 1) ** 2, 255.0, ("fp32", "fp16")
+    out = {"H": H, "W": W, "C": C, "d": D, "r": prm["r"], "S": prm["S"],
+           "spatial": kw.get("spatial", "gaussian"), "kmeans_iters": prm["iters"]}
+    res = {}
+    for prec in forms:
+        ms, st, (g, r_eff) = _timed(lambda: nkf.filter(ft, precision=prec, return_r_eff=True, **kw),
+                                    steps, warmup, ft)
+        ent = {"ms_per_call": round(ms, 3), "Mpixel_s": round(N / ms / 1e3, 2), "r_eff": r_eff,
+               "stages_ms": st}
+        if prec != "fp32":
+            km = prm["iters"] * N * 2.0 * D * prm["r"] / (st["kmeans"] * 1e-3) / 1e12
+            em = N * (2.0 * D * prm["r"] + 2.0 * prm["r"] * r_eff) / (st["embed"] * 1e-3) / 1e12
+            ent["kmeans_mfma_TFLOPs"] = round(km, 2)
+            ent["kmeans_mfma_frac"] = round(km / PEAK_MFMA16_TFLOPS, 4)
+            ent["embed_mfma_TFLOPs"] = round(em, 2)
+            ent["embed_mfma_frac"] = round(em / PEAK_MFMA16_TFLOPS, 4)
+        res[prec] = (ent, g)
+    out.update({p: e for p, (e, _) in res.items()})
+    lo = forms[1]
+    out[f"{lo}_speedup_over_fp32"] = round(res["fp32"][0]["ms_per_call"] / res[lo][0]["ms_per_call"], 3)
+    out[f"psnr_{lo}_vs_fp32_dB"] = round(_psnr(res[lo][1], res["fp32"][1], peak), 2)
+    return out
+
+
+def leg_diff(steps, warmup):
+    """Differentiation batch: eight images, landmarks fixed (k-means outside the
+    timed region), forward and forward + hand-written backward (df, dp,
+    d sigma_r, d sigma_s), one call per image on one stream."""
+    import numpy as np
+    import torch
+
+    from paper_1901_06112_amd import nkf, synth
+    sizes = synth.batch_sizes()
+    imgs = []
+    for i, (h, w) in enumerate(sizes):
+        f, prm = synth.workload("diff_batch8", h, w, seed=1050 + i)
+        ft = torch.from_numpy(f).cuda()
+        c = nkf.kmeans(ft, r=prm["r"], iters=prm["iters"], seed=prm["landmark_seed"])
+        Q, al, F, reff = nkf.landmark_factor(c.cpu().numpy().astype(np.float64), prm["sigma_r"])
+        G = torch.from_numpy(np.random.default_rng(1050 + i).normal(0, 1, f.shape).astype(np.float32)).cuda()
+        imgs.append((ft, c, Q, al, F, reff, G))
+    kw = dict(sigma_s=prm["sigma_s"], sigma_r=prm["sigma_r"], radius=prm["S"])
+    npx = sum(h * w for h, w in sizes)
+
+    def fwd():
+        for ft, c, Q, al, F, reff, G in imgs:
+            nkf.filter_landmarks(ft, c, F, **kw)
+
+    def fwdbwd():
+        for ft, c, Q, al, F, reff, G in imgs:
+            nkf.filter_landmarks(ft, c, F, **kw)
+            nkf.filter_backward(ft, c, Q, al, reff, G, **kw)
+
+    ms_f, _, _ = _timed(fwd, steps, warmup)
+    ms_b, _, _ = _timed(fwdbwd, steps, warmup)
+    return {"images": [list(s) for s in sizes], "pixels": npx, "r": prm["r"], "S": prm["S"],
+            "fwd_ms": round(ms_f, 3), "fwd_Mpixel_s": round(npx / ms_f / 1e3, 2),
+            "fwd_bwd_ms": round(ms_b, 3), "fwd_bwd_Mpixel_s": round(npx / ms_b / 1e3, 2)}
+
+
+LEGS = {
+    "hyperspectral": lambda s, w: leg_precision("hyperspectral_512x128", s, w),
+    "nlm": lambda s, w: leg_precision("color_nlm_1024", s, w),
+    "diff_batch": lambda s, w: leg_diff(s, w),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +240,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-crop", type=int, default=1024)
+    ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--leg", choices=sorted(LEGS), help="run one other workload only")
+    ap.add_argument("--leg-steps", type=int, default=3)
+    ap.add_argument("--copy-calibration", type=int, metavar="BYTES",
+                    help="only run device copies of BYTES bytes (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (the filter has no multi-GPU path); got --gpus {a.gpus}",
@@ -101,6 +255,13 @@ def main():
     import torch
 
     from paper_1901_06112_amd import nkf, synth
+
+    if a.copy_calibration:
+        copy_calibration(a.copy_calibration, 5)
+        return
+    if a.leg:
+        print(json.dumps({"leg": a.leg, **LEGS[a.leg](a.leg_steps, 1)}), flush=True)
+        return
 
     f, prm = synth.workload(WORKLOAD)
     H, W, C = f.shape
@@ -135,7 +296,7 @@ def main():
     conv_launch_ms = conv_ms / max(conv_n, 1)
     flops = conv_flops_per_pixel(r_eff, C, T) * N
     achieved = flops / (conv_launch_ms * 1e-3) / 1e12
-    traffic = _traffic(N)
+    traffic = _traffic()
     line = {
         "metric": "Mpixel/s Nystrom BLF forward (k-means + factor + embedding + r(C+1) convolutions + "
                   "contraction), FP32",
@@ -161,6 +322,8 @@ def main():
                      "algorithmic_hbm_GBs": round(conv_bytes_per_pixel(r_eff, C) * N / (conv_launch_ms * 1e-3) / 1e9, 1)},
         "stages_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in st.items() if v[1] > 0},
     }
+    if not a.no_extra:
+        line["workloads"] = {k: fn(a.leg_steps, 1) for k, fn in LEGS.items()}
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(a.cpu_crop)
     print(json.dumps(line), flush=True)

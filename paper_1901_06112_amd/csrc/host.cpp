@@ -264,6 +264,9 @@ nkf_status validate(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, co
     default:
       return fail(ctx, NKF_ERR_INVALID_ARG, "unknown guide kind %d", prm->guide);
   }
+  if (use_mfma_distance(g, prm->prec) && !mfma_path_supported(g, prm->r, prm->prec))
+    return fail(ctx, NKF_ERR_UNSUPPORTED,
+                "16-bit distance form: r=%d landmarks of dimension D=%d exceed the LDS plan", prm->r, D);
   rs.H = H;
   rs.W = W;
   rs.C = C;
@@ -325,8 +328,10 @@ struct FwdBufs {
   unsigned *mm;
   float *u;
   float *eta_buf;
-  float *mu;   // [D] centring of the 16-bit distance path
-  float *F32;  // [r][r_eff] FP32 factor for the MFMA mix
+  float *mu;     // [D] centring of the 16-bit distance path
+  float *F32;    // [r][r_eff] FP32 factor for the MFMA mix
+  double *mpart; // partial sums of the centring offsets
+  void *lm;      // prepared 16-bit landmarks
 };
 
 void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r = kMaxLandmarks) {
@@ -336,6 +341,8 @@ void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r = kMa
   b.eta_buf = cv.take<float>(rs.C > 3 ? rs.N : 1);
   b.mu = cv.take<float>(rs.D);
   b.F32 = cv.take<float>((size_t)r * r_eff);
+  b.mpart = cv.take<double>(guide_mean_scratch_doubles(rs.g));
+  b.lm = cv.take<unsigned char>(mfma_landmark_scratch_bytes(rs.g, r));
 }
 
 nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, const float *c, const double *F,
@@ -344,9 +351,9 @@ nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, cons
     StageTimer tm(ctx, NKF_STAGE_EMBED);
     HIP_TRY(ctx, launch_center(rs.g.f, rs.N, rs.C, prm->center, b.f0, b.mm, ctx->stream));
     if (use_mfma_distance(rs.g, prm->prec)) {
-      HIP_TRY(ctx, launch_guide_mean(rs.g, b.mu, ctx->stream));
+      HIP_TRY(ctx, launch_guide_mean(rs.g, b.mu, b.mpart, ctx->stream));
       HIP_TRY(ctx, launch_embed_mfma(rs.g, c, prm->r, b.mu, F, b.F32, r_eff, prm->sigma_r, prm->prec, b.u,
-                                     ctx->stream));
+                                     b.lm, ctx->stream));
     } else {
       HIP_TRY(ctx, launch_embed(rs.g, c, prm->r, F, r_eff, prm->sigma_r, b.u, ctx->stream));
     }
@@ -373,22 +380,25 @@ struct KmBufs {
   double *sums;
   int *lab_scratch;
   float *mu;
+  void *lm;  // prepared 16-bit landmarks
 };
 
 void carve_km(Carve &cv, const Resolved &rs, int r, KmBufs &b) {
   b.sums = cv.take<double>(kmeans_partials_doubles(r, rs.D));
   b.lab_scratch = cv.take<int>(rs.N);
   b.mu = cv.take<float>(rs.D);
+  b.lm = cv.take<unsigned char>(mfma_landmark_scratch_bytes(rs.g, r));
 }
 
 nkf_status run_lloyd(nkf_ctx *ctx, const Resolved &rs, int r, float *c, int iters, int *labels,
                      const KmBufs &b, int prec) {
   StageTimer tm(ctx, NKF_STAGE_KMEANS);
   if (use_mfma_distance(rs.g, prec)) {
-    if (iters > 0) HIP_TRY(ctx, launch_guide_mean(rs.g, b.mu, ctx->stream));
+    // the partial-sum buffer doubles as the scratch of the centring offsets
+    if (iters > 0) HIP_TRY(ctx, launch_guide_mean(rs.g, b.mu, b.sums, ctx->stream));
     for (int it = 0; it < iters; ++it)
-      HIP_TRY(ctx, launch_kmeans_step_mfma(rs.g, c, r, b.mu, prec, b.sums,
-                                           it + 1 == iters && labels ? labels : b.lab_scratch, ctx->stream));
+      HIP_TRY(ctx, launch_kmeans_step_mfma(rs.g, c, r, b.mu, prec, b.sums, it + 1 == iters ? labels : nullptr,
+                                           b.lm, ctx->stream));
     return NKF_OK;
   }
   for (int it = 0; it < iters; ++it)

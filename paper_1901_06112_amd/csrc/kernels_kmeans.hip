@@ -3,9 +3,10 @@
 //
 // One Lloyd iteration = assignment (nearest centroid, ties to the lowest
 // index) fused with the per-cluster sums, then the mean update.  Small guide
-// dimensions (D <= 8, explicit or self guide) run one pixel per lane with the
+// dimensions (D <= 4, explicit or self guide) run one pixel per lane with the
 // centroids in LDS; larger D (hyperspectral bands, NLM patches) use an LDS
-// pixel tile and register-blocked distances, then a separate accumulation pass.
+// pixel tile and register-blocked distances, then a separate accumulation
+// pass.  The 16-bit precision form of the assignment is in kernels_mfma.hip.
 #include <hip/hip_runtime.h>
 #include <float.h>
 
@@ -235,29 +236,56 @@ __global__ __launch_bounds__(kBlock) void accumulate_generic_kernel(Guide g, int
   }
 }
 
-// c_k = (sum of members) / count.  One block per cluster reduces the
-// per-block partials with a fixed-shape tree (deterministic); an empty
-// cluster keeps its centroid.
+// c_k[d] = mu(d) + S_k[d] / n_k from the per-block partial sums (S of the
+// centred values when mu is given, of the raw values otherwise; mu_mod > 0
+// indexes mu by d % mu_mod).  An empty cluster keeps its centroid.  One block
+// per cluster; every sum runs over the partials in a fixed order, so the
+// result does not depend on timing.
 __global__ __launch_bounds__(kBlock) void update_kernel(const double *__restrict__ partials, int nparts,
-                                                        int r, int D, float *__restrict__ c) {
+                                                        int r, int D, const float *__restrict__ mu,
+                                                        int mu_mod, float *__restrict__ c) {
   __shared__ double red[kBlock];
   __shared__ double cnt_s;
   const int k = blockIdx.x, tid = threadIdx.x;
-  const size_t stride = (size_t)r * (D + 1);
-  for (int d = D; d >= 0; --d) {  // the count (d == D) first
+  const int DA = D + 1;
+  const size_t stride = (size_t)r * DA;
+  const double *base = partials + (size_t)k * DA;
+  if (tid < kWave) {
     double s = 0.0;
-    for (int b = tid; b < nparts; b += kBlock) s += partials[b * stride + (size_t)k * (D + 1) + d];
+    for (int b = tid; b < nparts; b += kWave) s += base[(size_t)b * stride + D];
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m, kWave);
+    if (tid == 0) cnt_s = s;
+  }
+  __syncthreads();
+  const double n = cnt_s;
+  if (!(n > 0.0)) return;
+  // columns in groups of up to kBlock, each summed by G lanes (b = lane mod G)
+  for (int m0 = 0; m0 < D; m0 += kBlock) {
+    const int M = D - m0 < kBlock ? D - m0 : kBlock;
+    const int G = kBlock / M;
+    const int m = tid % M, gl = tid / M;
+    double s = 0.0;
+    if (gl < G) {
+      // loads issued eight at a time, added in block order
+      int b = gl;
+      for (; b + 7 * G < nparts; b += 8 * G) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = base[(size_t)(b + j * G) * stride + m0 + m];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += v[j];
+      }
+      for (; b < nparts; b += G) s += base[(size_t)b * stride + m0 + m];
+    }
     red[tid] = s;
     __syncthreads();
-    for (int h = kBlock / 2; h > 0; h >>= 1) {
-      if (tid < h) red[tid] += red[tid + h];
-      __syncthreads();
-    }
-    if (tid == 0) {
-      if (d == D)
-        cnt_s = red[0];
-      else if (cnt_s > 0.0)
-        c[k * D + d] = (float)(red[0] / cnt_s);
+    if (tid < M) {
+      double t = 0.0;
+      for (int q = 0; q < G; ++q) t += red[q * M + tid];
+      const int d = m0 + tid;
+      const double off = mu ? (double)mu[mu_mod > 0 ? d % mu_mod : d] : 0.0;
+      c[k * D + d] = (float)(off + t / n);
     }
     __syncthreads();
   }
@@ -329,27 +357,17 @@ static hipError_t assign_accumulate(const Guide &g, const float *c, int r, doubl
 }
 
 size_t kmeans_partials_doubles(int r, int D) {
-  const int parts = D <= 4 ? kMaxPartials : kMaxPartialsGeneric;  // (the MFMA path uses the generic count)
+  const int parts = D <= 4 ? kMaxPartials : kMaxPartialsGeneric;  // (the MFMA path: at most 256 blocks)
   return (size_t)parts * r * (D + 1);
 }
 
 hipError_t launch_kmeans_step_mfma(const Guide &g, float *c, int r, const float *mu, int prec, double *partials,
-                                   int *lab, hipStream_t s) {
-  hipError_t e = launch_assign_mfma(g, c, r, mu, prec, lab, s);
+                                   int *labels, void *lm_scratch, hipStream_t s) {
+  int nparts = 0;
+  hipError_t e = launch_lloyd_mfma(g, c, r, mu, prec, partials, labels, &nparts, lm_scratch, s);
   if (e != hipSuccess) return e;
-  const int64_t N = (int64_t)g.H * g.W;
-  const size_t acc_bytes = sizeof(float) * (size_t)r * (g.D + 1);
-  const int use_lds = acc_bytes <= 96 * 1024;
-  if (use_lds) {
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(accumulate_generic_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)acc_bytes);
-    if (e != hipSuccess) return e;
-  }
-  const int nparts = grid_for(N, kBlock * 16, kMaxPartialsGeneric);
-  hipLaunchKernelGGL(accumulate_generic_kernel, dim3(nparts), dim3(kBlock), use_lds ? acc_bytes : 0, s, g, N, lab,
-                     r, partials, use_lds);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(update_kernel, dim3(r), dim3(kBlock), 0, s, partials, nparts, r, g.D, c);
+  hipLaunchKernelGGL(update_kernel, dim3(r), dim3(kBlock), 0, s, partials, nparts, r, g.D, mu,
+                     g.kind == GUIDE_PATCH ? g.C : 0, c);
   return hipGetLastError();
 }
 
@@ -358,7 +376,8 @@ hipError_t launch_kmeans_step(const Guide &g, float *c, int r, double *partials,
   int nparts = 0;
   hipError_t e = assign_accumulate(g, c, r, partials, labels, label_scratch, &nparts, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(update_kernel, dim3(r), dim3(kBlock), 0, s, partials, nparts, r, g.D, c);
+  hipLaunchKernelGGL(update_kernel, dim3(r), dim3(kBlock), 0, s, partials, nparts, r, g.D,
+                     static_cast<const float *>(nullptr), 0, c);
   return hipGetLastError();
 }
 

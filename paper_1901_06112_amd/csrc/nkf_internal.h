@@ -40,14 +40,24 @@ hipError_t launch_kmeans_step(const Guide &g, float *c, int r, double *partials,
 
 // ---- kernels_mfma.hip -------------------------------------------------------
 // Distance step on MFMA with 16-bit centred operands (prec 1 = BF16, 2 = FP16).
-hipError_t launch_guide_mean(const Guide &g, float *mu, hipStream_t s);
-hipError_t launch_assign_mfma(const Guide &g, const float *c, int r, const float *mu, int prec, int *labels,
-                              hipStream_t s);
+// Whether the LDS plan of the 16-bit path fits this guide and landmark count.
+bool mfma_path_supported(const Guide &g, int r, int prec);
+// Centring offsets mu ([C] for patch guides, else [D]); scratch holds
+// guide_mean_scratch_doubles(g) doubles.
+size_t guide_mean_scratch_doubles(const Guide &g);
+hipError_t launch_guide_mean(const Guide &g, float *mu, double *scratch, hipStream_t s);
+// Device scratch (bytes) for the prepared 16-bit landmarks of one launch.
+size_t mfma_landmark_scratch_bytes(const Guide &g, int r);
+// Assignment fused with the per-cluster sums of the centred guide values:
+// per-block FP64 partials [*nparts][r][D+1] (at most 256 blocks); labels nullable.
+hipError_t launch_lloyd_mfma(const Guide &g, const float *c, int r, const float *mu, int prec, double *partials,
+                             int *labels, int *nparts, void *lm_scratch, hipStream_t s);
 hipError_t launch_embed_mfma(const Guide &g, const float *c, int r, const float *mu, const double *F,
-                             float *F32, int r_eff, double sigma_r, int prec, float *u, hipStream_t s);
-// Lloyd step whose assignment runs on MFMA (labels into `lab`, required).
+                             float *F32, int r_eff, double sigma_r, int prec, float *u, void *lm_scratch,
+                             hipStream_t s);
+// One Lloyd step whose assignment runs on MFMA (labels nullable).
 hipError_t launch_kmeans_step_mfma(const Guide &g, float *c, int r, const float *mu, int prec, double *partials,
-                                   int *lab, hipStream_t s);
+                                   int *labels, void *lm_scratch, hipStream_t s);
 // Whether the 16-bit MFMA distance path serves this guide / precision.
 inline bool use_mfma_distance(const Guide &g, int prec) { return prec != 0 && g.D > 8; }
 

@@ -103,3 +103,100 @@ def test_kmeans_assignment_16bit(prec, eps):
     assert mism.sum() == 0
     c_or, _, _ = kmeans.update(P, lab.astype(np.int64), cs)
     np.testing.assert_allclose(c1.cpu().numpy().astype(np.float64), c_or.astype(np.float32), rtol=0, atol=1e-5)
+
+
+def _mixture(h, w, D, seed):
+    """Dirichlet(0.5) mixtures of six random spectra plus N(0, 0.01^2)."""
+    rng = np.random.default_rng(seed)
+    ends = rng.uniform(0.0, 1.0, (6, D))
+    ab = rng.dirichlet(np.full(6, 0.5), h * w)
+    return (ab @ ends + rng.normal(0.0, 0.01, (h * w, D))).astype(np.float32).reshape(h, w, D)
+
+
+# (guide, D, r, precision, h, w): 8-wave blocks with LDS sums (patch), 4-wave
+# blocks with LDS sums (D=200), FP64 sums in global memory (D=256), a ragged
+# last tile in each image row (W=150), and a second patch radius
+LDS_PLANS = [("explicit", 200, 64, "fp16", 40, 44), ("explicit", 256, 64, "bf16", 36, 40),
+             ("patch", 147, 128, "fp16", 50, 150), ("patch", 75, 40, "bf16", 33, 70)]
+
+
+def _plan_case(guide, D, h, w):
+    if guide == "explicit":
+        p = _mixture(h, w, D, D)
+        f = np.ascontiguousarray(255.0 * p[:, :, :3])
+        P = p.reshape(-1, D).astype(np.float64)
+        mu = P.mean(0)
+        return f, p, P, mu, 0
+    pr = {147: 3, 75: 2}[D]
+    f, _ = synth.workload("color_nlm_1024", h, w, seed=D)
+    P = exact.patch_guide(f.astype(np.float64), pr).reshape(-1, D)
+    mu = np.tile(f.reshape(-1, 3).astype(np.float64).mean(0), D // 3)
+    return f, None, P, mu, pr
+
+
+@pytest.mark.parametrize("guide,D,r,prec,h,w", LDS_PLANS)
+def test_kmeans_16bit_lds_plans(guide, D, r, prec, h, w):
+    nkf = _nkf()
+    f, p, P, mu, pr = _plan_case(guide, D, h, w)
+    ft = torch.from_numpy(f).cuda()
+    pt = torch.from_numpy(p).cuda() if p is not None else None
+    kw = dict(guide=guide, patch_radius=pr) if guide == "patch" else dict(guide=guide)
+    c0 = nkf.kmeans(ft, pt, r=r, iters=0, seed=9, **kw)
+    cs = c0.cpu().numpy().astype(np.float64)
+    c1, lab = nkf.kmeans_iterate(ft, c0, pt, iters=1, precision=prec, return_labels=True, **kw)
+    lab = lab.cpu().numpy().reshape(-1)
+    eps = 2.0 ** -8 if prec == "bf16" else 2.0 ** -11
+    d2 = np.stack([((P - ck) ** 2).sum(1) for ck in cs], 1)
+    lab_or = np.argmin(d2, 1)
+    bnd = _tie_bound(P - mu, cs - mu, eps)
+    best = d2[np.arange(len(P)), lab_or]
+    gap_ok = np.all((d2 - best[:, None] > bnd + bnd[np.arange(len(P)), lab_or][:, None]) |
+                    (np.arange(r)[None, :] == lab_or[:, None]), axis=1)
+    mism = (lab != lab_or) & gap_ok
+    # centroids: FP32 sums of at most one 128-pixel tile per block (these
+    # images have fewer tiles than blocks): error <= 128 * 2^-24 * max|p~|
+    c_or, _, _ = kmeans.update(P, lab.astype(np.int64), cs)
+    err = np.abs(c1.cpu().numpy().astype(np.float64) - c_or).max()
+    tol = 2.0 ** -24 * (128 * np.abs(P - mu).max() + 2 * np.abs(P).max())
+    print(f"[kmeans {guide} D{D} r{r} {prec}] mismatches outside the tie band {mism.sum()} "
+          f"(band {(~gap_ok).sum()}); centroid err {err:.3g} (tol {tol:.3g})", flush=True)
+    assert mism.sum() == 0
+    assert err <= tol
+
+
+@pytest.mark.parametrize("guide,D,r,prec,h,w", LDS_PLANS)
+def test_embedding_16bit_lds_plans(guide, D, r, prec, h, w):
+    f, p, P, mu, pr = _plan_case(guide, D, h, w)
+    c32 = _landmarks(P, r, 4, 3)
+    if guide == "explicit":
+        sr, S, kw = float(np.sqrt(D / 40.0)), 4, dict(guide="explicit")
+        g = _run_p(f, p, c32, prec, sigma_s=2.0, sigma_r=sr, radius=S, **kw)
+        go = nystrom.nystrom_filter(f.astype(np.float64), p.astype(np.float64), c32.astype(np.float64), 2.0, sr, S)
+    else:
+        sr, S = 10.0 * np.sqrt(D), 4
+        g = _run_p(f, None, c32, prec, sigma_s=1.0, sigma_r=sr, radius=S, spatial="box", guide="patch",
+                   patch_radius=pr)
+        go = nystrom.nystrom_filter(f.astype(np.float64), P.reshape(h, w, D), c32.astype(np.float64), 1.0, sr,
+                                    S, "box")
+    ps = exact.psnr(g, go)
+    print(f"[embed {guide} D{D} r{r} {prec}] PSNR vs FP64 Nystrom {ps:.1f} dB", flush=True)
+    assert np.isfinite(g).all() and ps >= 45.0
+
+
+def _run_p(f, p, c32, prec, **kw):
+    nkf = _nkf()
+    _, _, F, _ = nkf.landmark_factor(c32.astype(np.float64), kw["sigma_r"])
+    pt = torch.from_numpy(p).cuda() if p is not None else None
+    g = nkf.filter_landmarks(torch.from_numpy(f).cuda(), torch.from_numpy(c32).cuda(), F, pt, precision=prec,
+                             **kw)
+    torch.cuda.synchronize()
+    return g.cpu().numpy().astype(np.float64)
+
+
+def test_16bit_plan_too_large_is_unsupported():
+    nkf = _nkf()
+    p = torch.rand(24, 24, 256, device="cuda")
+    f = torch.rand(24, 24, 3, device="cuda") * 255
+    with pytest.raises(nkf.NkfError) as ei:
+        nkf.kmeans(f, p, r=256, iters=1, seed=1, guide="explicit", precision="bf16")
+    assert ei.value.status == nkf.NKF_ERR_UNSUPPORTED
