@@ -2,9 +2,9 @@
 //
 // Method (Golub & Van Loan, "Matrix Computations", Sections 8.3.1-8.3.3):
 // Householder reduction A = Q T Q^T to tridiagonal form, then implicit
-// symmetric QR steps with the Wilkinson shift on the unreduced blocks of T,
-// accumulating every reflection and rotation into Q.  Cost O(n^3) with a small
-// constant, n <= 256.
+// symmetric QR steps with the Wilkinson shift on the unreduced blocks of T
+// (kept as its diagonal and off-diagonal), accumulating every reflection and
+// rotation into Q.  Cost O(n^3) with a small constant, n <= 256.
 #include <math.h>
 #include <string.h>
 
@@ -17,33 +17,11 @@ namespace {
 
 inline double sgn(double x) { return x < 0.0 ? -1.0 : 1.0; }
 
-// Rotation in the (k, k+1) plane, G = [[c, s], [-s, c]]: T <- G T G^T on the
-// band rows/columns [lo, hi), Q <- Q G^T on all rows.
-void rotate(int n, std::vector<double> &T, std::vector<double> &Q, int k, double c, double s) {
-  const int lo = std::max(0, k - 1), hi = std::min(n, k + 3);
-  for (int j = lo; j < hi; ++j) {  // rows k, k+1
-    const double a = T[k * n + j], b = T[(k + 1) * n + j];
-    T[k * n + j] = c * a + s * b;
-    T[(k + 1) * n + j] = -s * a + c * b;
-  }
-  for (int i = lo; i < hi; ++i) {  // columns k, k+1
-    const double a = T[i * n + k], b = T[i * n + k + 1];
-    T[i * n + k] = c * a + s * b;
-    T[i * n + k + 1] = -s * a + c * b;
-  }
-  for (int i = 0; i < n; ++i) {
-    const double a = Q[i * n + k], b = Q[i * n + k + 1];
-    Q[i * n + k] = c * a + s * b;
-    Q[i * n + k + 1] = -s * a + c * b;
-  }
-}
-
 }  // namespace
 
-// A: n x n row-major symmetric.  On success w[0..n) ascending and V (row-major
-// n x n) holds the matching eigenvectors as columns.  Returns 0, or -1 if the
-// QR iteration did not converge.
-int sym_eig(int n, const double *A, double *w, double *V) {
+namespace {
+
+int sym_eig_impl(int n, const double *A, double *w, double *V) {
   std::vector<double> T(A, A + (size_t)n * n), Q((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) Q[i * n + i] = 1.0;
   // symmetrise (guards against a caller's round-off asymmetry)
@@ -94,48 +72,64 @@ int sym_eig(int n, const double *A, double *w, double *V) {
       for (int j = 0; j < m; ++j) roww[j] -= acc * v[j];
     }
   }
-  // exact zeros outside the band
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j)
-      if (j < i - 1 || j > i + 1) T[i * n + j] = 0.0;
-
-  // ---- implicit symmetric QR with Wilkinson shift -------------------------
+  // ---- implicit symmetric QR with Wilkinson shift on the band -------------
+  // d: diagonal, e[i]: entry (i+1, i); the eigenvector estimates are the rows
+  // of Z = Q^T, so that a rotation in the (k, k+1) plane updates two
+  // contiguous rows.
+  std::vector<double> d(n), e(n, 0.0), Z((size_t)n * n);
+  for (int i = 0; i < n; ++i) {
+    d[i] = T[i * n + i];
+    if (i + 1 < n) e[i] = T[(i + 1) * n + i];
+    for (int j = 0; j < n; ++j) Z[(size_t)i * n + j] = Q[(size_t)j * n + i];
+  }
   const double eps = 2.220446049250313e-16;
   int hi = n - 1;
   int iter = 0;
   const int max_iter = 60 * n + 100;
   while (hi > 0) {
-    // deflate negligible off-diagonals
-    for (int i = 1; i <= hi; ++i) {
-      const double off = fabs(T[i * n + i - 1]);
-      if (off <= eps * (fabs(T[i * n + i]) + fabs(T[(i - 1) * n + i - 1])) || off < 1e-300)
-        T[i * n + i - 1] = T[(i - 1) * n + i] = 0.0;
-    }
-    if (T[hi * n + hi - 1] == 0.0) {
+    // deflate negligible off-diagonals of the active part
+    for (int i = 0; i < hi; ++i)
+      if (fabs(e[i]) <= eps * (fabs(d[i]) + fabs(d[i + 1])) || fabs(e[i]) < 1e-300) e[i] = 0.0;
+    if (e[hi - 1] == 0.0) {
       --hi;
       continue;
     }
     int lo = hi - 1;
-    while (lo > 0 && T[lo * n + lo - 1] != 0.0) --lo;
+    while (lo > 0 && e[lo - 1] != 0.0) --lo;
     if (++iter > max_iter) return -1;
-    // Wilkinson shift from the trailing 2x2 of the block
-    const double a = T[(hi - 1) * n + hi - 1], b = T[hi * n + hi - 1], c = T[hi * n + hi];
-    const double d = 0.5 * (a - c);
-    const double shift = c - b * b / (d + sgn(d) * hypot(d, b));
-    double x = T[lo * n + lo] - shift;
-    double z = T[(lo + 1) * n + lo];
+    // Wilkinson shift: eigenvalue of the trailing 2x2 closer to d[hi]
+    const double dd = 0.5 * (d[hi - 1] - d[hi]), b2 = e[hi - 1];
+    const double shift = d[hi] - b2 * b2 / (dd + sgn(dd) * hypot(dd, b2));
+    double x = d[lo] - shift, z = e[lo];
+    double bulge = 0.0;
     for (int k = lo; k < hi; ++k) {
+      // rotation G = [[c, s], [-s, c]] in the (k, k+1) plane with G (x, z)^T = (r, 0)^T
       const double rr = hypot(x, z);
-      double cs = 1.0, sn = 0.0;
+      double c = 1.0, s = 0.0;
       if (rr != 0.0) {
-        cs = x / rr;
-        sn = z / rr;
+        c = x / rr;
+        s = z / rr;
       }
-      rotate(n, T, Q, k, cs, sn);
-      if (k > lo) T[(k + 1) * n + k - 1] = T[(k - 1) * n + k + 1] = 0.0;  // bulge chased out
+      if (k > lo) e[k - 1] = rr;  // the bulge at (k-1, k+1) is chased out
+      // T <- G T G^T on the 2x2 block and its neighbours
+      const double dk = d[k], dk1 = d[k + 1], ek = e[k];
+      d[k] = c * c * dk + 2.0 * c * s * ek + s * s * dk1;
+      d[k + 1] = s * s * dk - 2.0 * c * s * ek + c * c * dk1;
+      e[k] = c * s * (dk1 - dk) + (c * c - s * s) * ek;
       if (k + 1 < hi) {
-        x = T[(k + 1) * n + k];
-        z = T[(k + 2) * n + k];
+        bulge = s * e[k + 1];  // new entry (k, k+2)
+        e[k + 1] *= c;
+      }
+      // Q <- Q G^T, i.e. rows k, k+1 of Z
+      double *zk = &Z[(size_t)k * n], *zk1 = &Z[(size_t)(k + 1) * n];
+      for (int i = 0; i < n; ++i) {
+        const double a = zk[i], bb = zk1[i];
+        zk[i] = c * a + s * bb;
+        zk1[i] = -s * a + c * bb;
+      }
+      if (k + 1 < hi) {
+        x = e[k];
+        z = bulge;
       }
     }
   }
@@ -143,12 +137,19 @@ int sym_eig(int n, const double *A, double *w, double *V) {
   // ---- sort ascending -------------------------------------------------------
   std::vector<int> ord(n);
   for (int i = 0; i < n; ++i) ord[i] = i;
-  std::sort(ord.begin(), ord.end(), [&](int i, int j) { return T[i * n + i] < T[j * n + j]; });
+  std::sort(ord.begin(), ord.end(), [&](int i, int j) { return d[i] < d[j]; });
   for (int j = 0; j < n; ++j) {
-    w[j] = T[ord[j] * n + ord[j]];
-    for (int i = 0; i < n; ++i) V[i * n + j] = Q[i * n + ord[j]];
+    w[j] = d[ord[j]];
+    for (int i = 0; i < n; ++i) V[i * n + j] = Z[(size_t)ord[j] * n + i];
   }
   return 0;
 }
+
+}  // namespace
+
+// A: n x n row-major symmetric.  On success w[0..n) ascending and V (row-major
+// n x n) holds the matching eigenvectors as columns.  Returns 0, or -1 if the
+// QR iteration did not converge.
+int sym_eig(int n, const double *A, double *w, double *V) { return sym_eig_impl(n, A, w, V); }
 
 }  // namespace nkf

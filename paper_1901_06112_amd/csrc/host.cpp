@@ -287,15 +287,17 @@ nkf_status factor(nkf_ctx *ctx, int r, int D, const double *c, double sigma_r, d
                   double *alpha, double *F, int *r_eff) {
   std::vector<double> A((size_t)r * r), Qv((size_t)r * r), al(r);
   const double inv = isinf(sigma_r) ? 0.0 : 1.0 / (2.0 * sigma_r * sigma_r);
-  for (int i = 0; i < r; ++i)
-    for (int j = 0; j < r; ++j) {
+  for (int i = 0; i < r; ++i) {
+    A[i * r + i] = 1.0;
+    for (int j = 0; j < i; ++j) {
       double d2 = 0.0;
       for (int k = 0; k < D; ++k) {
         const double t = c[i * D + k] - c[j * D + k];
         d2 += t * t;
       }
-      A[i * r + j] = exp(-d2 * inv);
+      A[i * r + j] = A[j * r + i] = exp(-d2 * inv);
     }
+  }
   if (sym_eig(r, A.data(), al.data(), Qv.data()) != 0)
     return fail(ctx, NKF_ERR_NUMERICAL, "eigendecomposition of A did not converge");
   const double amax = al[r - 1];
