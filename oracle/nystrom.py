@@ -162,18 +162,23 @@ def nystrom_kernel_matrix(P, c, sigma_r, tau=DEFAULT_TAU):
     return (V * alpha[None, :]) @ V.T
 
 
-def storage_error_bound(f, p, c, sigma_s, sigma_r, S, spatial="gaussian", tau=DEFAULT_TAU, center=None):
+def storage_error_bound(f, p, c, sigma_s, sigma_r, S, spatial="gaussian", tau=DEFAULT_TAU, center=None,
+                        cross_kernel_rounding=False):
     """First-order sensitivity of g_hat(x) to a relative perturbation of every
     stored intermediate (the embedding planes u_k, the products u_k f~ and the
-    convolved planes), used to derive per-pixel tolerances for reduced
-    precision evaluations of Algorithm 1:
+    convolved planes; with ``cross_kernel_rounding`` also the cross-kernel
+    values b_j), used to derive per-pixel tolerances for reduced precision
+    evaluations of Algorithm 1:
 
-        B(x, c) = ( sum_k |u_k(x)| (w * |u_k f~_c|)(x)
-                    + |g~_c(x)| sum_k |u_k(x)| (w * |u_k|)(x) ) / |eta_hat(x)|
+        B(x, c) = ( sum_k v_k(x) (w * (v_k |f~_c|))(x)
+                    + |g~_c(x)| sum_k v_k(x) (w * v_k)(x) ) / |eta_hat(x)|
 
-    with u = F^T b (u(x).u(y) = K_hat(x, y)), f~ = f - f0.  A relative error
-    delta in each stored value moves g_hat(x) by at most about delta B(x, c).
-    Returns B as [H, W, C]."""
+    with u = F^T b (u(x).u(y) = K_hat(x, y)), f~ = f - f0 and v_k = |u_k|, or
+    v_k = sum_j |F_jk| b_j >= |u_k| when the b_j themselves carry a relative
+    error: Eq. (vk) cancels when A is ill-conditioned, and a relative error
+    delta in each b_j moves u_k by up to delta sum_j |F_jk| b_j.  A relative
+    error delta in each stored value moves g_hat(x) by at most about
+    delta B(x, c).  Returns B as [H, W, C]."""
     f = np.asarray(f, np.float64)
     p = np.asarray(p, np.float64)
     H, W, C = f.shape
@@ -181,18 +186,21 @@ def storage_error_bound(f, p, c, sigma_s, sigma_r, S, spatial="gaussian", tau=DE
     fc = f - f0
     w1 = spatial_taps(sigma_s, S, spatial)
     alpha, Wv = landmark_eig(c, sigma_r, tau)
-    U = (cross_kernel_sr(c, p.reshape(H * W, -1), sigma_r) @ Wv) / np.sqrt(alpha)[None, :]
+    Fm = Wv / np.sqrt(alpha)[None, :]
+    bx = cross_kernel_sr(c, p.reshape(H * W, -1), sigma_r)
+    U = bx @ Fm
+    Vm = bx @ np.abs(Fm) if cross_kernel_rounding else np.abs(U)
     eta = np.zeros((H, W))
     eabs = np.zeros((H, W))
     zeta = np.zeros((H, W, C))
     zabs = np.zeros((H, W, C))
     for k in range(U.shape[1]):
         uk = U[:, k].reshape(H, W)
-        ua = np.abs(uk)
+        vk = Vm[:, k].reshape(H, W)
         eta += uk * conv_zero(uk, w1)
-        eabs += ua * conv_zero(ua, w1)
+        eabs += vk * conv_zero(vk, w1)
         zeta += uk[:, :, None] * conv_zero(uk[:, :, None] * fc, w1)
-        zabs += ua[:, :, None] * conv_zero(ua[:, :, None] * np.abs(fc), w1)
+        zabs += vk[:, :, None] * conv_zero(vk[:, :, None] * np.abs(fc), w1)
     with np.errstate(divide="ignore", invalid="ignore"):
         gt = zeta / eta[:, :, None]
         B = (zabs + np.abs(gt) * eabs[:, :, None]) / np.abs(eta)[:, :, None]

@@ -28,6 +28,7 @@ SOURCES = [
     "kernels_kmeans.hip",
     "kernels_embed.hip",
     "kernels_conv.hip",
+    "kernels_conv_box.hip",
     "kernels_bwd.hip",
     "kernels_mfma.hip",
 ]

@@ -132,7 +132,30 @@ __device__ __forceinline__ double fir_sym(const double *w, const double *x) {
   return s;
 }
 
-template <int S, int NP, bool HAS_E, int RC, int MODE, int BT = kBlock>
+// Output i of a run of consecutive outputs over win[i .. i + 2S], called for
+// i = 0, 1, ... in order: the symmetric FIR with taps w, or for the box
+// kernel (all taps 1) a sliding FP64 sum that adds the entering and drops
+// the leaving value (2 operations per output instead of 2S + 1).
+template <int S, bool BOX>
+struct Window {
+  double s = 0.0;
+  __device__ __forceinline__ double at(const double *w, const double *win, int i) {
+    if constexpr (BOX) {
+      if (i == 0) {
+        s = 0.0;
+#pragma unroll
+        for (int t = 0; t <= 2 * S; ++t) s += win[t];
+      } else {
+        s += win[i + 2 * S] - win[i - 1];
+      }
+      return s;
+    } else {
+      return fir_sym<S>(w, &win[i]);
+    }
+  }
+};
+
+template <int S, int NP, bool HAS_E, int RC, int MODE, int BT = kBlock, bool BOX = false>
 __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
   using K = Cfg<S, NP, HAS_E, RC, MODE, BT>;
   constexpr int SW = K::SW, RUN = K::RUN, SEGS = K::SEGS, LAG = K::LAG, RING = K::RING;
@@ -266,9 +289,10 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
             win[4 * v4 + 3] = (double)q.w;
           }
           float *dst = &ring[r_p * K::PR + slot * kTWP + r_sg * RUN];
+          Window<S, BOX> rw;
 #pragma unroll
           for (int i = 0; i < RUN; ++i) {
-            const double s = fir_sym<S>(a.wr, &win[i]);
+            const double s = rw.at(a.wr, win, i);
             const float sf = (float)s;
             dst[i] = sf;
             if (mirror) dst[RING * kTWP + i] = sf;
@@ -302,9 +326,10 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
           const double *wcol = MODE == MODE_SIGS ? a.wc : a.wr;
           if constexpr (FWD) {
             const float *ucol = &uring[(b0 + S) * kTWP + c_x];
+            Window<S, BOX> cw;
 #pragma unroll
             for (int i = 0; i < RUN; ++i) {
-              const double z = fir_sym<S>(wcol, &win[i]);
+              const double z = cw.at(wcol, win, i);
               acc[oc][i] = fmaf(ucol[i * kTWP], (float)z, acc[oc][i]);
             }
           } else {
@@ -457,7 +482,7 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
 }
 
 // Tile geometry and launch of one kernel instantiation.
-template <int S, int NP, bool HAS_E, int RC, int MODE, int BT = kBlock>
+template <int S, int NP, bool HAS_E, int RC, int MODE, int BT = kBlock, bool BOX = false>
 hipError_t launch_one(ConvArgs a, hipStream_t s, int ch_per_block, int nchunks_c, int min_blocks = 512,
                       int *nblocks_out = nullptr) {
   using K = Cfg<S, NP, HAS_E, RC, MODE, BT>;
@@ -479,7 +504,7 @@ hipError_t launch_one(ConvArgs a, hipStream_t s, int ch_per_block, int nchunks_c
   if (nb > 0x7fffffff) return hipErrorInvalidValue;
   a.nblocks = (int)nb;
   if (nblocks_out) *nblocks_out = a.nblocks;
-  hipLaunchKernelGGL((conv_kernel<S, NP, HAS_E, RC, MODE, BT>), dim3(a.nblocks), dim3(BT), 0, s, a);
+  hipLaunchKernelGGL((conv_kernel<S, NP, HAS_E, RC, MODE, BT, BOX>), dim3(a.nblocks), dim3(BT), 0, s, a);
   return hipGetLastError();
 }
 

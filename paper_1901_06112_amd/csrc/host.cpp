@@ -201,6 +201,7 @@ struct Resolved {
   int64_t N;
   Guide g;
   Taps taps;
+  int box;  // spatial kernel is the box
 };
 
 // Validation shared by every device entry point.
@@ -274,6 +275,7 @@ nkf_status validate(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, co
   rs.S = S;
   rs.N = N;
   rs.g = g;
+  rs.box = prm->spatial == NKF_SPATIAL_BOX;
   for (int t = 0; t < 2 * kMaxRadius + 1; ++t) rs.taps.w[t] = 0.0f;
   for (int t = -S; t <= S; ++t)
     rs.taps.w[t + S] = prm->spatial == NKF_SPATIAL_BOX
@@ -370,6 +372,7 @@ nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, cons
   pb.f0 = b.f0;
   pb.u = b.u;
   pb.taps = rs.taps;
+  pb.box = rs.box;
   pb.out = out;
   pb.eta_out = eta_out;
   pb.eta_buf = b.eta_buf;

@@ -6,9 +6,9 @@
 // Also the per-channel centring offset f0 of the image.
 //
 // Precision: squared distances are formed in FP64 from the FP32 guide and
-// landmarks (exact differences), and the exponential takes an exact FP64
-// argument reduction exp(-z) = 2^-n * 2^-fr, so the relative error of b does
-// not grow with the exponent; the r x r_eff mix accumulates in FP64.
+// landmarks (exact differences), b = exp(-d^2 / (2 sigma_r^2)) is evaluated
+// and kept in FP64, and the r x r_eff mix accumulates in FP64, so the stored
+// u_k carries a single FP32 rounding even where F^T b cancels.
 #include <hip/hip_runtime.h>
 #include <float.h>
 #include <math.h>
@@ -20,62 +20,84 @@ namespace nkf {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kTilePx = 64;
 
-// exp(-z) for z >= 0 with relative error independent of z.
-__device__ __forceinline__ float exp_neg(double z) {
-  const double y = z * 1.4426950408889634074;  // log2(e)
-  if (y > 160.0) return 0.0f;
-  const double n = floor(y);
-  const float fr = (float)(y - n);
-  return ldexpf(exp2f(-fr), -(int)n);
+// exp(-z) for z >= 0 to FP64 accuracy: z = n ln2 - r with n = round(z / ln2)
+// and |r| <= ln2 / 2, ln2 split in two parts (the high part has 21
+// significant bits, so n * ln2_hi is exact for the n that occur); exp(r) from
+// its Taylor polynomial of degree 13 (truncation below 5e-18 relative), then
+// a scale by 2^-n.  FP64 accuracy matters when F has large entries: the mix
+// u = F^T b cancels, and an FP32 rounding of each b_j would move u_k by up to
+// eps sum_j |F_jk| b_j instead of eps |u_k|.
+__device__ __forceinline__ double exp_neg64(double z) {
+  if (!(z < 745.0)) return 0.0;
+  const double n = rint(z * 1.4426950408889634);
+  const double r = (n * 0.6931467056274414 - z) + n * 4.7493250390316726e-07;
+  double q = 1.6059043836821613e-10;  // 1 / 13!
+  q = fma(q, r, 2.08767569878681e-09);
+  q = fma(q, r, 2.505210838544172e-08);
+  q = fma(q, r, 2.755731922398589e-07);
+  q = fma(q, r, 2.7557319223985893e-06);
+  q = fma(q, r, 2.48015873015873e-05);
+  q = fma(q, r, 0.0001984126984126984);
+  q = fma(q, r, 0.001388888888888889);
+  q = fma(q, r, 0.008333333333333333);
+  q = fma(q, r, 0.041666666666666664);
+  q = fma(q, r, 0.16666666666666666);
+  q = fma(q, r, 0.5);
+  q = fma(q, r, 1.0);
+  q = fma(q, r, 1.0);
+  return ldexp(q, -(int)n);
 }
 
+// Tiles of TPX pixels (64, or 32 when the FP64 b tile of 64 pixels would not
+// fit in LDS); thread groups of TPX lanes take landmarks kg, kg + NG, ...
+template <int TPX>
 __global__ __launch_bounds__(kBlock) void embed_kernel(Guide g, int64_t N, const float *__restrict__ c,
                                                        int r, const double *__restrict__ F, int r_eff,
                                                        double inv2s2, float *__restrict__ u) {
-  extern __shared__ float smem[];
+  constexpr int NG = kBlock / TPX;
+  extern __shared__ double smem_d[];
   const int D = g.D;
-  float *pt = smem;                          // [D][64]
-  float *bs = smem + (size_t)D * kTilePx;    // [r][64]
+  double *bs = smem_d;                                              // [r][TPX]
+  float *pt = reinterpret_cast<float *>(smem_d + (size_t)r * TPX);  // [D][TPX]
   const int tid = threadIdx.x;
-  const int px = tid & (kTilePx - 1);
-  const int kg = __builtin_amdgcn_readfirstlane(tid >> 6);
-  for (int64_t base = (int64_t)blockIdx.x * kTilePx; base < N; base += (int64_t)gridDim.x * kTilePx) {
+  const int px = tid & (TPX - 1);
+  const int kg = __builtin_amdgcn_readfirstlane(tid / TPX);
+  for (int64_t base = (int64_t)blockIdx.x * TPX; base < N; base += (int64_t)gridDim.x * TPX) {
     __syncthreads();
-    for (int e = tid; e < D * kTilePx; e += kBlock) {
-      const int d = e / kTilePx, q = e - d * kTilePx;
+    for (int e = tid; e < D * TPX; e += kBlock) {
+      const int d = e / TPX, q = e - d * TPX;
       const int64_t x = base + q;
       pt[e] = x < N ? guide_elem(g, x, d) : 0.0f;
     }
     __syncthreads();
-    for (int k = kg; k < r; k += 4) {
+    for (int k = kg; k < r; k += NG) {
       double acc = 0.0;
       for (int d = 0; d < D; ++d) {
-        const double t = (double)pt[d * kTilePx + px] - (double)c[k * D + d];
+        const double t = (double)pt[d * TPX + px] - (double)c[k * D + d];
         acc = fma(t, t, acc);
       }
-      bs[k * kTilePx + px] = exp_neg(acc * inv2s2);
+      bs[k * TPX + px] = exp_neg64(acc * inv2s2);
     }
     __syncthreads();
     const int64_t x = base + px;
     // four outputs per thread share each b read and give four independent chains
-    for (int kb = 0; kb < r_eff; kb += 16) {
+    for (int kb = 0; kb < r_eff; kb += 4 * NG) {
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
       int kk[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int v = kb + kg + 4 * q;
+        const int v = kb + kg + NG * q;
         kk[q] = v < r_eff ? v : r_eff - 1;
       }
       for (int k = 0; k < r; ++k) {
-        const double bv = (double)bs[k * kTilePx + px];
+        const double bv = bs[k * TPX + px];
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[q] = fma(F[k * r_eff + kk[q]], bv, acc[q]);
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        if (kb + kg + 4 * q < r_eff && x < N) u[(int64_t)(kb + kg + 4 * q) * N + x] = (float)acc[q];
+        if (kb + kg + NG * q < r_eff && x < N) u[(int64_t)(kb + kg + NG * q) * N + x] = (float)acc[q];
     }
   }
 }
@@ -158,13 +180,20 @@ hipError_t launch_embed(const Guide &g, const float *c, int r, const double *F, 
                         float *u, hipStream_t s) {
   const int64_t N = (int64_t)g.H * g.W;
   const double inv2s2 = isinf(sigma_r) ? 0.0 : 1.0 / (2.0 * sigma_r * sigma_r);
-  const size_t sm = sizeof(float) * ((size_t)g.D + r) * kTilePx;
-  int64_t blocks = (N + kTilePx - 1) / kTilePx;
+  auto lds = [&](int tpx) { return (sizeof(double) * r + sizeof(float) * g.D) * tpx; };
+  const bool wide = lds(64) <= 160 * 1024;
+  const int tpx = wide ? 64 : 32;
+  const size_t sm = lds(tpx);
+  int64_t blocks = (N + tpx - 1) / tpx;
   if (blocks > 16384) blocks = 16384;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(embed_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  const void *kern = wide ? reinterpret_cast<const void *>(embed_kernel<64>)
+                          : reinterpret_cast<const void *>(embed_kernel<32>);
+  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(embed_kernel, dim3((int)blocks), dim3(kBlock), sm, s, g, N, c, r, F, r_eff, inv2s2, u);
+  if (wide)
+    hipLaunchKernelGGL(embed_kernel<64>, dim3((int)blocks), dim3(kBlock), sm, s, g, N, c, r, F, r_eff, inv2s2, u);
+  else
+    hipLaunchKernelGGL(embed_kernel<32>, dim3((int)blocks), dim3(kBlock), sm, s, g, N, c, r, F, r_eff, inv2s2, u);
   return hipGetLastError();
 }
 

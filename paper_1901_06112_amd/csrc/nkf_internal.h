@@ -79,8 +79,11 @@ struct ConvProblem {
   float *out;         // [H, W, C]
   float *eta_out;     // nullable [N]
   float *eta_buf;     // [N] scratch used when C > 3 (eta pass, then channel chunks)
+  int box;            // box spatial kernel (all taps 1): sliding sums for C <= 3
 };
 hipError_t launch_conv_contract(const ConvProblem &pb, hipStream_t s);
+// Box-kernel form for C <= 3 (kernels_conv_box.hip).
+hipError_t launch_conv_contract_box(const ConvProblem &pb, hipStream_t s);
 
 // ---- kernels_bwd.hip --------------------------------------------------------
 // Backward passes (C <= 3).  mode 1: du_dir planes; 2: sigma_s partial sums

@@ -212,3 +212,17 @@ def test_full_size_color_blf_2048_sampled():
           flush=True)
     assert err <= TOL_255
     assert np.isfinite(g).all()
+
+
+@pytest.mark.parametrize("C,S,h,w", [(3, 0, 37, 45), (3, 5, 70, 101), (3, 16, 90, 66), (1, 3, 41, 77),
+                                     (1, 10, 100, 35)])
+def test_box_window_colour_and_gray(C, S, h, w):
+    """Box spatial kernel on self-guided images with 1 and 3 channels (the
+    sliding-sum form of the fused kernel), several radii, ragged tiles."""
+    f, prm = synth.workload("color_blf_256", h, w, seed=500 + S)
+    f = np.ascontiguousarray(f[:, :, :C])
+    P = f.reshape(-1, C).astype(np.float64)
+    c32 = _landmarks(P, 12, 3, 5)
+    g, eta, _ = _run_case(f, f, c32, 1.0, 30.0, S, spatial="box", guide="self")
+    go, etao = _oracle(f, f, c32, 1.0, 30.0, S, spatial="box")
+    _report_conditioned(f"box_C{C}_S{S}", f, f, c32, 1.0, 30.0, S, g, go, spatial="box")

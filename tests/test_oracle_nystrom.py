@@ -180,3 +180,61 @@ def test_guard_nonpositive_eta_outputs_input():
     g, eta = nystrom.nystrom_filter(f, p, c, 1.0, 1.0, 1, tau=0.0, return_eta=True)
     assert np.all(eta == 0)
     np.testing.assert_array_equal(g, f)
+
+
+def _perturbed_pipeline(f, p, c, sigma_s, sigma_r, S, spatial, delta, rng, perturb_b):
+    """Algorithm 1 in FP64 with centring f~ = f - f0, every stored
+    intermediate (u_k(x), u_k f~_c, the convolved planes, and b_j(x) when
+    ``perturb_b``) multiplied by an independent random factor
+    1 + delta * U(-1, 1)."""
+    H, W, C = f.shape
+    f0 = 0.5 * (f.min(axis=(0, 1)) + f.max(axis=(0, 1)))
+    fc = f - f0
+    w1 = exact.spatial_taps(sigma_s, S, spatial)
+    alpha, Wv = nystrom.landmark_eig(c, sigma_r)
+    Fm = Wv / np.sqrt(alpha)[None, :]
+
+    def pert(a):
+        return a * (1.0 + delta * rng.uniform(-1.0, 1.0, a.shape))
+
+    b = nystrom.cross_kernel_sr(c, p.reshape(H * W, -1), sigma_r)
+    if perturb_b:
+        b = pert(b)
+    U = pert(b @ Fm)
+    zeta = np.zeros((H, W, C))
+    eta = np.zeros((H, W))
+    for k in range(U.shape[1]):
+        uk = U[:, k].reshape(H, W)
+        zeta += uk[:, :, None] * pert(nystrom.conv_zero(pert(uk[:, :, None] * fc), w1))
+        eta += uk * pert(nystrom.conv_zero(uk, w1))
+    return zeta / eta[:, :, None] + f0
+
+
+@pytest.mark.parametrize("C,r,seed", [(3, 12, 1), (1, 12, 2), (1, 6, 3)])
+@pytest.mark.parametrize("perturb_b", [False, True])
+def test_storage_bound_covers_injected_perturbations(C, r, seed, perturb_b):
+    """The per-pixel storage bound B (first order) covers the change of g_hat
+    when each stored stage is perturbed by up to delta relative:
+    |dg| <= 4 delta B (5 delta B with b).  The 1-D guide with 12 landmarks is
+    ill-conditioned (Eq. (vk) cancels, |F| ~ 1e4): there a rounding of b is
+    amplified far beyond |u_k|, which only the cross-kernel form of B covers
+    (checked as well: the plain form is exceeded)."""
+    rng = np.random.default_rng(seed)
+    f, _ = synth.workload("color_blf_256", 24, 28, seed=600 + seed)
+    f = np.ascontiguousarray(f[:, :, :C]).astype(np.float64)
+    P = f.reshape(-1, C)
+    c, _, _ = kmeans.lloyd(P, P[seeding.distinct_indices(P.shape[0], r, seed)], 5)
+    B = nystrom.storage_error_bound(f, f, c, 1.5, 30.0, 3, cross_kernel_rounding=perturb_b)
+    g0 = _perturbed_pipeline(f, f, c, 1.5, 30.0, 3, "gaussian", 0.0, rng, perturb_b)
+    delta, stages = 1e-9, (5 if perturb_b else 4)
+    worst = 0.0
+    for _ in range(3):
+        g1 = _perturbed_pipeline(f, f, c, 1.5, 30.0, 3, "gaussian", delta, rng, perturb_b)
+        ok = np.isfinite(B)
+        worst = max(worst, float((np.abs(g1 - g0)[ok] / (stages * delta * B[ok])).max()))
+    assert worst <= 1.0, worst
+    if perturb_b and (C, r) == (1, 12):
+        Bp = nystrom.storage_error_bound(f, f, c, 1.5, 30.0, 3)
+        g1 = _perturbed_pipeline(f, f, c, 1.5, 30.0, 3, "gaussian", delta, rng, True)
+        ok = np.isfinite(Bp)
+        assert (np.abs(g1 - g0)[ok] / (stages * delta * Bp[ok])).max() > 1.0
