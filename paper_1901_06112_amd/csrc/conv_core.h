@@ -202,9 +202,12 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
   const int c_p = (tid / kTW) % NP;
   const int c_sub = tid / (kTW * NP);
 
-  float f0c[NCHAN > 0 ? NCHAN : 1];
+  float f0c[NCHAN > 0 ? NCHAN : 1], chm[NCHAN > 0 ? NCHAN : 1];
 #pragma unroll
-  for (int ch = 0; ch < NCHAN; ++ch) f0c[ch] = c0 + ch < C ? a.f0[c0 + ch] : 0.0f;
+  for (int ch = 0; ch < NCHAN; ++ch) {
+    f0c[ch] = c0 + ch < C ? a.f0[c0 + ch] : 0.0f;
+    chm[ch] = c0 + ch < C ? 1.0f : 0.0f;
+  }
 
   float acc[NCH_MAX][RUN];
 #pragma unroll
@@ -221,27 +224,33 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
   constexpr int NPOS = (RC * SW + BT - 1) / BT;
   constexpr int NCH1 = NCHAN > 0 ? NCHAN : 1;
   float pu[NPOS], pf[NPOS][NCH1], pb[NPOS];
+  // Loads use clamped in-bounds addresses and keep the raw values; the
+  // validity of each position goes into the bit mask inm and is applied when
+  // the values are stored, so the loads are issued without branches and
+  // nothing waits for them until the store one chunk later.
+  unsigned inm = 0;
   auto fetch = [&](int kk, int icc) {
-    const int ty0k = opaque(ty * TH);
+    const int ty0k = opaque(ty * TH);  // redefined per call: no address is hoisted out of the k loop
     const float *uk = a.u + (int64_t)kk * N;
-    const float *fk = opaque(MODE == MODE_ADJ ? a.ab : a.f);
     const int gy0 = ty0k - S + icc * RC;
+    inm = 0;
 #pragma unroll
     for (int q = 0; q < NPOS; ++q) {
       const int e = tid + q * BT;
       const int rr = e / SW, j = e - rr * SW;
       const int gy = gy0 + rr, gx = tx0 - S + j;
       const bool in = e < RC * SW && j < kTW + 2 * S && gy >= 0 && gy < H && gx >= 0 && gx < W;
-      pu[q] = in ? uk[gy * W + gx] : 0.0f;
+      inm |= (in ? 1u : 0u) << q;
+      const int64_t pix = in ? (int64_t)gy * W + gx : 0;
+      pu[q] = uk[pix];
       if constexpr (MODE == MODE_ADJ) {
-        const float *ap = fk + (int64_t)(in ? gy * W + gx : 0) * 4;
-        pb[q] = in ? ap[0] : 0.0f;
+        const float *ap = a.ab + pix * 4;
+        pb[q] = ap[0];
 #pragma unroll
-        for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = in ? ap[1 + ch] : 0.0f;
+        for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = ap[1 + ch];
       } else {
-        const float *fp = fk + (int64_t)(in ? gy * W + gx : 0) * C + c0;
 #pragma unroll
-        for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = (in && c0 + ch < C) ? fp[ch] - f0c[ch] : 0.0f;
+        for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = a.f[pix * C + (c0 + ch < C ? c0 + ch : C - 1)];
       }
     }
   };
@@ -258,13 +267,17 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
           const int e = tid + q * BT;
           if (e < RC * SW) {
             const int rr = e / SW, j = e - rr * SW;
+            const float uq = (inm >> q) & 1u ? pu[q] : 0.0f;  // zero outside the image
             if constexpr (MODE == MODE_ADJ)
-              stg[rr * SW + j] = pb[q] * pu[q];  // plane 0: beta u_k
+              stg[rr * SW + j] = pb[q] * uq;  // plane 0: beta u_k
             else
-              stg[UPL * K::PSTG + rr * SW + j] = pu[q];
+              stg[UPL * K::PSTG + rr * SW + j] = uq;
 #pragma unroll
-            for (int ch = 0; ch < NCHAN; ++ch)
-              stg[((HAS_E ? 1 : 0) + ch) * K::PSTG + rr * SW + j] = pf[q][ch] * pu[q];
+            for (int ch = 0; ch < NCHAN; ++ch) {
+              // forward modes: f~ = f - f0; channels past C are zero
+              const float fv = MODE == MODE_ADJ ? pf[q][ch] : (pf[q][ch] - f0c[ch]) * chm[ch];
+              stg[((HAS_E ? 1 : 0) + ch) * K::PSTG + rr * SW + j] = fv * uq;
+            }
           }
         }
         if (ic + 1 < nin)

@@ -22,8 +22,7 @@ hipError_t launch_S(ConvArgs a, hipStream_t s) {
   if (e != hipSuccess) return e;
   ConvArgs b = a;
   b.eta_out = nullptr;
-  if (C < 8) return launch_one<S, 4, false, 16, MODE_FWD>(b, s, 4, (C + 3) / 4);
-  return launch_one<S, 8, false, 16, MODE_FWD>(b, s, 8, (C + 7) / 8);
+  return launch_one<S, 4, false, 32, MODE_FWD, 512>(b, s, 4, (C + 3) / 4);
 }
 
 }  // namespace
