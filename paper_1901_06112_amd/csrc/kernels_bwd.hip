@@ -49,15 +49,19 @@ __global__ void ab_kernel(int64_t N, int C, const float *__restrict__ G, const f
 
 constexpr int kRBlock = 256;
 constexpr int kRTile = 64;
+constexpr int kRMaxJ = 16;   // landmarks per thread group (r <= 64)
+constexpr int kRS = kRTile + 1;  // padded row stride of the b and du_dir tiles
 
-// exp(-z) for z >= 0 in FP64.
-__device__ __forceinline__ double exp_neg64(double z) { return exp(-z); }
+typedef double double4_t __attribute__((ext_vector_type(4)));
 
 // Per 64-pixel tile: b (FP64), db = F du, dp, the sigma_r-through-b sum and
-// the block's share of R = sum_x b du_dir^T.  LDS layout (doubles unless
-// noted): bs[r][64], d2s[r][64], wj[r][64] (= db_j b_j / sigma_r^2), then the
-// block's R accumulator [r * r_eff], then floats pt[D][64], du[r_eff][64],
-// dud[r_eff][64].
+// the block's share of R = sum_x b du_dir^T.  Thread (px, kg) evaluates the
+// landmarks j = kg + 4 m in registers.  R runs on v_mfma_f64_16x16x4f64:
+// A = b^T (16 landmarks x 4 pixels), B = du_dir (4 pixels x 16 planes); wave w
+// keeps the output tiles w, w + 4, ... of R in registers for the whole launch
+// (lane l, element i holds R[16 jt + l/16 + 4 i][16 kt + l%16]).
+// LDS (doubles): bs[r][65], wj[r][64] (= db_j b_j / sigma_r^2), red[256];
+// floats: pt[D][64], dus[r_eff][64], duds[r_eff][65].
 __global__ __launch_bounds__(kRBlock) void reduce_kernel(Guide g, int64_t N, const float *__restrict__ c, int r,
                                                          const double *__restrict__ F, int r_eff, double sigma_r,
                                                          const float *__restrict__ du, const float *__restrict__ dud,
@@ -66,21 +70,23 @@ __global__ __launch_bounds__(kRBlock) void reduce_kernel(Guide g, int64_t N, con
   extern __shared__ double sm[];
   const int D = g.D;
   double *bs = sm;
-  double *d2s = bs + (size_t)r * kRTile;
-  double *wj = d2s + (size_t)r * kRTile;
-  double *Rl = wj + (size_t)r * kRTile;
-  const int nR = want_R ? r * r_eff : 0;
-  double *red = Rl + nR;                                     // [256]
+  double *wj = bs + (size_t)r * kRS;
+  double *red = wj + (size_t)r * kRTile;                     // [256]
   float *pt = reinterpret_cast<float *>(red + kRBlock);      // [D][64]
   float *dus = pt + (size_t)D * kRTile;                      // [r_eff][64]
-  float *duds = dus + (size_t)r_eff * kRTile;                // [r_eff][64]
-  const int tid = threadIdx.x;
+  float *duds = dus + (size_t)r_eff * kRTile;                // [r_eff][65]
+  const int tid = threadIdx.x, lane = tid & 63;
   const int px = tid & (kRTile - 1);
   const int kg = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nj = (r - kg + 3) / 4;  // landmarks j = kg + 4 m of this thread group
   const double inv2s2 = 1.0 / (2.0 * sigma_r * sigma_r);
   const double inv_s2 = 1.0 / (sigma_r * sigma_r);
   const double inv_s3 = inv_s2 / sigma_r;
-  for (int e = tid; e < nR; e += kRBlock) Rl[e] = 0.0;
+  const int ntj = (r + 15) / 16, ntk = (r_eff + 15) / 16;
+  const int nt = want_R ? ntj * ntk : 0;
+  double4_t racc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) racc[q] = double4_t{0.0, 0.0, 0.0, 0.0};
   double sr_acc = 0.0;
   for (int64_t base = (int64_t)blockIdx.x * kRTile; base < N; base += (int64_t)gridDim.x * kRTile) {
     __syncthreads();
@@ -93,23 +99,33 @@ __global__ __launch_bounds__(kRBlock) void reduce_kernel(Guide g, int64_t N, con
       const int k = e / kRTile, q = e - k * kRTile;
       const int64_t x = base + q;
       dus[e] = x < N ? du[(int64_t)k * N + x] : 0.0f;
-      duds[e] = x < N ? dud[(int64_t)k * N + x] : 0.0f;
+      duds[k * kRS + q] = x < N ? dud[(int64_t)k * N + x] : 0.0f;
     }
     __syncthreads();
     const bool valid = base + px < N;
-    for (int j = kg; j < r; j += 4) {
+    // db_j = sum_k F[j][k] du_k for this thread's landmarks: each du_k read once
+    double db[kRMaxJ];
+#pragma unroll
+    for (int m = 0; m < kRMaxJ; ++m) db[m] = 0.0;
+    for (int k = 0; k < r_eff; ++k) {
+      const double duk = (double)dus[k * kRTile + px];
+#pragma unroll
+      for (int m = 0; m < kRMaxJ; ++m)
+        if (m < nj) db[m] = fma(F[(kg + 4 * m) * r_eff + k], duk, db[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < kRMaxJ; ++m) {
+      if (m >= nj) continue;
+      const int j = kg + 4 * m;
       double d2 = 0.0;
       for (int d = 0; d < D; ++d) {
         const double t = (double)pt[d * kRTile + px] - (double)c[j * D + d];
         d2 = fma(t, t, d2);
       }
       const double b = valid ? exp_neg64(d2 * inv2s2) : 0.0;
-      double db = 0.0;
-      for (int k = 0; k < r_eff; ++k) db = fma(F[j * r_eff + k], (double)dus[k * kRTile + px], db);
-      bs[j * kRTile + px] = b;
-      d2s[j * kRTile + px] = d2;
-      wj[j * kRTile + px] = db * b * inv_s2;
-      sr_acc = fma(db * b, d2 * inv_s3, sr_acc);
+      bs[j * kRS + px] = b;
+      wj[j * kRTile + px] = db[m] * b * inv_s2;
+      sr_acc = fma(db[m] * b, d2 * inv_s3, sr_acc);
     }
     __syncthreads();
     // dp_d = -sum_j w_j (p_d - c_jd)
@@ -122,12 +138,19 @@ __global__ __launch_bounds__(kRBlock) void reduce_kernel(Guide g, int64_t N, con
         if (x < N) dp[x * D + d] = (float)(-s);
       }
     }
-    // R[j][k] += sum_px b_j du_dir_k  (each entry owned by one thread)
-    for (int e = tid; e < nR; e += kRBlock) {
-      const int j = e / r_eff, k = e - j * r_eff;
-      double s = Rl[e];
-      for (int q = 0; q < kRTile; ++q) s = fma(bs[j * kRTile + q], (double)duds[k * kRTile + q], s);
-      Rl[e] = s;
+    // R tiles on the matrix cores, 4 pixels per step
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = kg + 4 * q;
+      if (t >= nt) break;
+      const int jt = t / ntk, kt = t - jt * ntk;
+      const int ja = 16 * jt + (lane & 15), kb = 16 * kt + (lane & 15);
+      for (int s4 = 0; s4 < kRTile / 4; ++s4) {
+        const int pq = 4 * s4 + (lane >> 4);
+        const double av = ja < r ? bs[ja * kRS + pq] : 0.0;
+        const double bv = kb < r_eff ? (double)duds[kb * kRS + pq] : 0.0;
+        racc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, racc[q], 0, 0, 0);
+      }
     }
   }
   __syncthreads();
@@ -137,9 +160,21 @@ __global__ __launch_bounds__(kRBlock) void reduce_kernel(Guide g, int64_t N, con
     if (tid < h) red[tid] += red[tid + h];
     __syncthreads();
   }
+  const int nR = want_R ? r * r_eff : 0;
   double *dst = partials + (size_t)blockIdx.x * (nR + 1);
   if (tid == 0) dst[0] = red[0];
-  for (int e = tid; e < nR; e += kRBlock) dst[1 + e] = Rl[e];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int t = kg + 4 * q;
+    if (t >= nt) break;
+    const int jt = t / ntk, kt = t - jt * ntk;
+    const int k = 16 * kt + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int j = 16 * jt + (lane >> 4) + 4 * i;
+      if (j < r && k < r_eff) dst[1 + j * r_eff + k] = racc[q][i];
+    }
+  }
 }
 
 template <int MODE>
@@ -147,7 +182,7 @@ hipError_t launch_mode(ConvArgs a, int S, hipStream_t s, int *nblocks) {
   switch (S) {
 #define NKF_CASE(SV) \
   case SV:           \
-    return launch_one<SV, 4, true, 16, MODE>(a, s, 3, 1, 512, nblocks);
+    return launch_one<SV, 4, true, 32, MODE, 512>(a, s, 3, 1, 512, nblocks);
     NKF_CASE(0) NKF_CASE(1) NKF_CASE(2) NKF_CASE(3) NKF_CASE(4) NKF_CASE(5) NKF_CASE(6) NKF_CASE(7)
     NKF_CASE(8) NKF_CASE(9) NKF_CASE(10) NKF_CASE(11) NKF_CASE(12) NKF_CASE(13) NKF_CASE(14)
     NKF_CASE(15) NKF_CASE(16)
@@ -160,7 +195,7 @@ hipError_t launch_mode(ConvArgs a, int S, hipStream_t s, int *nblocks) {
 }  // namespace
 
 int bwd_conv_max_blocks(int H, int W) {
-  // launch_one uses at least one 16-row chunk per tile
+  // launch_one uses at least one 32-row chunk per tile (bound kept at 16 rows)
   return ((W + conv::kTW - 1) / conv::kTW) * ((H + 15) / 16);
 }
 
@@ -210,8 +245,9 @@ int bwd_reduce_blocks(int64_t N) {
 }
 
 size_t bwd_reduce_lds(int r, int r_eff, int D, int want_R) {
-  return sizeof(double) * (3 * (size_t)r * kRTile + (want_R ? (size_t)r * r_eff : 0) + kRBlock) +
-         sizeof(float) * ((size_t)D + 2 * (size_t)r_eff) * kRTile;
+  (void)want_R;
+  return sizeof(double) * ((size_t)r * kRS + (size_t)r * kRTile + kRBlock) +
+         sizeof(float) * ((size_t)D * kRTile + (size_t)r_eff * kRTile + (size_t)r_eff * kRS);
 }
 
 hipError_t launch_bwd_reduce(const Guide &g, const float *c, int r, const double *F, int r_eff, double sigma_r,

@@ -21,34 +21,6 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// exp(-z) for z >= 0 to FP64 accuracy: z = n ln2 - r with n = round(z / ln2)
-// and |r| <= ln2 / 2, ln2 split in two parts (the high part has 21
-// significant bits, so n * ln2_hi is exact for the n that occur); exp(r) from
-// its Taylor polynomial of degree 13 (truncation below 5e-18 relative), then
-// a scale by 2^-n.  FP64 accuracy matters when F has large entries: the mix
-// u = F^T b cancels, and an FP32 rounding of each b_j would move u_k by up to
-// eps sum_j |F_jk| b_j instead of eps |u_k|.
-__device__ __forceinline__ double exp_neg64(double z) {
-  if (!(z < 745.0)) return 0.0;
-  const double n = rint(z * 1.4426950408889634);
-  const double r = (n * 0.6931467056274414 - z) + n * 4.7493250390316726e-07;
-  double q = 1.6059043836821613e-10;  // 1 / 13!
-  q = fma(q, r, 2.08767569878681e-09);
-  q = fma(q, r, 2.505210838544172e-08);
-  q = fma(q, r, 2.755731922398589e-07);
-  q = fma(q, r, 2.7557319223985893e-06);
-  q = fma(q, r, 2.48015873015873e-05);
-  q = fma(q, r, 0.0001984126984126984);
-  q = fma(q, r, 0.001388888888888889);
-  q = fma(q, r, 0.008333333333333333);
-  q = fma(q, r, 0.041666666666666664);
-  q = fma(q, r, 0.16666666666666666);
-  q = fma(q, r, 0.5);
-  q = fma(q, r, 1.0);
-  q = fma(q, r, 1.0);
-  return ldexp(q, -(int)n);
-}
-
 // Tiles of TPX pixels (64, or 32 when the FP64 b tile of 64 pixels would not
 // fit in LDS); thread groups of TPX lanes take landmarks kg, kg + NG, ...
 template <int TPX>
