@@ -229,6 +229,15 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
   // the values are stored, so the loads are issued without branches and
   // nothing waits for them until the store one chunk later.
   unsigned inm = 0;
+  // per staged position q: column validity (fixed for the thread) as a bit mask
+  unsigned colm = 0;
+#pragma unroll
+  for (int q = 0; q < NPOS; ++q) {
+    const int e = tid + q * BT;
+    const int rr = e / SW, j = e - rr * SW;
+    const int gx = tx0 - S + j;
+    colm |= (e < RC * SW && j < kTW + 2 * S && gx >= 0 && gx < W ? 1u : 0u) << q;
+  }
   auto fetch = [&](int kk, int icc) {
     const int ty0k = opaque(ty * TH);  // redefined per call: no address is hoisted out of the k loop
     const float *uk = a.u + (int64_t)kk * N;
@@ -238,19 +247,22 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
     for (int q = 0; q < NPOS; ++q) {
       const int e = tid + q * BT;
       const int rr = e / SW, j = e - rr * SW;
-      const int gy = gy0 + rr, gx = tx0 - S + j;
-      const bool in = e < RC * SW && j < kTW + 2 * S && gy >= 0 && gy < H && gx >= 0 && gx < W;
+      // H * W <= 2^31, so a valid pixel index fits in 32 bits; invalid
+      // positions read pixel 0 and are masked at the store
+      const unsigned gy = (unsigned)(gy0 + rr), gx = (unsigned)(tx0 - S + j);
+      const bool in = ((colm >> q) & 1u) && gy < (unsigned)H;
       inm |= (in ? 1u : 0u) << q;
-      const int64_t pix = in ? (int64_t)gy * W + gx : 0;
+      const unsigned pix = in ? gy * (unsigned)W + gx : 0u;
       pu[q] = uk[pix];
       if constexpr (MODE == MODE_ADJ) {
-        const float *ap = a.ab + pix * 4;
+        const float *ap = a.ab + (size_t)pix * 4;
         pb[q] = ap[0];
 #pragma unroll
         for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = ap[1 + ch];
       } else {
+        const float *fp = a.f + (size_t)pix * C;
 #pragma unroll
-        for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = a.f[pix * C + (c0 + ch < C ? c0 + ch : C - 1)];
+        for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = fp[c0 + ch < C ? c0 + ch : C - 1];
       }
     }
   };

@@ -38,17 +38,25 @@ __global__ void gather_kernel(Guide g, const int64_t *__restrict__ idx, int r,
 // Block b writes its per-cluster sums to partials[b][r][D+1] (every entry,
 // zeros included); the update kernel reduces the partials in block order.
 // Distances in the GEMM form |c|^2 - 2 p.c (|p|^2 is common to all clusters
-// and drops out of the argmin); each lane adds its pixel to the block's FP64
-// accumulators with native LDS atomics.
+// and drops out of the argmin); each lane adds its pixel to one of ncopy
+// FP64 accumulator sets in LDS (thread % ncopy) with native LDS atomics:
+// neighbouring pixels mostly share a cluster, and one set would serialise a
+// wave's atomics on the same words.  The sets (stride padded by one double so
+// that they start on different banks) are summed in a fixed order at the end.
+constexpr int kSmallCopiesMax = 32;
+constexpr size_t kSmallCopiesLds = 64 * 1024;
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void assign_small_kernel(const float *__restrict__ P, int64_t N,
                                                               const float *__restrict__ c, int r,
                                                               double *__restrict__ partials,
-                                                              int *__restrict__ labels) {
+                                                              int *__restrict__ labels, int ncopy) {
   constexpr int DS = D + 1;  // stored per cluster: -2 c (D values), |c|^2
   __shared__ __attribute__((aligned(16))) float sc[kMaxLandmarks * DS];
-  __shared__ double sacc[kMaxLandmarks * (D + 1)];
+  extern __shared__ double sacc_all[];  // [ncopy][r (D+1) + 1]
   const int tid = threadIdx.x;
+  const int cstride = r * (D + 1) + 1;
+  double *sacc = sacc_all + (tid % ncopy) * cstride;
   for (int k = tid; k < r; k += kBlock) {
     float n2 = 0.0f;
 #pragma unroll
@@ -59,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void assign_small_kernel(const float *__res
     }
     sc[k * DS + D] = n2;
   }
-  for (int i = tid; i < r * (D + 1); i += kBlock) sacc[i] = 0.0;
+  for (int i = tid; i < ncopy * cstride; i += kBlock) sacc_all[i] = 0.0;
   __syncthreads();
   // two pixels per thread per pass share each centroid read and interleave
   // two independent distance chains
@@ -107,7 +115,11 @@ __global__ __launch_bounds__(kBlock) void assign_small_kernel(const float *__res
   }
   __syncthreads();
   double *dst = partials + (size_t)blockIdx.x * r * (D + 1);
-  for (int i = tid; i < r * (D + 1); i += kBlock) dst[i] = sacc[i];
+  for (int i = tid; i < r * (D + 1); i += kBlock) {
+    double s = 0.0;
+    for (int q = 0; q < ncopy; ++q) s += sacc_all[q * cstride + i];
+    dst[i] = s;
+  }
 }
 
 // ---- generic D: labels from a pixel tile in LDS ----------------------------
@@ -304,7 +316,15 @@ hipError_t launch_small(const Guide &g, const float *c, int r, double *partials,
   const int64_t N = (int64_t)g.H * g.W;
   const float *P = g.kind == GUIDE_EXPLICIT ? g.p : g.f;
   *nparts = grid_for(N, kBlock * 8, kMaxPartials);
-  hipLaunchKernelGGL(assign_small_kernel<D>, dim3(*nparts), dim3(kBlock), 0, s, P, N, c, r, partials, labels);
+  const size_t set_bytes = sizeof(double) * ((size_t)r * (D + 1) + 1);
+  int ncopy = (int)(kSmallCopiesLds / set_bytes);
+  ncopy = ncopy < 1 ? 1 : (ncopy > kSmallCopiesMax ? kSmallCopiesMax : ncopy);
+  const size_t sm = set_bytes * ncopy;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(assign_small_kernel<D>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(assign_small_kernel<D>, dim3(*nparts), dim3(kBlock), sm, s, P, N, c, r, partials, labels,
+                     ncopy);
   return hipGetLastError();
 }
 
