@@ -53,23 +53,31 @@ __global__ __launch_bounds__(kBlock) void embed_kernel(Guide g, int64_t N, const
     }
     __syncthreads();
     const int64_t x = base + px;
-    // four outputs per thread share each b read and give four independent chains
-    for (int kb = 0; kb < r_eff; kb += 4 * NG) {
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      int kk[4];
+    // thread group kg mixes output planes kb .. kb+7 (kb = 8 kg, 8 kg + 8 NG, ...):
+    // one b read and one contiguous row segment of F per k feed 8 FMA chains
+    for (int kb = 8 * kg; kb < r_eff; kb += 8 * NG) {
+      double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      if (kb + 8 <= r_eff) {
+        for (int k = 0; k < r; ++k) {
+          const double bv = bs[k * TPX + px];
+          const double *Fr = F + (size_t)k * r_eff + kb;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int v = kb + kg + NG * q;
-        kk[q] = v < r_eff ? v : r_eff - 1;
+          for (int q = 0; q < 8; ++q) acc[q] = fma(Fr[q], bv, acc[q]);
+        }
+      } else {
+        for (int k = 0; k < r; ++k) {
+          const double bv = bs[k * TPX + px];
+          const double *Fr = F + (size_t)k * r_eff + kb;
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (kb + q < r_eff) acc[q] = fma(Fr[q], bv, acc[q]);
+        }
       }
-      for (int k = 0; k < r; ++k) {
-        const double bv = bs[k * TPX + px];
+      if (x < N) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = fma(F[k * r_eff + kk[q]], bv, acc[q]);
+        for (int q = 0; q < 8; ++q)
+          if (kb + q < r_eff) u[(int64_t)(kb + q) * N + x] = (float)acc[q];
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (kb + kg + NG * q < r_eff && x < N) u[(int64_t)(kb + kg + NG * q) * N + x] = (float)acc[q];
     }
   }
 }
