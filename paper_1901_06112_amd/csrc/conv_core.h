@@ -56,6 +56,7 @@ struct ConvArgs {
   int tiles_x, tiles_y, nblocks;
   int ch_per_block; // channel planes per block
   const float *f;
+  const float *fpl;  // nullable: f as planes [C][N] (channel loads coalesced across pixels)
   const float *f0;
   const float *u;
   float *out;
@@ -238,6 +239,8 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
     const int gx = tx0 - S + j;
     colm |= (e < RC * SW && j < kTW + 2 * S && gx >= 0 && gx < W ? 1u : 0u) << q;
   }
+  // channel chunks of 4 within C % 4 == 0 (and a 16-byte aligned f) load as float4
+  const bool vec4 = NCHAN == 4 && C % 4 == 0 && c0 + 4 <= C && (reinterpret_cast<uintptr_t>(a.f) & 15) == 0;
   auto fetch = [&](int kk, int icc) {
     const int ty0k = opaque(ty * TH);  // redefined per call: no address is hoisted out of the k loop
     const float *uk = a.u + (int64_t)kk * N;
@@ -260,7 +263,21 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
 #pragma unroll
         for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = ap[1 + ch];
       } else {
+        if (a.fpl) {
+          // planar f: each channel load is contiguous across the lanes
+#pragma unroll
+          for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = a.fpl[(size_t)(c0 + ch < C ? c0 + ch : C - 1) * N + pix];
+          continue;
+        }
         const float *fp = a.f + (size_t)pix * C;
+        if constexpr (NCHAN == 4) {
+          if (vec4) {
+            // four whole channels of a pixel in one 16-byte load
+            const float4 v = *reinterpret_cast<const float4 *>(fp + c0);
+            pf[q][0] = v.x, pf[q][1] = v.y, pf[q][2] = v.z, pf[q][3] = v.w;
+            continue;
+          }
+        }
 #pragma unroll
         for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = fp[c0 + ch < C ? c0 + ch : C - 1];
       }

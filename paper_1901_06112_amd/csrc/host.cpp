@@ -332,6 +332,7 @@ struct FwdBufs {
   unsigned *mm;
   float *u;
   float *eta_buf;
+  float *f_planar;  // [C][N] when C > 3
   float *mu;     // [D] centring of the 16-bit distance path
   float *F32;    // [r][r_eff] FP32 factor for the MFMA mix
   double *mpart; // partial sums of the centring offsets
@@ -343,6 +344,7 @@ void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r = kMa
   b.mm = cv.take<unsigned>(2 * (size_t)rs.C);
   b.u = cv.take<float>((size_t)r_eff * rs.N);
   b.eta_buf = cv.take<float>(rs.C > 3 ? rs.N : 1);
+  b.f_planar = cv.take<float>(rs.C > 3 ? (size_t)rs.C * rs.N : 1);
   b.mu = cv.take<float>(rs.D);
   b.F32 = cv.take<float>((size_t)r * r_eff);
   b.mpart = cv.take<double>(guide_mean_scratch_doubles(rs.g));
@@ -376,6 +378,7 @@ nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, cons
   pb.out = out;
   pb.eta_out = eta_out;
   pb.eta_buf = b.eta_buf;
+  pb.f_planar = b.f_planar;
   StageTimer tm(ctx, NKF_STAGE_CONV);
   HIP_TRY(ctx, launch_conv_contract(pb, ctx->stream));
   return NKF_OK;

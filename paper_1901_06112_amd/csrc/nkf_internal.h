@@ -79,6 +79,7 @@ struct ConvProblem {
   float *out;         // [H, W, C]
   float *eta_out;     // nullable [N]
   float *eta_buf;     // [N] scratch used when C > 3 (eta pass, then channel chunks)
+  float *f_planar;    // [C][N] scratch used when C > 3 (f transposed to planes)
   int box;            // box spatial kernel (all taps 1): sliding sums for C <= 3
 };
 hipError_t launch_conv_contract(const ConvProblem &pb, hipStream_t s);
