@@ -530,7 +530,9 @@ hipError_t launch_one(ConvArgs a, hipStream_t s, int ch_per_block, int nchunks_c
   using K = Cfg<S, NP, HAS_E, RC, MODE, BT>;
   a.ch_per_block = ch_per_block;
   a.tiles_x = (a.W + kTW - 1) / kTW;
-  // largest chunk count (<= NCH_MAX) that still gives >= min_blocks blocks
+  // largest chunk count (<= NCH_MAX) that still gives >= min_blocks blocks;
+  // 512-thread blocks hold a whole CU's LDS, so one block per CU fills the chip
+  if (BT == 512 && min_blocks > 256) min_blocks = 256;
   int nch = K::NCH_MAX;
   auto blocks = [&](int n) {
     const int th = n * RC;
