@@ -215,9 +215,11 @@ def leg_diff(steps, warmup):
             nkf.filter_landmarks(ft, c, F, **kw)
 
     def fwdbwd():
+        # as the autograd function runs it: the backward reuses the forward's
+        # output and eta_hat, and recomputes the embedding
         for ft, c, Q, al, F, reff, G in imgs:
-            nkf.filter_landmarks(ft, c, F, **kw)
-            nkf.filter_backward(ft, c, Q, al, reff, G, **kw)
+            out, eta = nkf.filter_landmarks(ft, c, F, return_eta=True, **kw)
+            nkf.filter_backward(ft, c, Q, al, reff, G, out=out, eta=eta, **kw)
 
     ms_f, _, _ = _timed(fwd, steps, warmup)
     ms_b, _, _ = _timed(fwdbwd, steps, warmup)

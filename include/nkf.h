@@ -158,14 +158,19 @@ nkf_status nkf_filter_landmarks(nkf_ctx *ctx, int H, int W, int C, const float *
  * Outputs (each nullable): grad_f [H, W, C], grad_p [H, W, D] (EXPLICIT or
  * SELF guide; for SELF the caller adds grad_f and grad_p to get the total),
  * grad_sigma_r_host, grad_sigma_s_host (host doubles; sigma_s only for the
- * Gaussian window).  Recomputes the embedding and convolutions instead of
- * storing r_eff (C+1) planes.  Synchronises the stream once (the r x r_eff
- * reduction for the sigma_r gradient is finished on the host in FP64). */
+ * Gaussian window).  Recomputes the embedding instead of storing r_eff (C+1)
+ * planes.  out_fwd [H, W, C] and eta_fwd [H, W] (both nullable, device) are
+ * the out and eta_out of the nkf_filter_landmarks call with the same
+ * arguments; when both are given the forward convolutions are not repeated
+ * (the caller guarantees they match), otherwise they are recomputed.
+ * Synchronises the stream (the r x r_eff reduction for the sigma_r gradient
+ * is finished on the host in FP64). */
 nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f, int D,
                                const float *p, const nkf_params *prm, const float *centroids,
                                const double *eigvecs_host, const double *eigvals_host, int r_eff,
                                const float *grad_out, float *grad_f, float *grad_p,
-                               double *grad_sigma_r_host, double *grad_sigma_s_host);
+                               double *grad_sigma_r_host, double *grad_sigma_s_host,
+                               const float *out_fwd, const float *eta_fwd);
 
 /* Stage timing.  When enabled, every stage a call enqueues is bracketed by
  * HIP events on the context's stream (host-side stages by the host clock).

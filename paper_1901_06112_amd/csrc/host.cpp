@@ -360,7 +360,7 @@ void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r = kMa
 }
 
 nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, const float *c, const double *F,
-                   int r_eff, float *out, float *eta_out, const FwdBufs &b) {
+                   int r_eff, float *out, float *eta_out, const FwdBufs &b, bool conv = true) {
   {
     StageTimer tm(ctx, NKF_STAGE_EMBED);
     HIP_TRY(ctx, launch_center(rs.g.f, rs.N, rs.C, prm->center, b.f0, b.mm, ctx->stream));
@@ -372,6 +372,7 @@ nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, cons
       HIP_TRY(ctx, launch_embed(rs.g, c, prm->r, F, r_eff, prm->sigma_r, b.u, ctx->stream));
     }
   }
+  if (!conv) return NKF_OK;
   ConvProblem pb{};
   pb.H = rs.H;
   pb.W = rs.W;
@@ -685,7 +686,8 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
 nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, const float *p,
                                const nkf_params *prm, const float *centroids, const double *eigvecs_host,
                                const double *eigvals_host, int r_eff, const float *grad_out, float *grad_f,
-                               float *grad_p, double *grad_sigma_r_host, double *grad_sigma_s_host) {
+                               float *grad_p, double *grad_sigma_r_host, double *grad_sigma_s_host,
+                               const float *out_fwd, const float *eta_fwd) {
   Resolved rs;
   nkf_status st = validate(ctx, H, W, C, f, D, p, prm, rs);
   if (st != NKF_OK) return st;
@@ -749,8 +751,10 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
   {
     StageTimer tm(ctx, NKF_STAGE_BACKWARD);
     HIP_TRY(ctx, hipMemcpyAsync(Fd, hF, sizeof(double) * r * r_eff, hipMemcpyHostToDevice, ctx->stream));
-    if ((st = run_fwd(ctx, rs, prm, centroids, Fd, r_eff, out_s, eta_s, fb)) != NKF_OK) return st;
-    HIP_TRY(ctx, launch_bwd_ab(rs.N, C, grad_out, out_s, eta_s, fb.f0, ab, ctx->stream));
+    const bool have_fwd = out_fwd && eta_fwd;
+    if ((st = run_fwd(ctx, rs, prm, centroids, Fd, r_eff, out_s, eta_s, fb, !have_fwd)) != NKF_OK) return st;
+    const float *outv = have_fwd ? out_fwd : out_s, *etav = have_fwd ? eta_fwd : eta_s;
+    HIP_TRY(ctx, launch_bwd_ab(rs.N, C, grad_out, outv, etav, fb.f0, ab, ctx->stream));
     BwdConvProblem bp{};
     bp.H = H;
     bp.W = W;
@@ -762,7 +766,7 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
     bp.u = fb.u;
     bp.ab = ab;
     bp.G = grad_out;
-    bp.eta = eta_s;
+    bp.eta = etav;
     bp.wr = rs.taps;
     bp.wc = rs.taps;
     bp.mode = 1;

@@ -77,7 +77,7 @@ def load_library(path=LIB_PATH):
             "nkf_kmeans_iterate": (I, [P, I, I, I, P, I, P, PP, P, I, P]),
             "nkf_landmark_factor": (I, [I, I, P, D, D, P, P, P, ct.POINTER(I)]),
             "nkf_filter_landmarks": (I, [P, I, I, I, P, I, P, PP, P, P, I, P, P]),
-            "nkf_filter_backward": (I, [P, I, I, I, P, I, P, PP, P, P, P, I, P, P, P, P, P]),
+            "nkf_filter_backward": (I, [P, I, I, I, P, I, P, PP, P, P, P, I, P, P, P, P, P, P, P]),
             "nkf_seed_indices": (I, [ct.c_int64, I, U64, P]),
             "nkf_spatial_taps": (I, [I, D, I, ct.POINTER(I), P]),
             "nkf_enable_timing": (I, [P, I]),
@@ -319,10 +319,12 @@ def stage_times(t, reset=True):
 
 def filter_backward(f, centroids, Q, alpha, r_eff, grad_out, p=None, *, sigma_s=3.0, sigma_r=30.0,
                     radius=-1, spatial="gaussian", guide=None, patch_radius=3, center=None,
-                    need_f=True, need_p=True, need_sigma_r=True, need_sigma_s=True):
+                    need_f=True, need_p=True, need_sigma_r=True, need_sigma_s=True, out=None, eta=None):
     """Gradients of L with dL/dg = grad_out through the filter with given
     landmarks (held fixed).  Q [r, r] / alpha [r] are the eigenpairs returned
-    by landmark_factor for the same landmarks and sigma_r.  Returns
+    by landmark_factor for the same landmarks and sigma_r.  ``out`` / ``eta``
+    (optional) are the forward's output and eta_hat for the same arguments;
+    given both, the forward convolutions are not repeated.  Returns
     (df, dp, dsigma_r, dsigma_s); entries not requested are None.  dp is the
     gradient w.r.t. the guide (for guide='self' add it to df)."""
     if guide is None:
@@ -344,7 +346,9 @@ def filter_backward(f, centroids, Q, alpha, r_eff, grad_out, p=None, *, sigma_s=
         ctx, H, W, C, _dev_f32(f, "f"), D, _dev_f32(p, "p") if guide == "explicit" else ct.c_void_p(0),
         ct.byref(prm), _dev_f32(centroids, "centroids"), Qh.ctypes.data_as(ct.c_void_p),
         ah.ctypes.data_as(ct.c_void_p), int(r_eff), _dev_f32(go, "grad_out"), _ptr(df), _ptr(dp),
-        ct.byref(dsr) if need_sigma_r else None, ct.byref(dss) if need_sigma_s else None), ctx)
+        ct.byref(dsr) if need_sigma_r else None, ct.byref(dss) if need_sigma_s else None,
+        _dev_f32(out, "out") if out is not None else ct.c_void_p(0),
+        _dev_f32(eta, "eta") if eta is not None else ct.c_void_p(0)), ctx)
     return (df, dp, dsr.value if need_sigma_r else None, dss.value if need_sigma_s else None)
 
 
@@ -355,17 +359,18 @@ class NystromFilter(torch.autograd.Function):
     f [H, W, C] float32 CUDA; p [H, W, D] or None (the image guides itself);
     sigma_r, sigma_s 0-d float64 tensors (or floats); landmarks [r, D] float32
     CUDA.  Gradients flow to f, p, sigma_r and sigma_s; the landmarks and the
-    window radius are held fixed.  The backward recomputes the embedding and
-    the convolutions instead of storing them."""
+    window radius are held fixed.  The forward keeps its output and eta_hat
+    (C + 1 planes); the backward recomputes the embedding instead of storing
+    the r_eff (C + 1) convolution planes."""
 
     @staticmethod
     def forward(ctx, f, p, sigma_r, sigma_s, landmarks, radius=-1, spatial="gaussian", center=None, tau=1e-10):
         sr = float(sigma_r)
         ss = float(sigma_s)
         Q, al, F, reff = landmark_factor(landmarks, sr, tau)
-        out = filter_landmarks(f, landmarks, F, p, sigma_s=ss, sigma_r=sr, radius=radius, spatial=spatial,
-                               center=center)
-        ctx.save_for_backward(f, p if p is not None else f, landmarks)
+        out, eta = filter_landmarks(f, landmarks, F, p, sigma_s=ss, sigma_r=sr, radius=radius, spatial=spatial,
+                                    center=center, return_eta=True)
+        ctx.save_for_backward(f, p if p is not None else f, landmarks, out, eta)
         ctx.self_guided = p is None
         ctx.factor = (Q, al, reff)
         ctx.cfg = dict(sigma_s=ss, sigma_r=sr, radius=radius, spatial=spatial, center=center)
@@ -374,7 +379,7 @@ class NystromFilter(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, G):
-        f, p, landmarks = ctx.saved_tensors
+        f, p, landmarks, out, eta = ctx.saved_tensors
         Q, al, reff = ctx.factor
         need_p = ctx.self_guided or ctx.needs_input_grad[1]
         sr_t, ss_t = ctx.sigma_types
@@ -382,7 +387,7 @@ class NystromFilter(torch.autograd.Function):
         need_ss = ctx.needs_input_grad[3] and ctx.cfg["spatial"] == "gaussian"
         df, dp, dsr, dss = filter_backward(
             f, landmarks, Q, al, reff, G, None if ctx.self_guided else p, need_f=True, need_p=need_p,
-            need_sigma_r=need_sr, need_sigma_s=need_ss, **ctx.cfg)
+            need_sigma_r=need_sr, need_sigma_s=need_ss, out=out, eta=eta, **ctx.cfg)
         if ctx.self_guided:
             df = df + dp
             dp = None

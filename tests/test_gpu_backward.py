@@ -141,3 +141,21 @@ def test_unsupported_backward_requests():
     with pytest.raises(nkf.NkfError) as ei:
         nkf.filter_backward(f, c, Q, al, reff, torch.ones_like(f), sigma_s=2.0, sigma_r=30.0, radius=3)
     assert ei.value.status == nkf.NKF_ERR_UNSUPPORTED
+
+
+def test_forward_outputs_reused_bitwise():
+    """The backward fed the forward's own output and eta_hat (no convolution
+    recompute) gives bit-identical gradients to the recomputing backward."""
+    nkf = _nkf()
+    f, c32, G = _case(57, 49, 16, seed=21)
+    ss, sr, S = 2.0, 30.0, 6
+    Q, al, F, reff = nkf.landmark_factor(c32.astype(np.float64), sr)
+    ft = torch.from_numpy(f).cuda()
+    ct_ = torch.from_numpy(c32).cuda()
+    Gt = torch.from_numpy(G).cuda()
+    out, eta = nkf.filter_landmarks(ft, ct_, F, sigma_s=ss, sigma_r=sr, radius=S, return_eta=True)
+    a = nkf.filter_backward(ft, ct_, Q, al, reff, Gt, sigma_s=ss, sigma_r=sr, radius=S)
+    b = nkf.filter_backward(ft, ct_, Q, al, reff, Gt, sigma_s=ss, sigma_r=sr, radius=S, out=out, eta=eta)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert a[2] == b[2] and a[3] == b[3]
