@@ -14,8 +14,10 @@
 // beta = -sum_c G_c g~_c / eta per pixel (see kernels_bwd.hip):
 //   MODE_DUDIR  du_dir_k(x) = beta E_k(x) + sum_c a_c Z_kc(x)        -> HBM
 //   MODE_SIGS   sum_x u_k(x) [beta (w' * u_k) + sum_c a_c (w' * u_k f~_c)]
-//               for one separable term of dw/dsigma_s (row and column taps
-//               given separately)                                   -> partials
+//               with w' = dw/dsigma_s = w1' (x) w1 + w1 (x) w1' (taps w1 in
+//               wr, w1' in wc): the row pass keeps both w1 and w1' rows in two
+//               rings, the column pass takes w1' over the first and w1 over
+//               the second                                          -> partials
 //   MODE_ADJ    Yb_k = w * (beta u_k), Ya_kc = w * (a_c u_k):
 //               du_k(x) = du_dir_k(x) + Yb_k(x) + sum_c f~_c(x) Ya_kc(x) -> HBM
 //               df_c(x) = sum_k u_k(x) Ya_kc(x)                  -> registers
@@ -101,7 +103,7 @@ struct Cfg {
   static constexpr int UPL = RAWU_SEP ? NP : 0;               // index of the raw-u staged plane
   static constexpr int WIN = ((RUN + 2 * S + 3) / 4) * 4;
   static constexpr int STG = NPU * PSTG;                      // staging floats
-  static constexpr int RINGF = NP * PR;                       // convolved-row ring floats
+  static constexpr int RINGF = NP * PR * (MODE == MODE_SIGS ? 2 : 1);  // convolved-row ring floats
   static constexpr int URINGF = FWD ? RINGX * kTWP : 0;       // raw-u ring floats (forward)
   static constexpr int EXF = (MODE == MODE_DUDIR || MODE == MODE_ADJ) ? NP * RC * kTW : 0;
   static constexpr int ETAB = FWD ? NCH_MAX * RC * kTW : 0;   // epilogue eta tile
@@ -339,6 +341,16 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
             dst[i] = sf;
             if (mirror) dst[RING * kTWP + i] = sf;
           }
+          if constexpr (MODE == MODE_SIGS) {
+            // the w1' rows, in the second ring
+            float *dst2 = dst + NP * K::PR;
+#pragma unroll
+            for (int i = 0; i < RUN; ++i) {
+              const float sf = (float)fir_sym<S>(a.wc, &win[i]);
+              dst2[i] = sf;
+              if (mirror) dst2[RING * kTWP + i] = sf;
+            }
+          }
           if constexpr (FWD) {
             if (r_p == 0) {
               // raw u_k at the tile's own columns, for the contraction
@@ -365,7 +377,7 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
 #pragma unroll
           for (int j = 0; j < RUN + 2 * S; ++j) win[j] = col[j * kTWP];
           // the forward and the adjoint passes use one tap set for both passes
-          const double *wcol = MODE == MODE_SIGS ? a.wc : a.wr;
+          const double *wcol = a.wr;
           if constexpr (FWD) {
             const float *ucol = &uring[(b0 + S) * kTWP + c_x];
             Window<S, BOX> cw;
@@ -378,9 +390,11 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
             const int ty0k = opaque(ty * TH);
             const int gx = tx0 + c_x;
             const float *uk = a.u + (int64_t)k * N;
+            float cu[MODE == MODE_SIGS ? RUN : 1];
 #pragma unroll
             for (int i = 0; i < RUN; ++i) {
-              const double z = fir_sym<S>(wcol, &win[i]);
+              // SIGS: w1' down the w1 rows here, w1 down the w1' rows below
+              const double z = fir_sym<S>(MODE == MODE_SIGS ? a.wc : wcol, &win[i]);
               const int gy = ty0k + o0 + i;
               const bool inpix = oc < a.nch && gy < H && gx < W;
               const int pix = inpix ? gy * W + gx : 0;
@@ -391,6 +405,7 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
                 } else {
                   const float uo = inpix ? uk[pix] : 0.0f;
                   sacc = fma((double)(uo * coef), z, sacc);
+                  if constexpr (MODE == MODE_SIGS) cu[i] = uo * coef;
                 }
               } else {  // MODE_ADJ
                 float coef = 1.0f;
@@ -402,6 +417,12 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
                 }
                 ex[(c_p * RC + c_sub * RUN + i) * kTW + c_x] = coef * (float)z;
               }
+            }
+            if constexpr (MODE == MODE_SIGS) {
+#pragma unroll
+              for (int j = 0; j < RUN + 2 * S; ++j) win[j] = col[NP * K::PR + j * kTWP];
+#pragma unroll
+              for (int i = 0; i < RUN; ++i) sacc = fma((double)cu[i], fir_sym<S>(wcol, &win[i]), sacc);
             }
           }
           if constexpr (MODE == MODE_DUDIR || MODE == MODE_ADJ) {

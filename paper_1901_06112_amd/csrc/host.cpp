@@ -747,7 +747,7 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
   double *hsig = hred + (size_t)nred * (nR + 1);
   float *hc = reinterpret_cast<float *>(hsig + 2 * (size_t)nsig);
   memcpy(hF, Fh.data(), sizeof(double) * Fh.size());
-  int nb1 = 0, nb2 = 0;
+  int nb1 = 0;
   {
     StageTimer tm(ctx, NKF_STAGE_BACKWARD);
     HIP_TRY(ctx, hipMemcpyAsync(Fd, hF, sizeof(double) * r * r_eff, hipMemcpyHostToDevice, ctx->stream));
@@ -778,17 +778,12 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
       const double s3 = prm->sigma_s * prm->sigma_s * prm->sigma_s;
       for (int t = -rs.S; t <= rs.S; ++t)
         dt.w[t + rs.S] = (float)(exp(-(double)t * t / (2.0 * prm->sigma_s * prm->sigma_s)) * t * t / s3);
-      bp.mode = 2;
+      bp.mode = 2;  // both terms in one pass: w1 in wr, w1' in wc
       bp.plane_out = nullptr;
       bp.partials = sig;
-      bp.wr = dt;
-      bp.wc = rs.taps;
-      bp.nblocks_out = &nb1;
-      HIP_TRY(ctx, launch_bwd_conv(bp, ctx->stream));
-      bp.partials = sig + nsig;
       bp.wr = rs.taps;
       bp.wc = dt;
-      bp.nblocks_out = &nb2;
+      bp.nblocks_out = &nb1;
       HIP_TRY(ctx, launch_bwd_conv(bp, ctx->stream));
       bp.wr = bp.wc = rs.taps;
       bp.nblocks_out = nullptr;
@@ -806,7 +801,6 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
   HIP_TRY(ctx, hipMemcpyAsync(hred, red, sizeof(double) * nred * (nR + 1), hipMemcpyDeviceToHost, ctx->stream));
   if (want_S) {
     HIP_TRY(ctx, hipMemcpyAsync(hsig, sig, sizeof(double) * nb1, hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(hsig + nsig, sig + nsig, sizeof(double) * nb2, hipMemcpyDeviceToHost, ctx->stream));
   }
   if (want_R)
     HIP_TRY(ctx, hipMemcpyAsync(hc, centroids, sizeof(float) * r * rs.D, hipMemcpyDeviceToHost, ctx->stream));
@@ -814,7 +808,6 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
   if (want_S) {
     double s = 0.0;
     for (int b = 0; b < nb1; ++b) s += hsig[b];
-    for (int b = 0; b < nb2; ++b) s += hsig[nsig + b];
     *grad_sigma_s_host = s;
   }
   if (want_R) {
