@@ -27,6 +27,8 @@
  *  - Errors are returned as nkf_status; nkf_last_error() gives a message.
  *    Arguments are validated before any work is enqueued; a call that fails
  *    validation has no effect.  No call aborts the process.
+ *  - Sizes: H * W <= 2^31 (else NKF_ERR_INVALID_ARG), W <= 2^21 and
+ *    C <= 1024 (else NKF_ERR_UNSUPPORTED).
  *  - Non-finite input pixels give unspecified output (not checked).
  *  - The image border is handled by intersecting the window with the image
  *    (zero extension of numerator and denominator alike).

@@ -124,6 +124,22 @@ __device__ __forceinline__ V opaque(V v) {
   return v;
 }
 
+// The same for a wave-uniform value, kept in a scalar register.
+__device__ __forceinline__ int opaque_s(int v) {
+  return __builtin_amdgcn_readfirstlane(opaque(v));
+}
+
+// Raw buffer resource (no stride, gfx9 data format field) over 2^31 - 256
+// bytes from base.  A buffer load whose offset is at or past that range
+// returns 0 instead of touching memory; kOffInvalid is such an offset.
+constexpr unsigned kOffInvalid = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, 0x7FFFFF00, 0x00020000);
+}
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
 // sum_t w[t] x[t] for a symmetric window (w[t] == w[2S - t]): the mirrored
 // pair x[t] + x[2S - t] of two FP32 values is exact in FP64, so folding halves
 // the taps held in scalar registers without changing the VALU operation count.
@@ -227,61 +243,67 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
   constexpr int NPOS = (RC * SW + BT - 1) / BT;
   constexpr int NCH1 = NCHAN > 0 ? NCHAN : 1;
   float pu[NPOS], pf[NPOS][NCH1], pb[NPOS];
-  // Loads use clamped in-bounds addresses and keep the raw values; the
-  // validity of each position goes into the bit mask inm and is applied when
-  // the values are stored, so the loads are issued without branches and
-  // nothing waits for them until the store one chunk later.
-  unsigned inm = 0;
-  // per staged position q: column validity (fixed for the thread) as a bit mask
-  unsigned colm = 0;
+  // Loads go through buffer resources based at the first image row of the
+  // chunk, with 32-bit byte offsets relative to it.  A position outside the
+  // image (or past the staging tile) takes kOffInvalid and reads 0, so the
+  // loads are issued without branches or masks, and nothing waits for them
+  // until the store one chunk later.  relq[q] = rr * W + gx of position q;
+  // colv[q]: its column lies in the image.
+  int relq[NPOS];
+  bool colv[NPOS];
 #pragma unroll
   for (int q = 0; q < NPOS; ++q) {
     const int e = tid + q * BT;
     const int rr = e / SW, j = e - rr * SW;
     const int gx = tx0 - S + j;
-    colm |= (e < RC * SW && j < kTW + 2 * S && gx >= 0 && gx < W ? 1u : 0u) << q;
+    colv[q] = e < RC * SW && j < kTW + 2 * S && gx >= 0 && gx < W;
+    relq[q] = rr * W + gx;
   }
-  // channel chunks of 4 within C % 4 == 0 (and a 16-byte aligned f) load as float4
-  const bool vec4 = NCHAN == 4 && C % 4 == 0 && c0 + 4 <= C && (reinterpret_cast<uintptr_t>(a.f) & 15) == 0;
   auto fetch = [&](int kk, int icc) {
-    const int ty0k = opaque(ty * TH);  // redefined per call: no address is hoisted out of the k loop
-    const float *uk = a.u + (int64_t)kk * N;
-    const int gy0 = ty0k - S + icc * RC;
-    inm = 0;
+    // redefined per call, so that no offset is hoisted out of the k loop
+    const int gy0 = opaque_s(ty * TH) - S + icc * RC;   // image row of staging row 0
+    const int gyb = gy0 > 0 ? gy0 : 0;                  // resource base row
+    const int dW = (gy0 - gyb) * W;                     // staging row 0 relative to it
+    const int64_t rowoff = (int64_t)gyb * W;
+    const __amdgpu_buffer_rsrc_t ru = buf_rsrc(a.u + (int64_t)kk * N + rowoff);
+    unsigned off[NPOS];
 #pragma unroll
     for (int q = 0; q < NPOS; ++q) {
-      const int e = tid + q * BT;
-      const int rr = e / SW, j = e - rr * SW;
-      // H * W <= 2^31, so a valid pixel index fits in 32 bits; invalid
-      // positions read pixel 0 and are masked at the store
-      const unsigned gy = (unsigned)(gy0 + rr), gx = (unsigned)(tx0 - S + j);
-      const bool in = ((colm >> q) & 1u) && gy < (unsigned)H;
-      inm |= (in ? 1u : 0u) << q;
-      const unsigned pix = in ? gy * (unsigned)W + gx : 0u;
-      pu[q] = uk[pix];
-      if constexpr (MODE == MODE_ADJ) {
-        const float *ap = a.ab + (size_t)pix * 4;
-        pb[q] = ap[0];
+      const int rr = (tid + q * BT) / SW;
+      const bool in = colv[q] && (unsigned)(gy0 + rr) < (unsigned)H;
+      const unsigned rel = (unsigned)(relq[q] + dW);   // pixel offset from the base row
+      off[q] = in ? rel : kOffInvalid;
+      pu[q] = buf_ld(ru, in ? rel * 4u : kOffInvalid);
+    }
+    if constexpr (MODE == MODE_ADJ) {
+      // (beta, a_1..a_3) of a pixel: four dword loads at one offset (the
+      // 16-byte buffer load builtin is not used: this compiler lowers it to a
+      // single dword)
+      const __amdgpu_buffer_rsrc_t rab = buf_rsrc(a.ab + rowoff * 4);
 #pragma unroll
-        for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = ap[1 + ch];
-      } else {
-        if (a.fpl) {
-          // planar f: each channel load is contiguous across the lanes
+      for (int q = 0; q < NPOS; ++q) {
+        const unsigned ob = off[q] != kOffInvalid ? off[q] * 16u : kOffInvalid;
+        pb[q] = buf_ld(rab, ob);
 #pragma unroll
-          for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = a.fpl[(size_t)(c0 + ch < C ? c0 + ch : C - 1) * N + pix];
-          continue;
-        }
-        const float *fp = a.f + (size_t)pix * C;
-        if constexpr (NCHAN == 4) {
-          if (vec4) {
-            // four whole channels of a pixel in one 16-byte load
-            const float4 v = *reinterpret_cast<const float4 *>(fp + c0);
-            pf[q][0] = v.x, pf[q][1] = v.y, pf[q][2] = v.z, pf[q][3] = v.w;
-            continue;
-          }
-        }
+        for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = buf_ld(rab, ob + 4u * (unsigned)(1 + ch));
+      }
+    } else if (a.fpl) {
+      // planar f: each channel load is contiguous across the lanes
 #pragma unroll
-        for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = fp[c0 + ch < C ? c0 + ch : C - 1];
+      for (int ch = 0; ch < NCHAN; ++ch) {
+        const int cc = c0 + ch < C ? c0 + ch : C - 1;
+        const __amdgpu_buffer_rsrc_t rc = buf_rsrc(a.fpl + (int64_t)cc * N + rowoff);
+#pragma unroll
+        for (int q = 0; q < NPOS; ++q) pf[q][ch] = buf_ld(rc, off[q] != kOffInvalid ? off[q] * 4u : kOffInvalid);
+      }
+    } else {
+      // interleaved f (C <= 3); channels past C re-read channel C-1 and are zeroed by chm
+      const __amdgpu_buffer_rsrc_t rf = buf_rsrc(a.f + rowoff * C);
+#pragma unroll
+      for (int q = 0; q < NPOS; ++q) {
+        const unsigned of = off[q] != kOffInvalid ? off[q] * (unsigned)(4 * C) : kOffInvalid;
+#pragma unroll
+        for (int ch = 0; ch < NCHAN; ++ch) pf[q][ch] = buf_ld(rf, of + 4u * (unsigned)(c0 + ch < C ? c0 + ch : C - 1));
       }
     }
   };
@@ -298,7 +320,7 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
           const int e = tid + q * BT;
           if (e < RC * SW) {
             const int rr = e / SW, j = e - rr * SW;
-            const float uq = (inm >> q) & 1u ? pu[q] : 0.0f;  // zero outside the image
+            const float uq = pu[q];  // 0 outside the image
             if constexpr (MODE == MODE_ADJ)
               stg[rr * SW + j] = pb[q] * uq;  // plane 0: beta u_k
             else

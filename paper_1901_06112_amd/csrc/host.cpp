@@ -213,6 +213,8 @@ nkf_status validate(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, co
     return fail(ctx, NKF_ERR_INVALID_ARG, "sizes must be >= 1 (H=%d W=%d C=%d D=%d)", H, W, C, D);
   if ((int64_t)H * W > (int64_t)1 << 31)
     return fail(ctx, NKF_ERR_INVALID_ARG, "H*W exceeds 2^31");
+  // the convolution kernels address a chunk of rows with 32-bit byte offsets
+  if (W > (1 << 21)) return fail(ctx, NKF_ERR_UNSUPPORTED, "W=%d exceeds 2^21", W);
   if (!f) return fail(ctx, NKF_ERR_INVALID_ARG, "f is NULL");
   if (D > 256) return fail(ctx, NKF_ERR_UNSUPPORTED, "guide dimension D=%d exceeds 256", D);
   if (C > 1024) return fail(ctx, NKF_ERR_UNSUPPORTED, "C=%d exceeds 1024", C);

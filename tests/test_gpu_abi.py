@@ -49,6 +49,9 @@ def test_validation_errors_have_no_effect():
     assert call(prm, D=2) == nkf.NKF_ERR_INVALID_ARG                     # self guide needs D == C
     assert call(prm, fptr=ct.c_void_p(0)) == nkf.NKF_ERR_INVALID_ARG       # NULL image
     assert call(prm, outp=ct.c_void_p(0)) == nkf.NKF_ERR_INVALID_ARG       # NULL output
+    # width past 2^21: rejected during validation, before any buffer is read
+    assert lib.nkf_filter(ctx, 1, (1 << 21) + 1, C, ct.c_void_p(f.data_ptr()), 3, ct.c_void_p(0), ct.byref(prm),
+                          ct.c_void_p(out.data_ptr()), ct.c_void_p(0), None) == nkf.NKF_ERR_UNSUPPORTED
     prm.guide = nkf.GUIDE["patch"]
     prm.patch_radius = 1
     assert call(prm, D=3) == nkf.NKF_ERR_INVALID_ARG                     # needs D = 27
