@@ -216,7 +216,7 @@ nkf_status validate(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, co
   // the convolution kernels address a chunk of rows with 32-bit byte offsets
   if (W > (1 << 21)) return fail(ctx, NKF_ERR_UNSUPPORTED, "W=%d exceeds 2^21", W);
   if (!f) return fail(ctx, NKF_ERR_INVALID_ARG, "f is NULL");
-  if (D > 256) return fail(ctx, NKF_ERR_UNSUPPORTED, "guide dimension D=%d exceeds 256", D);
+  if (D > kMaxGuideDim) return fail(ctx, NKF_ERR_UNSUPPORTED, "guide dimension D=%d exceeds %d", D, kMaxGuideDim);
   if (C > 1024) return fail(ctx, NKF_ERR_UNSUPPORTED, "C=%d exceeds 1024", C);
   if (!(prm->sigma_r > 0.0) || isnan(prm->sigma_r))
     return fail(ctx, NKF_ERR_INVALID_ARG, "sigma_r must be > 0 (got %g)", prm->sigma_r);

@@ -13,6 +13,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace nkf {
@@ -98,6 +100,88 @@ __global__ void mm_init_kernel(unsigned *mm, int C) {
   }
 }
 
+// C <= 4 with a 16-byte aligned f: the N*C floats as float4 groups of
+// G = lcm(4, C) / 4 vectors (whole pixels, so the channel of every component
+// is known at compile time), four groups in flight per thread, per-channel
+// min / max in registers, then wave and block reductions and one pair of
+// atomics per channel and block.  The last N*C mod 4G floats are read one by one.
+template <int C>
+__global__ __launch_bounds__(256) void minmax_small_kernel(const float *__restrict__ f, int64_t total,
+                                                           unsigned *mm) {
+  constexpr int G = C == 3 ? 3 : 1;
+  constexpr int FG = 4 * G;  // floats per group
+  constexpr int UNR = 4;
+  __shared__ unsigned slo[4][C], shi[4][C];
+  unsigned lo[C], hi[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) lo[c] = 0xffffffffu, hi[c] = 0u;
+  const float4 *f4 = reinterpret_cast<const float4 *>(f);
+  const int64_t ngroups = total / FG;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; g + (UNR - 1) * stride < ngroups; g += UNR * stride) {
+    float4 v[UNR][G];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int j = 0; j < G; ++j) v[u][j] = f4[(g + u * stride) * G + j];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const float e[4] = {v[u][j].x, v[u][j].y, v[u][j].z, v[u][j].w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int c = (4 * j + t) % C;
+          const unsigned k = ord_encode(e[t]);
+          lo[c] = min(lo[c], k);
+          hi[c] = max(hi[c], k);
+        }
+      }
+  }
+  for (; g < ngroups; g += stride)
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const float4 q = f4[g * G + j];
+      const float e[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int c = (4 * j + t) % C;
+        const unsigned k = ord_encode(e[t]);
+        lo[c] = min(lo[c], k);
+        hi[c] = max(hi[c], k);
+      }
+    }
+  // tail floats (fewer than FG), by the first threads of block 0
+  if (blockIdx.x == 0 && threadIdx.x < FG) {
+    const int64_t e = ngroups * FG + threadIdx.x;
+    if (e < total) {
+      const unsigned k = ord_encode(f[e]);
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        if ((int)(e % C) == c) lo[c] = min(lo[c], k), hi[c] = max(hi[c], k);
+    }
+  }
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1) {
+      lo[c] = min(lo[c], (unsigned)__shfl_xor((int)lo[c], m, kWave));
+      hi[c] = max(hi[c], (unsigned)__shfl_xor((int)hi[c], m, kWave));
+    }
+    if (lane == 0) slo[w][c] = lo[c], shi[w][c] = hi[c];
+  }
+  __syncthreads();
+  if (threadIdx.x < C) {
+    const int c = threadIdx.x;
+    unsigned a = slo[0][c], b = shi[0][c];
+    for (int q = 1; q < (int)(blockDim.x / kWave); ++q) a = min(a, slo[q][c]), b = max(b, shi[q][c]);
+    atomicMin(&mm[c], a);
+    atomicMax(&mm[C + c], b);
+  }
+}
+
 // Block size is a multiple of C, so a thread's channel is fixed.
 __global__ void minmax_kernel(const float *__restrict__ f, int64_t total, int C, unsigned *mm) {
   extern __shared__ unsigned sm[];
@@ -145,8 +229,20 @@ hipError_t launch_center(const float *f, int64_t N, int C, double center, float 
   hipLaunchKernelGGL(mm_init_kernel, dim3(cb), dim3(256), 0, s, mm, C);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int B = C <= 256 ? C * (256 / C) : C;
   const int64_t total = N * C;
+  if (C <= 4 && (reinterpret_cast<uintptr_t>(f) & 15) == 0) {
+    const int blocks = (int)std::min<int64_t>(std::max<int64_t>((total / 16 + 255) / 256, 1), 1024);
+    switch (C) {
+      case 1: hipLaunchKernelGGL(minmax_small_kernel<1>, dim3(blocks), dim3(256), 0, s, f, total, mm); break;
+      case 2: hipLaunchKernelGGL(minmax_small_kernel<2>, dim3(blocks), dim3(256), 0, s, f, total, mm); break;
+      case 3: hipLaunchKernelGGL(minmax_small_kernel<3>, dim3(blocks), dim3(256), 0, s, f, total, mm); break;
+      default: hipLaunchKernelGGL(minmax_small_kernel<4>, dim3(blocks), dim3(256), 0, s, f, total, mm); break;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(center_final_kernel, dim3(cb), dim3(256), 0, s, mm, C, f0, 0, 0.0f);
+    return hipGetLastError();
+  }
+  const int B = C <= 256 ? C * (256 / C) : C;
   int64_t blocks = (total + (int64_t)B * 16 - 1) / ((int64_t)B * 16);
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;

@@ -251,35 +251,25 @@ __global__ __launch_bounds__(kBlock) void accumulate_generic_kernel(Guide g, int
 // c_k[d] = mu(d) + S_k[d] / n_k from the per-block partial sums (S of the
 // centred values when mu is given, of the raw values otherwise; mu_mod > 0
 // indexes mu by d % mu_mod).  An empty cluster keeps its centroid.  One block
-// per cluster; every sum runs over the partials in a fixed order, so the
-// result does not depend on timing.
+// per cluster; the D sums and the count (column D) are formed in groups of
+// up to kBlock columns, each column summed by G lanes (partial b on lane
+// b mod G, loads issued eight at a time) and the G lane sums added in lane
+// order: a fixed order, so the result does not depend on timing.
 __global__ __launch_bounds__(kBlock) void update_kernel(const double *__restrict__ partials, int nparts,
                                                         int r, int D, const float *__restrict__ mu,
                                                         int mu_mod, float *__restrict__ c) {
   __shared__ double red[kBlock];
-  __shared__ double cnt_s;
+  __shared__ double tot[kMaxGuideDim + 1];
   const int k = blockIdx.x, tid = threadIdx.x;
   const int DA = D + 1;
   const size_t stride = (size_t)r * DA;
   const double *base = partials + (size_t)k * DA;
-  if (tid < kWave) {
-    double s = 0.0;
-    for (int b = tid; b < nparts; b += kWave) s += base[(size_t)b * stride + D];
-#pragma unroll
-    for (int m = kWave / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m, kWave);
-    if (tid == 0) cnt_s = s;
-  }
-  __syncthreads();
-  const double n = cnt_s;
-  if (!(n > 0.0)) return;
-  // columns in groups of up to kBlock, each summed by G lanes (b = lane mod G)
-  for (int m0 = 0; m0 < D; m0 += kBlock) {
-    const int M = D - m0 < kBlock ? D - m0 : kBlock;
+  for (int m0 = 0; m0 < DA; m0 += kBlock) {
+    const int M = DA - m0 < kBlock ? DA - m0 : kBlock;
     const int G = kBlock / M;
     const int m = tid % M, gl = tid / M;
     double s = 0.0;
     if (gl < G) {
-      // loads issued eight at a time, added in block order
       int b = gl;
       for (; b + 7 * G < nparts; b += 8 * G) {
         double v[8];
@@ -295,11 +285,15 @@ __global__ __launch_bounds__(kBlock) void update_kernel(const double *__restrict
     if (tid < M) {
       double t = 0.0;
       for (int q = 0; q < G; ++q) t += red[q * M + tid];
-      const int d = m0 + tid;
-      const double off = mu ? (double)mu[mu_mod > 0 ? d % mu_mod : d] : 0.0;
-      c[k * D + d] = (float)(off + t / n);
+      tot[m0 + tid] = t;
     }
     __syncthreads();
+  }
+  const double n = tot[D];
+  if (!(n > 0.0)) return;
+  for (int d = tid; d < D; d += kBlock) {
+    const double off = mu ? (double)mu[mu_mod > 0 ? d % mu_mod : d] : 0.0;
+    c[k * D + d] = (float)(off + tot[d] / n);
   }
 }
 

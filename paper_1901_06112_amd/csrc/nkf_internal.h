@@ -22,6 +22,7 @@ struct Guide {
 // Window radius limit of the convolution kernels (T = 2S+1 <= 33 taps).
 constexpr int kMaxRadius = 16;
 constexpr int kMaxLandmarks = 256;
+constexpr int kMaxGuideDim = 256;  // D
 
 struct Taps {
   float w[2 * kMaxRadius + 1];

@@ -226,3 +226,31 @@ def test_box_window_colour_and_gray(C, S, h, w):
     g, eta, _ = _run_case(f, f, c32, 1.0, 30.0, S, spatial="box", guide="self")
     go, etao = _oracle(f, f, c32, 1.0, 30.0, S, spatial="box")
     _report_conditioned(f"box_C{C}_S{S}", f, f, c32, 1.0, 30.0, S, g, go, spatial="box")
+
+
+@pytest.mark.parametrize("C,h,w", [(1, 37, 29), (2, 33, 31), (3, 41, 27), (4, 29, 35)])
+def test_auto_centre_equals_explicit_midrange(C, h, w):
+    """The device's per-channel centring offset f0 = (min + max) / 2 (float4
+    reduction with an unaligned tail): every channel is given the extremes 3
+    and 250 (those of the last channel in the last pixels, which the vector
+    loop leaves to the tail), so the automatic offsets all equal 126.5 and
+    the output must be bit-identical to the run with that explicit centre."""
+    nkf = _nkf()
+    rng = np.random.default_rng(C * 100 + h)
+    f = rng.uniform(10.0, 200.0, (h, w, C)).astype(np.float32)
+    flat = f.reshape(-1, C)
+    for c in range(C):
+        lo_px, hi_px = (flat.shape[0] - 1, flat.shape[0] - 2) if c == C - 1 else (3 * c, 3 * c + 1)
+        flat[lo_px, c], flat[hi_px, c] = 3.0, 250.0
+    assert C == 4 or (h * w * C) % (12 if C == 3 else 4) != 0   # a tail (C = 4 has none)
+    ft = torch.from_numpy(f).cuda()
+    c32 = _landmarks(flat.astype(np.float64), 6, seed=C, iters=3)
+    Q, al, F, reff = nkf.landmark_factor(c32.astype(np.float64), 40.0)
+    ct_ = torch.from_numpy(c32).cuda()
+    kw = dict(sigma_s=2.0, sigma_r=40.0, radius=4, guide="self")
+    g_auto = nkf.filter_landmarks(ft, ct_, F, **kw).cpu().numpy()
+    g_expl = nkf.filter_landmarks(ft, ct_, F, center=126.5, **kw).cpu().numpy()
+    g_off = nkf.filter_landmarks(ft, ct_, F, center=0.0, **kw).cpu().numpy()
+    print(f"[centre C={C}] max|auto-explicit|={np.abs(g_auto - g_expl).max():.3e} "
+          f"max|auto-uncentred|={np.abs(g_auto - g_off).max():.3e}", flush=True)
+    assert np.array_equal(g_auto, g_expl)
