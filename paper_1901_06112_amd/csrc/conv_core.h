@@ -76,7 +76,7 @@ struct ConvArgs {
   double wc[2 * kMaxRadius + 1];  // column-pass taps
 };
 
-template <int S, int NP, bool HAS_E, int RC, int MODE, int BT = kBlock>
+template <int S, int NP, bool HAS_E, int RC, int MODE, int BT = kBlock, bool BOX = false>
 struct Cfg {
   static constexpr int T = 2 * S + 1;
   // LDS has 64 banks of 4 bytes; a b128 access is served 16 lanes at a time.
@@ -110,6 +110,13 @@ struct Cfg {
   static constexpr int MAIN = STG + RINGF + URINGF + EXF;
   static constexpr int SMEM = MAIN > ETAB ? MAIN : ETAB;
   static_assert(RUN * SEGS == kTW, "row pass split");
+  // Ring rows as 16-byte stores (row stride == 4 mod 32 and plane stride ==
+  // 32 mod 64: each 16 lanes of a store cover all 64 banks, where single-float
+  // stores of the same lanes meet 4 to a bank).  Measured faster for the box
+  // window and the channel-chunk kernels, slightly slower for the Gaussian
+  // kernels with the E plane, which keep single-float stores.
+  static constexpr bool VEC_RING = BOX || !HAS_E;
+  static_assert(kTWP % 4 == 0 && PR % 4 == 0 && PSTG % 4 == 0, "ring and staging rows hold whole float4s");
   static_assert(SUBS * RUN == RC, "column pass split");
   static_assert(RC * NP * SEGS == BT, "row pass threads");
   static_assert(FWD || (NP == 4 && HAS_E), "backward modes use the E plane + 3 channel planes");
@@ -174,11 +181,25 @@ struct Window {
   }
 };
 
+// RUN floats (RUN % 4 == 0) to the 16-byte aligned run at dst as 16-byte
+// stores, and again at dst + mirror_off when mirror is set.
+template <int RUN>
+__device__ __forceinline__ void store_run4(float *dst, const float *v, bool mirror, int mirror_off) {
+  static_assert(RUN % 4 == 0, "runs are whole float4s");
+  float4 *d4 = reinterpret_cast<float4 *>(dst);
+#pragma unroll
+  for (int j = 0; j < RUN / 4; ++j) {
+    const float4 q = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+    d4[j] = q;
+    if (mirror) d4[mirror_off / 4 + j] = q;
+  }
+}
+
 template <int S, int NP, bool HAS_E, int RC, int MODE, int BT = kBlock, bool BOX = false>
 __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
-  using K = Cfg<S, NP, HAS_E, RC, MODE, BT>;
+  using K = Cfg<S, NP, HAS_E, RC, MODE, BT, BOX>;
   constexpr int SW = K::SW, RUN = K::RUN, SEGS = K::SEGS, LAG = K::LAG, RING = K::RING;
-  constexpr int RINGX = K::RINGX, NCH_MAX = K::NCH_MAX, NCHAN = K::NCHAN, UPL = K::UPL;
+  constexpr int NCH_MAX = K::NCH_MAX, NCHAN = K::NCHAN, UPL = K::UPL;
   constexpr bool FWD = K::FWD;
   constexpr bool BWD_AB = MODE == MODE_DUDIR || MODE == MODE_SIGS;  // contraction weights a, beta
   __shared__ __attribute__((aligned(16))) float smem[K::SMEM];
@@ -356,12 +377,19 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
           }
           float *dst = &ring[r_p * K::PR + slot * kTWP + r_sg * RUN];
           Window<S, BOX> rw;
+          if constexpr (K::VEC_RING) {
+            float ov[RUN];
 #pragma unroll
-          for (int i = 0; i < RUN; ++i) {
-            const double s = rw.at(a.wr, win, i);
-            const float sf = (float)s;
-            dst[i] = sf;
-            if (mirror) dst[RING * kTWP + i] = sf;
+            for (int i = 0; i < RUN; ++i) ov[i] = (float)rw.at(a.wr, win, i);
+            store_run4<RUN>(dst, ov, mirror, RING * kTWP);
+          } else {
+            // each output stored as soon as it is formed
+#pragma unroll
+            for (int i = 0; i < RUN; ++i) {
+              const float sf = (float)rw.at(a.wr, win, i);
+              dst[i] = sf;
+              if (mirror) dst[RING * kTWP + i] = sf;
+            }
           }
           if constexpr (MODE == MODE_SIGS) {
             // the w1' rows, in the second ring
@@ -378,11 +406,18 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
               // raw u_k at the tile's own columns, for the contraction
               const float *us = &stg[UPL * K::PSTG + r_rr * SW + S + r_sg * RUN];
               float *ud = &uring[slot * kTWP + r_sg * RUN];
+              if constexpr (K::VEC_RING) {
+                float ov[RUN];
 #pragma unroll
-              for (int i = 0; i < RUN; ++i) {
-                const float uv = us[i];
-                ud[i] = uv;
-                if (mirror) ud[RING * kTWP + i] = uv;
+                for (int i = 0; i < RUN; ++i) ov[i] = us[i];
+                store_run4<RUN>(ud, ov, mirror, RING * kTWP);
+              } else {
+#pragma unroll
+                for (int i = 0; i < RUN; ++i) {
+                  const float uv = us[i];
+                  ud[i] = uv;
+                  if (mirror) ud[RING * kTWP + i] = uv;
+                }
               }
             }
           }
@@ -570,7 +605,7 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
 template <int S, int NP, bool HAS_E, int RC, int MODE, int BT = kBlock, bool BOX = false>
 hipError_t launch_one(ConvArgs a, hipStream_t s, int ch_per_block, int nchunks_c, int min_blocks = 512,
                       int *nblocks_out = nullptr) {
-  using K = Cfg<S, NP, HAS_E, RC, MODE, BT>;
+  using K = Cfg<S, NP, HAS_E, RC, MODE, BT, BOX>;
   a.ch_per_block = ch_per_block;
   a.tiles_x = (a.W + kTW - 1) / kTW;
   // largest chunk count (<= NCH_MAX) that still gives >= min_blocks blocks;
