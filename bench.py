@@ -13,7 +13,9 @@ HBM before the timed region.
 
 Prints one JSON line; ``roofline`` describes the convolution + contraction
 kernel, timed with HIP events on the stream it runs on; ``cpu_baseline`` is
-the FP64 oracle on a bounded crop of the same image.  ``workloads`` holds the
+the FP64 oracle on a bounded crop of the same image, with (``quality``) the
+PSNR of the GPU output against the exact brute-force filter on the centre
+256 x 256 pixels.  ``workloads`` holds the
 other configurations, each timed the same way (whole calls, inputs resident):
 the hyperspectral BLF (512 x 512 x 128, d = 128) in the plain FP32 form and
 the BF16 precision form, the colour NLM (1024 x 1024, 7 x 7 x 3 patches,
@@ -92,13 +94,18 @@ def copy_calibration(nbytes, reps):
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def cpu_baseline(crop=1024):
+def cpu_baseline(crop=1024, gpu_out=None, gpu_landmarks=None, qcrop=256):
     """The FP64 oracle (k-means + Algorithm 1) on a crop x crop centre crop
-    of the workload image, single-threaded BLAS."""
+    of the workload image, single-threaded BLAS.  With the GPU output of the
+    full image and its landmarks, also the quality the throughput is quoted
+    at: PSNR against the exact brute-force filter (Eq. (num)) on the centre
+    qcrop x qcrop pixels, evaluated on a crop with an S-pixel margin so that
+    every window lies inside it, for the GPU output and for the FP64 oracle
+    with the same landmarks (the two differ by arithmetic only)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
-    from oracle import kmeans, nystrom, seeding
+    from oracle import exact, kmeans, nystrom, seeding
     from paper_1901_06112_amd import synth
 
     f, prm = synth.workload(WORKLOAD)
@@ -111,9 +118,24 @@ def cpu_baseline(crop=1024):
         c, _, _ = kmeans.lloyd(P, c0, prm["iters"])
         nystrom.nystrom_filter(fc, fc, c, prm["sigma_s"], prm["sigma_r"], prm["S"])
         dt = time.perf_counter() - t0
-    return {"value": crop * crop / dt / 1e6, "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
-            "sample": f"{crop}x{crop} centre crop of the 2048x2048 image, full oracle path "
-                      f"(seeding, {prm['iters']} Lloyd iterations, Algorithm 1 in FP64), {dt:.1f} s"}
+    res = {"value": crop * crop / dt / 1e6, "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+           "sample": f"{crop}x{crop} centre crop of the 2048x2048 image, full oracle path "
+                     f"(seeding, {prm['iters']} Lloyd iterations, Algorithm 1 in FP64), {dt:.1f} s"}
+    if gpu_out is not None:
+        m, q = prm["S"], qcrop
+        yq = (f.shape[0] - q) // 2
+        fe = np.ascontiguousarray(f[yq - m:yq + q + m, yq - m:yq + q + m]).astype(np.float64)
+        ex = exact.exact_filter(fe, fe, prm["sigma_s"], prm["sigma_r"], prm["S"])[m:m + q, m:m + q]
+        gq = gpu_out[yq:yq + q, yq:yq + q]
+        qual = {"gpu_psnr_vs_exact_dB": round(float(exact.psnr(gq, ex)), 2)}
+        if gpu_landmarks is not None:
+            ny = nystrom.nystrom_filter(fe, fe, gpu_landmarks, prm["sigma_s"], prm["sigma_r"], prm["S"])[m:m + q, m:m + q]
+            qual["oracle_same_landmarks_psnr_vs_exact_dB"] = round(float(exact.psnr(ny, ex)), 2)
+            qual["max_abs_gpu_vs_oracle"] = float(np.abs(gq - ny).max())
+        qual["sample"] = (f"centre {q}x{q} pixels of the full-image GPU call; exact brute-force BLF "
+                          f"({2 * m + 1}x{2 * m + 1} window); oracle: Algorithm 1 in FP64 with the GPU's landmarks")
+        res["quality"] = qual
+    return res
 
 
 def _timed(fn, steps, warmup, timing_tensor=None):
@@ -327,7 +349,9 @@ def main():
     if not a.no_extra:
         line["workloads"] = {k: fn(a.leg_steps, 1) for k, fn in LEGS.items()}
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(a.cpu_crop)
+        cen = nkf.kmeans(ft, r=prm["r"], iters=prm["iters"], seed=prm["landmark_seed"])
+        line["cpu_baseline"] = cpu_baseline(a.cpu_crop, out.cpu().numpy().astype(np.float64),
+                                            cen.cpu().numpy().astype(np.float64))
     print(json.dumps(line), flush=True)
 
 

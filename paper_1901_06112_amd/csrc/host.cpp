@@ -351,7 +351,7 @@ struct FwdBufs {
 
 void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r = kMaxLandmarks) {
   b.f0 = cv.take<float>(rs.C);
-  b.mm = cv.take<unsigned>(2 * (size_t)rs.C);
+  b.mm = cv.take<unsigned>(center_scratch_words(rs.C));
   b.u = cv.take<float>((size_t)r_eff * rs.N);
   b.eta_buf = cv.take<float>(rs.C > 3 ? rs.N : 1);
   b.f_planar = cv.take<float>(rs.C > 3 ? (size_t)rs.C * rs.N : 1);

@@ -92,6 +92,16 @@ __device__ __forceinline__ float ord_decode(unsigned k) {
   return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
 }
 
+// The C <= 4 path keeps kMmReps copies of the (min, max) words, each copy
+// in its own 128-byte slot, so that the per-block atomics of a launch spread
+// over kMmReps cache lines instead of queueing on one.
+constexpr int kMmReps = 32, kMmSlot = 32;
+
+__global__ void mm_init_reps_kernel(unsigned *mm, int C) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kMmReps * kMmSlot) mm[i] = i % kMmSlot < C ? 0xffffffffu : 0u;
+}
+
 __global__ void mm_init_kernel(unsigned *mm, int C) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < C) {
@@ -177,8 +187,9 @@ __global__ __launch_bounds__(256) void minmax_small_kernel(const float *__restri
     const int c = threadIdx.x;
     unsigned a = slo[0][c], b = shi[0][c];
     for (int q = 1; q < (int)(blockDim.x / kWave); ++q) a = min(a, slo[q][c]), b = max(b, shi[q][c]);
-    atomicMin(&mm[c], a);
-    atomicMax(&mm[C + c], b);
+    unsigned *slot = mm + (blockIdx.x % kMmReps) * kMmSlot;
+    atomicMin(&slot[c], a);
+    atomicMax(&slot[C + c], b);
   }
 }
 
@@ -206,13 +217,19 @@ __global__ void minmax_kernel(const float *__restrict__ f, int64_t total, int C,
   }
 }
 
-__global__ void center_final_kernel(const unsigned *mm, int C, float *f0, int use_value, float value) {
+// reps > 1: the replicated layout of the C <= 4 path
+__global__ void center_final_kernel(const unsigned *mm, int C, float *f0, int use_value, float value, int reps) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= C) return;
   if (use_value) {
     f0[i] = value;
   } else {
-    const double lo = ord_decode(mm[i]), hi = ord_decode(mm[C + i]);
+    unsigned a = mm[i], b = mm[C + i];
+    for (int q = 1; q < reps; ++q) {
+      a = min(a, mm[q * kMmSlot + i]);
+      b = max(b, mm[q * kMmSlot + C + i]);
+    }
+    const double lo = ord_decode(a), hi = ord_decode(b);
     f0[i] = (float)(0.5 * (lo + hi));
   }
 }
@@ -223,14 +240,14 @@ hipError_t launch_center(const float *f, int64_t N, int C, double center, float 
                          hipStream_t s) {
   const int cb = (C + 255) / 256;
   if (isfinite(center)) {
-    hipLaunchKernelGGL(center_final_kernel, dim3(cb), dim3(256), 0, s, mm, C, f0, 1, (float)center);
+    hipLaunchKernelGGL(center_final_kernel, dim3(cb), dim3(256), 0, s, mm, C, f0, 1, (float)center, 1);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(mm_init_kernel, dim3(cb), dim3(256), 0, s, mm, C);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e;
   const int64_t total = N * C;
   if (C <= 4 && (reinterpret_cast<uintptr_t>(f) & 15) == 0) {
+    hipLaunchKernelGGL(mm_init_reps_kernel, dim3(kMmReps * kMmSlot / 256), dim3(256), 0, s, mm, C);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     const int blocks = (int)std::min<int64_t>(std::max<int64_t>((total / 16 + 255) / 256, 1), 1024);
     switch (C) {
       case 1: hipLaunchKernelGGL(minmax_small_kernel<1>, dim3(blocks), dim3(256), 0, s, f, total, mm); break;
@@ -239,18 +256,22 @@ hipError_t launch_center(const float *f, int64_t N, int C, double center, float 
       default: hipLaunchKernelGGL(minmax_small_kernel<4>, dim3(blocks), dim3(256), 0, s, f, total, mm); break;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(center_final_kernel, dim3(cb), dim3(256), 0, s, mm, C, f0, 0, 0.0f);
+    hipLaunchKernelGGL(center_final_kernel, dim3(cb), dim3(256), 0, s, mm, C, f0, 0, 0.0f, kMmReps);
     return hipGetLastError();
   }
+  hipLaunchKernelGGL(mm_init_kernel, dim3(cb), dim3(256), 0, s, mm, C);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   const int B = C <= 256 ? C * (256 / C) : C;
   int64_t blocks = (total + (int64_t)B * 16 - 1) / ((int64_t)B * 16);
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(minmax_kernel, dim3((int)blocks), dim3(B), 2 * B * sizeof(unsigned), s, f, total, C, mm);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(center_final_kernel, dim3(cb), dim3(256), 0, s, mm, C, f0, 0, 0.0f);
+  hipLaunchKernelGGL(center_final_kernel, dim3(cb), dim3(256), 0, s, mm, C, f0, 0, 0.0f, 1);
   return hipGetLastError();
 }
+
+size_t center_scratch_words(int C) { return C <= 4 ? (size_t)kMmReps * kMmSlot : 2 * (size_t)C; }
 
 hipError_t launch_embed(const Guide &g, const float *c, int r, const double *F, int r_eff, double sigma_r,
                         float *u, hipStream_t s) {

@@ -64,6 +64,8 @@ inline bool use_mfma_distance(const Guide &g, int prec) { return prec != 0 && g.
 
 // ---- kernels_embed.hip ------------------------------------------------------
 // f0[c] = center (finite) or (min_c + max_c) / 2 over f.
+// words of the mm scratch that launch_center needs
+size_t center_scratch_words(int C);
 hipError_t launch_center(const float *f, int64_t N, int C, double center, float *f0,
                          unsigned *scratch /*[2C]*/, hipStream_t s);
 // u[k][x] = sum_j F[j][k] exp(-|p(x) - c_j|^2 / (2 sigma_r^2)), planar [r_eff][N] float32.
