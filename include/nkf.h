@@ -131,9 +131,28 @@ nkf_status nkf_kmeans_iterate(nkf_ctx *ctx, int H, int W, int C, const float *f,
                               const float *p, const nkf_params *prm, float *centroids, int iters,
                               int *labels);
 
+/* PCA patch guide of PCA-NLM (Section IV: the NLM experiments reduce the
+ * (2pr+1)^2 C patch values by PCA, e.g. 147 -> 25, before the range kernel).
+ * f: device [H, W, C] float32.  The basis is estimated from the patches
+ * ((dy, dx, channel) order, symmetric padding) of min(H*W, 65536) pixels: a
+ * SplitMix64 partial Fisher-Yates draw from `seed` (as in nkf_seed_indices)
+ * when H*W is larger, all pixels in order otherwise.  FP64 mean and
+ * mean-centred covariance (1/n); the `dim` eigenvectors of the largest
+ * eigenvalues, in descending order, each with its largest-magnitude entry
+ * positive (the first on ties).  guide_out: device [H, W, dim] float32,
+ * g(x)_k = (p(x) - mean) . v_k evaluated in FP64; pass it to nkf_filter as an
+ * explicit guide with D = dim.  eigvals_host (nullable, host [dim]): the kept
+ * eigenvalues.  Limits: (2pr+1)^2 C <= 256 (else NKF_ERR_UNSUPPORTED) and
+ * 1 <= dim <= min((2pr+1)^2 C, 32) (else NKF_ERR_INVALID_ARG).  Synchronises
+ * the stream once (the covariance is decomposed on the host);
+ * NKF_ERR_NUMERICAL if that eigensolver does not converge. */
+nkf_status nkf_patch_pca(nkf_ctx *ctx, int H, int W, int C, const float *f, int patch_radius, int dim,
+                         uint64_t seed, float *guide_out, double *eigvals_host);
+
 /* Host-only, synchronous, FP64.  Landmark Gram matrix A(i,j) = k(c_i, c_j)
  * (Eq. (defA)), its eigendecomposition A = Q diag(alpha) Q^T (Eq. (eigA)) by
- * cyclic Jacobi, truncation of alpha <= tau * max(alpha), and the factor
+ * Householder tridiagonalisation and implicit symmetric QR steps, truncation
+ * of alpha <= tau * max(alpha), and the factor
  * F = Q_keep diag(alpha_keep^{-1/2}) so that u(x) = F^T b(x) gives
  * u(x).u(y) = b(x)^T A^+ b(y) = K_hat(x, y) (Eqs. (hatK), (vk)).
  * centroids_host [r, D]; eigvecs_host (nullable) [r, r], column j = q_j;

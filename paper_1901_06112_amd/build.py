@@ -31,6 +31,7 @@ SOURCES = [
     "kernels_conv_box.hip",
     "kernels_bwd.hip",
     "kernels_mfma.hip",
+    "kernels_pca.hip",
 ]
 
 COMMON = [

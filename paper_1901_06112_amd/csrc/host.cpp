@@ -614,6 +614,83 @@ nkf_status nkf_kmeans(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
   return run_lloyd(ctx, rs, prm->r, centroids, prm->kmeans_iters, labels, kb, prm->prec);
 }
 
+// PCA patch guide (PCA-NLM, Section IV).  Basis from the patches of
+// min(N, kPcaSample) pixels (a seeded draw when N is larger), FP64 moments on
+// the device, the D x D eigenproblem on the host, projection on the device.
+constexpr int kPcaSample = 65536;
+
+nkf_status nkf_patch_pca(nkf_ctx *ctx, int H, int W, int C, const float *f, int patch_radius, int dim,
+                         uint64_t seed, float *guide_out, double *eigvals_host) {
+  if (!ctx) return fail(nullptr, NKF_ERR_INVALID_ARG, "ctx is NULL");
+  if (H < 1 || W < 1 || C < 1) return fail(ctx, NKF_ERR_INVALID_ARG, "sizes must be >= 1 (H=%d W=%d C=%d)", H, W, C);
+  if ((int64_t)H * W > (int64_t)1 << 31) return fail(ctx, NKF_ERR_INVALID_ARG, "H*W exceeds 2^31");
+  if (!f || !guide_out) return fail(ctx, NKF_ERR_INVALID_ARG, "f and guide_out are required");
+  const int pr = patch_radius;
+  if (pr < 0) return fail(ctx, NKF_ERR_INVALID_ARG, "patch_radius must be >= 0");
+  if (pr > H || pr > W) return fail(ctx, NKF_ERR_INVALID_ARG, "patch_radius exceeds the image");
+  const int64_t D64 = (int64_t)(2 * pr + 1) * (2 * pr + 1) * C;
+  if (D64 > kMaxGuideDim)
+    return fail(ctx, NKF_ERR_UNSUPPORTED, "patch dimension %lld exceeds %d", (long long)D64, kMaxGuideDim);
+  const int D = (int)D64;
+  if (dim < 1 || dim > D || dim > pca_max_dim())
+    return fail(ctx, NKF_ERR_INVALID_ARG, "need 1 <= dim <= min(D = %d, %d) (got %d)", D, pca_max_dim(), dim);
+  const int64_t N = (int64_t)H * W;
+  const int ns = N > kPcaSample ? kPcaSample : (int)N;
+  const int mb = ns < 64 ? ns : 64;
+  const int cc = std::max(1, std::min(16, (ns + 63) / 64));
+  Guide g{GUIDE_PATCH, nullptr, f, H, W, C, D, pr};
+  auto carve = [&](Carve &cv, int64_t *&idx, double *&part, double *&mu, double *&cpart, double *&cov, double *&V) {
+    idx = cv.take<int64_t>(ns);
+    part = cv.take<double>((size_t)mb * D);
+    mu = cv.take<double>(D);
+    cpart = cv.take<double>((size_t)cc * D * D);
+    cov = cv.take<double>((size_t)D * D);
+    V = cv.take<double>((size_t)D * dim);
+  };
+  int64_t *idx;
+  double *part, *mu, *cpart, *cov, *V;
+  Carve dry{nullptr};
+  carve(dry, idx, part, mu, cpart, cov, V);
+  nkf_status st;
+  if ((st = ensure_workspace(ctx, dry.off)) != NKF_OK) return st;
+  const size_t h_idx = (sizeof(int64_t) * ns + 255) & ~(size_t)255;
+  const size_t h_cov = (sizeof(double) * D * D + 255) & ~(size_t)255;
+  if ((st = ensure_pinned(ctx, h_idx + h_cov + sizeof(double) * D * dim)) != NKF_OK) return st;
+  Carve cv{ctx->ws};
+  carve(cv, idx, part, mu, cpart, cov, V);
+  int64_t *idx_host = reinterpret_cast<int64_t *>(ctx->pinned);
+  double *cov_host = reinterpret_cast<double *>(ctx->pinned + h_idx);
+  double *V_host = reinterpret_cast<double *>(ctx->pinned + h_idx + h_cov);
+  const int64_t *idx_dev = nullptr;
+  if (N > ns) {
+    // the stream may still read the pinned buffer from an earlier call
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    draw_indices(N, ns, seed, idx_host);
+    HIP_TRY(ctx, hipMemcpyAsync(idx, idx_host, sizeof(int64_t) * ns, hipMemcpyHostToDevice, ctx->stream));
+    idx_dev = idx;
+  }
+  HIP_TRY(ctx, launch_pca_moments(g, idx_dev, ns, mb, cc, part, mu, cpart, cov, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(cov_host, cov, sizeof(double) * D * D, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  std::vector<double> w(D), Q((size_t)D * D);
+  if (sym_eig(D, cov_host, w.data(), Q.data()) != 0)
+    return fail(ctx, NKF_ERR_NUMERICAL, "eigendecomposition of the patch covariance did not converge");
+  // the dim largest eigenvalues, descending; each vector's largest-magnitude
+  // entry (the first on ties) made positive
+  for (int k = 0; k < dim; ++k) {
+    const int col = D - 1 - k;
+    int jm = 0;
+    for (int j = 1; j < D; ++j)
+      if (fabs(Q[(size_t)j * D + col]) > fabs(Q[(size_t)jm * D + col])) jm = j;
+    const double sg = Q[(size_t)jm * D + col] < 0.0 ? -1.0 : 1.0;
+    for (int j = 0; j < D; ++j) V_host[(size_t)j * dim + k] = sg * Q[(size_t)j * D + col];
+    if (eigvals_host) eigvals_host[k] = w[col];
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(V, V_host, sizeof(double) * D * dim, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, launch_pca_project(g, mu, V, dim, guide_out, ctx->stream));
+  return NKF_OK;
+}
+
 nkf_status nkf_filter_landmarks(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, const float *p,
                                 const nkf_params *prm, const float *centroids, const double *F, int r_eff,
                                 float *out, float *eta_out) {

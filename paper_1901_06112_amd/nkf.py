@@ -28,7 +28,7 @@ EXPORTS = [
     "nkf_params_default", "nkf_version", "nkf_create", "nkf_set_stream", "nkf_destroy",
     "nkf_last_error", "nkf_set_workspace_limit", "nkf_workspace_bytes", "nkf_filter", "nkf_kmeans",
     "nkf_kmeans_iterate", "nkf_landmark_factor", "nkf_filter_landmarks", "nkf_filter_backward",
-    "nkf_seed_indices", "nkf_spatial_taps", "nkf_enable_timing", "nkf_stage_times",
+    "nkf_seed_indices", "nkf_spatial_taps", "nkf_enable_timing", "nkf_stage_times", "nkf_patch_pca",
 ]
 STAGES = ["seed", "kmeans", "factor", "embed", "conv", "backward"]
 
@@ -80,6 +80,7 @@ def load_library(path=LIB_PATH):
             "nkf_filter_backward": (I, [P, I, I, I, P, I, P, PP, P, P, P, I, P, P, P, P, P, P, P]),
             "nkf_seed_indices": (I, [ct.c_int64, I, U64, P]),
             "nkf_spatial_taps": (I, [I, D, I, ct.POINTER(I), P]),
+            "nkf_patch_pca": (I, [P, I, I, I, P, I, I, U64, P, P]),
             "nkf_enable_timing": (I, [P, I]),
             "nkf_stage_times": (I, [P, P, P, I]),
         }
@@ -201,6 +202,18 @@ def filter(f, p=None, *, sigma_s=3.0, sigma_r=30.0, r=16, radius=-1, spatial="ga
     if return_r_eff:
         res += (reff.value,)
     return res[0] if len(res) == 1 else res
+
+
+def patch_pca(f, *, patch_radius=3, dim=25, seed=0, return_eigvals=False):
+    """PCA-reduced patch guide [H, W, dim] (float32, device) of PCA-NLM; use
+    it as the explicit guide ``p`` of ``filter``."""
+    H, W, C = f.shape
+    g = torch.empty((H, W, dim), dtype=torch.float32, device=f.device)
+    ev = np.zeros(dim, np.float64)
+    ctx = _cur_ctx(f)
+    _check(load_library().nkf_patch_pca(ctx, H, W, C, _dev_f32(f, "f"), patch_radius, dim, seed, _ptr(g),
+                                        ev.ctypes.data_as(ct.c_void_p)), ctx)
+    return (g, ev) if return_eigvals else g
 
 
 def kmeans(f, p=None, *, r=16, iters=10, seed=0, guide=None, patch_radius=3, precision="fp32",
