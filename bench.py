@@ -19,8 +19,10 @@ PSNR of the GPU output against the exact brute-force filter on the centre
 other configurations, each timed the same way (whole calls, inputs resident):
 the hyperspectral BLF (512 x 512 x 128, d = 128) in the plain FP32 form and
 the BF16 precision form, the colour NLM (1024 x 1024, 7 x 7 x 3 patches,
-d = 147, 21 x 21 box) in FP32 and FP16, and the differentiation batch (eight
-384..1024-sided images, fixed landmarks) forward and forward + backward.
+d = 147, 21 x 21 box) in FP32 and FP16, the colour PCA-NLM (the same image,
+patches reduced by PCA to 25 dimensions, 31 landmarks) in FP32 and FP16, and
+the differentiation batch (eight 384..1024-sided images, fixed landmarks)
+forward and forward + backward.
 ``--leg NAME`` runs one of those legs alone (for profiling).
 """
 from __future__ import annotations
@@ -212,6 +214,47 @@ def leg_precision(name, steps, warmup):
     return out
 
 
+def leg_pca_nlm(steps, warmup):
+    """Colour PCA-NLM (the paper's NLM): the NLM image, 7x7x3 patches reduced
+    by PCA to 25 dimensions (nkf_patch_pca), 21x21 box, 31 landmarks, sigma_r =
+    3 x the noise level.  One call = PCA guide + filter with the reduced
+    explicit guide, in the FP32 form and the FP16 form."""
+    import numpy as np
+    import torch
+
+    from paper_1901_06112_amd import nkf, synth
+    f, prm = synth.workload("color_pca_nlm_1024")
+    H, W, C = f.shape
+    N = H * W
+    ft = torch.from_numpy(f).cuda()
+    pk = dict(patch_radius=prm["patch_radius"], dim=prm["pca_dim"], seed=prm["seed"])
+    kw = dict(sigma_s=1.0, sigma_r=prm["sigma_r"], r=prm["r"], radius=prm["S"], spatial="box",
+              iters=prm["iters"], seed=prm["landmark_seed"])
+    pca_ms, _, _ = _timed(lambda: nkf.patch_pca(ft, **pk), steps, warmup)
+    out = {"H": H, "W": W, "C": C, "d_patch": C * (2 * prm["patch_radius"] + 1) ** 2, "d_pca": prm["pca_dim"],
+           "r": prm["r"], "S": prm["S"], "spatial": "box", "sigma_r": prm["sigma_r"], "kmeans_iters": prm["iters"],
+           "pca_ms": round(pca_ms, 3)}
+    res = {}
+    for prec in ("fp32", "fp16"):
+        def call():
+            g = nkf.patch_pca(ft, **pk)
+            return nkf.filter(ft, g, precision=prec, return_r_eff=True, **kw)
+        ms, st, (g, r_eff) = _timed(call, steps, warmup, ft)
+        res[prec] = ({"ms_per_call": round(ms, 3), "Mpixel_s": round(N / ms / 1e3, 2), "r_eff": r_eff,
+                      "stages_ms": st}, g)
+    out.update({p: e for p, (e, _) in res.items()})
+    # each form runs its own k-means, which in 25 dimensions may settle on other
+    # landmarks; the arithmetic of the two forms is compared with shared ones
+    g = nkf.patch_pca(ft, **pk)
+    cen = nkf.kmeans(ft, g, r=prm["r"], iters=prm["iters"], seed=prm["landmark_seed"])
+    Q, al, F, r_eff = nkf.landmark_factor(cen.cpu().numpy().astype(np.float64), prm["sigma_r"])
+    fl = {prec: nkf.filter_landmarks(ft, cen, F, g, sigma_s=1.0, sigma_r=prm["sigma_r"], radius=prm["S"],
+                                     spatial="box", precision=prec) for prec in ("fp32", "fp16")}
+    out["psnr_fp16_vs_fp32_same_landmarks_dB"] = round(_psnr(fl["fp16"], fl["fp32"], 255.0), 2)
+    out["psnr_fp16_vs_fp32_own_landmarks_dB"] = round(_psnr(res["fp16"][1], res["fp32"][1], 255.0), 2)
+    return out
+
+
 def leg_diff(steps, warmup):
     """Differentiation batch: eight images, landmarks fixed (k-means outside the
     timed region), forward and forward + hand-written backward (df, dp,
@@ -254,6 +297,7 @@ LEGS = {
     "hyperspectral": lambda s, w: leg_precision("hyperspectral_512x128", s, w),
     "nlm": lambda s, w: leg_precision("color_nlm_1024", s, w),
     "diff_batch": lambda s, w: leg_diff(s, w),
+    "pca_nlm": lambda s, w: leg_pca_nlm(s, w),
 }
 
 

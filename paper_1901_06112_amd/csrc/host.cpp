@@ -10,7 +10,6 @@
 
 #include <chrono>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "../../include/nkf.h"
@@ -41,6 +40,10 @@ struct nkf_ctx {
   std::vector<hipEvent_t> event_pool;
   double host_ms[NKF_STAGE_COUNT] = {0};
   int host_count[NKF_STAGE_COUNT] = {0};
+  // the last PCA sample draw (it depends on N and the seed only)
+  int64_t pca_draw_N = -1;
+  uint64_t pca_draw_seed = 0;
+  std::vector<int64_t> pca_draw;
 };
 
 namespace {
@@ -175,18 +178,49 @@ uint64_t splitmix_next(uint64_t &s) {
   return z ^ (z >> 31);
 }
 
+// The swaps of a partial Fisher-Yates shuffle of the virtual identity array
+// [0, N), kept in an open-addressing table (linear probing, at most 2r keys in
+// a power-of-two table of >= 4r slots): entry k of the array is map[k] when
+// present, else k.
+class SwapMap {
+ public:
+  explicit SwapMap(int r) {
+    size_t cap = 16;
+    int bits = 4;
+    while (cap < 4 * (size_t)r) cap <<= 1, ++bits;
+    keys_.assign(cap, -1);
+    vals_.resize(cap);
+    mask_ = cap - 1;
+    shift_ = 64 - bits;
+  }
+  int64_t get(int64_t k) const {
+    for (size_t h = slot(k);; h = (h + 1) & mask_) {
+      if (keys_[h] == k) return vals_[h];
+      if (keys_[h] < 0) return k;
+    }
+  }
+  void set(int64_t k, int64_t v) {
+    size_t h = slot(k);
+    while (keys_[h] >= 0 && keys_[h] != k) h = (h + 1) & mask_;
+    keys_[h] = k;
+    vals_[h] = v;
+  }
+
+ private:
+  size_t slot(int64_t k) const { return (size_t)(((uint64_t)k * 0x9E3779B97F4A7C15ull) >> shift_); }
+  std::vector<int64_t> keys_, vals_;
+  size_t mask_;
+  int shift_;
+};
+
 void draw_indices(int64_t N, int r, uint64_t seed, int64_t *idx) {
   uint64_t s = seed;
-  std::unordered_map<int64_t, int64_t> sw;
-  sw.reserve(2 * (size_t)r + 8);
+  SwapMap sw(r);
   for (int i = 0; i < r; ++i) {
     const int64_t j = i + (int64_t)(splitmix_next(s) % (uint64_t)(N - i));
-    auto ai = sw.find(i);
-    auto aj = sw.find(j);
-    const int64_t vi = ai == sw.end() ? i : ai->second;
-    const int64_t vj = aj == sw.end() ? j : aj->second;
-    sw[i] = vj;
-    sw[j] = vi;
+    const int64_t vi = sw.get(i), vj = sw.get(j);
+    sw.set(i, vj);
+    sw.set(j, vi);
     idx[i] = vj;
   }
 }
@@ -636,11 +670,13 @@ nkf_status nkf_patch_pca(nkf_ctx *ctx, int H, int W, int C, const float *f, int 
     return fail(ctx, NKF_ERR_INVALID_ARG, "need 1 <= dim <= min(D = %d, %d) (got %d)", D, pca_max_dim(), dim);
   const int64_t N = (int64_t)H * W;
   const int ns = N > kPcaSample ? kPcaSample : (int)N;
-  const int mb = ns < 64 ? ns : 64;
+  const int mb = ns < 256 ? ns : 256;
   const int cc = std::max(1, std::min(16, (ns + 63) / 64));
   Guide g{GUIDE_PATCH, nullptr, f, H, W, C, D, pr};
+  float *S;
   auto carve = [&](Carve &cv, int64_t *&idx, double *&part, double *&mu, double *&cpart, double *&cov, double *&V) {
     idx = cv.take<int64_t>(ns);
+    S = cv.take<float>(pca_sample_floats(D, ns));
     part = cv.take<double>((size_t)mb * D);
     mu = cv.take<double>(D);
     cpart = cv.take<double>((size_t)cc * D * D);
@@ -663,13 +699,19 @@ nkf_status nkf_patch_pca(nkf_ctx *ctx, int H, int W, int C, const float *f, int 
   double *V_host = reinterpret_cast<double *>(ctx->pinned + h_idx + h_cov);
   const int64_t *idx_dev = nullptr;
   if (N > ns) {
+    if (ctx->pca_draw_N != N || ctx->pca_draw_seed != seed) {
+      ctx->pca_draw.resize(ns);
+      draw_indices(N, ns, seed, ctx->pca_draw.data());
+      ctx->pca_draw_N = N;
+      ctx->pca_draw_seed = seed;
+    }
     // the stream may still read the pinned buffer from an earlier call
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    draw_indices(N, ns, seed, idx_host);
+    memcpy(idx_host, ctx->pca_draw.data(), sizeof(int64_t) * ns);
     HIP_TRY(ctx, hipMemcpyAsync(idx, idx_host, sizeof(int64_t) * ns, hipMemcpyHostToDevice, ctx->stream));
     idx_dev = idx;
   }
-  HIP_TRY(ctx, launch_pca_moments(g, idx_dev, ns, mb, cc, part, mu, cpart, cov, ctx->stream));
+  HIP_TRY(ctx, launch_pca_moments(g, idx_dev, ns, mb, cc, S, part, mu, cpart, cov, ctx->stream));
   HIP_TRY(ctx, hipMemcpyAsync(cov_host, cov, sizeof(double) * D * D, hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   std::vector<double> w(D), Q((size_t)D * D);

@@ -22,18 +22,28 @@ constexpr int kProjMaxDim = 32;  // dim bound (registers of the projection)
 
 __device__ __forceinline__ int64_t sample_pixel(const int64_t *idx, int s) { return idx ? idx[s] : (int64_t)s; }
 
-// partials[b][d] = sum of p(x)_d over block b's share of the sample
-__global__ __launch_bounds__(kBlock) void pca_mean_kernel(Guide g, const int64_t *__restrict__ idx, int ns,
-                                                          int chunk, double *__restrict__ partials) {
+// S[s][d] = p(x_s)_d: the sample's patches gathered once, row-major
+__global__ __launch_bounds__(kBlock) void pca_gather_kernel(Guide g, const int64_t *__restrict__ idx, int ns,
+                                                            float *__restrict__ S) {
+  const int64_t total = (int64_t)ns * g.D;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
+    const int s = (int)(e / g.D), d = (int)(e - (int64_t)s * g.D);
+    S[e] = guide_elem(g, sample_pixel(idx, s), d);
+  }
+}
+
+// partials[b][d] = sum of S[s][d] over block b's share of the sample
+__global__ __launch_bounds__(kBlock) void pca_mean_kernel(const float *__restrict__ S, int ns, int D, int chunk,
+                                                          double *__restrict__ partials) {
   const int s0 = blockIdx.x * chunk, s1 = min(ns, s0 + chunk);
-  for (int d = threadIdx.x; d < g.D; d += kBlock) {
+  for (int d = threadIdx.x; d < D; d += kBlock) {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     int s = s0;
     for (; s + 4 <= s1; s += 4)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) a[q] += (double)guide_elem(g, sample_pixel(idx, s + q), d);
-    for (; s < s1; ++s) a[0] += (double)guide_elem(g, sample_pixel(idx, s), d);
-    partials[(size_t)blockIdx.x * g.D + d] = (a[0] + a[1]) + (a[2] + a[3]);
+      for (int q = 0; q < 4; ++q) a[q] += (double)S[(size_t)(s + q) * D + d];
+    for (; s < s1; ++s) a[0] += (double)S[(size_t)s * D + d];
+    partials[(size_t)blockIdx.x * D + d] = (a[0] + a[1]) + (a[2] + a[3]);
   }
 }
 
@@ -46,15 +56,14 @@ __global__ void pca_mean_final_kernel(const double *__restrict__ partials, int n
   mu[d] = s / ns;
 }
 
-// One 16 x 16 tile (ti <= tj) of sum_s (p_s - mu)(p_s - mu)^T over one chunk
+// One 16 x 16 tile (ti <= tj) of sum_s (S_s - mu)(S_s - mu)^T over one chunk
 // of the sample: thread (a, b) owns entry (16 ti + a, 16 tj + b); the centred
 // values of 64 samples for both tiles' dimensions are staged in LDS per pass.
 // cpart[chunk][i][j] for the entries of tiles with ti <= tj.
-__global__ __launch_bounds__(kBlock) void pca_cov_kernel(Guide g, const int64_t *__restrict__ idx, int ns,
+__global__ __launch_bounds__(kBlock) void pca_cov_kernel(const float *__restrict__ S, int ns, int D,
                                                          const double *__restrict__ mu, int chunk,
                                                          double *__restrict__ cpart) {
   __shared__ double xi[kCovBatch][kCovTile], xj[kCovBatch][kCovTile + 1];
-  const int D = g.D;
   const int nt = (D + kCovTile - 1) / kCovTile;
   // pair index -> (ti, tj), ti <= tj, row-major over the upper triangle
   int pidx = blockIdx.x, ti = 0;
@@ -74,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void pca_cov_kernel(Guide g, const int64_t 
       const int s = r / kCovTile, k = r % kCovTile;
       const int d = (which ? tj : ti) * kCovTile + k;
       double v = 0.0;
-      if (sb + s < s1 && d < D) v = (double)guide_elem(g, sample_pixel(idx, sb + s), d) - mu[d];
+      if (sb + s < s1 && d < D) v = (double)S[(size_t)(sb + s) * D + d] - mu[d];
       if (which)
         xj[s][k] = v;
       else
@@ -105,21 +114,22 @@ __global__ void pca_cov_final_kernel(const double *__restrict__ cpart, int nchun
 }
 
 // g(x) = (p(x) - mu) V for one pixel per thread; V and mu in LDS.
+template <int DIM>
 __global__ __launch_bounds__(kBlock) void pca_project_kernel(Guide g, int64_t N, const double *__restrict__ mu,
-                                                             const double *__restrict__ V, int dim,
+                                                             const double *__restrict__ V,
                                                              float *__restrict__ out) {
   extern __shared__ double sm[];
   const int D = g.D;
-  double *Vs = sm;              // [D][dim]
-  double *ms = sm + D * dim;    // [D]
-  for (int e = threadIdx.x; e < D * dim; e += kBlock) Vs[e] = V[e];
+  double *Vs = sm;              // [D][DIM]
+  double *ms = sm + D * DIM;    // [D]
+  for (int e = threadIdx.x; e < D * DIM; e += kBlock) Vs[e] = V[e];
   for (int e = threadIdx.x; e < D; e += kBlock) ms[e] = mu[e];
   __syncthreads();
   const int T = 2 * g.pr + 1, C = g.C;
   for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < N; x += (int64_t)gridDim.x * kBlock) {
-    double acc[kProjMaxDim];
+    double acc[DIM];
 #pragma unroll
-    for (int k = 0; k < kProjMaxDim; ++k) acc[k] = 0.0;
+    for (int k = 0; k < DIM; ++k) acc[k] = 0.0;
     const int y = (int)(x / g.W), xx = (int)(x - (int64_t)y * g.W);
     int d = 0;
     for (int dy = 0; dy < T; ++dy) {
@@ -129,54 +139,73 @@ __global__ __launch_bounds__(kBlock) void pca_project_kernel(Guide g, int64_t N,
         const float *px = row + (int64_t)sym_index(xx + dx - g.pr, g.W) * C;
         for (int c = 0; c < C; ++c, ++d) {
           const double v = (double)px[c] - ms[d];
-          const double *vr = Vs + d * dim;
+          const double *vr = Vs + d * DIM;
 #pragma unroll
-          for (int k = 0; k < kProjMaxDim; ++k)
-            if (k < dim) acc[k] = fma(v, vr[k], acc[k]);
+          for (int k = 0; k < DIM; ++k) acc[k] = fma(v, vr[k], acc[k]);
         }
       }
     }
-    float *o = out + x * dim;
+    float *o = out + x * DIM;
 #pragma unroll
-    for (int k = 0; k < kProjMaxDim; ++k)
-      if (k < dim) o[k] = (float)acc[k];
+    for (int k = 0; k < DIM; ++k) o[k] = (float)acc[k];
   }
+}
+
+template <int DIM>
+hipError_t launch_project_dim(const Guide &g, const double *mu, const double *V, float *out, hipStream_t s) {
+  const int64_t N = (int64_t)g.H * g.W;
+  const size_t sm = sizeof(double) * ((size_t)g.D * DIM + g.D);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(pca_project_kernel<DIM>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  if (e != hipSuccess) return e;
+  int64_t blocks = (N + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(pca_project_kernel<DIM>, dim3((int)blocks), dim3(kBlock), sm, s, g, N, mu, V, out);
+  return hipGetLastError();
 }
 
 }  // namespace
 
 int pca_max_dim() { return kProjMaxDim; }
 
+size_t pca_sample_floats(int D, int ns) { return (size_t)ns * D; }
+
 hipError_t launch_pca_moments(const Guide &g, const int64_t *idx, int ns, int mean_blocks, int cov_chunks,
-                              double *partials, double *mu, double *cpart, double *cov, hipStream_t s) {
-  const int chunk_m = (ns + mean_blocks - 1) / mean_blocks;
-  hipLaunchKernelGGL(pca_mean_kernel, dim3(mean_blocks), dim3(kBlock), 0, s, g, idx, ns, chunk_m, partials);
+                              float *S, double *partials, double *mu, double *cpart, double *cov, hipStream_t s) {
+  const int D = g.D;
+  int64_t gb = ((int64_t)ns * D + kBlock - 1) / kBlock;
+  if (gb > 16384) gb = 16384;
+  hipLaunchKernelGGL(pca_gather_kernel, dim3((int)gb), dim3(kBlock), 0, s, g, idx, ns, S);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(pca_mean_final_kernel, dim3((g.D + 255) / 256), dim3(256), 0, s, partials, mean_blocks, g.D,
-                     ns, mu);
+  const int chunk_m = (ns + mean_blocks - 1) / mean_blocks;
+  hipLaunchKernelGGL(pca_mean_kernel, dim3(mean_blocks), dim3(kBlock), 0, s, S, ns, D, chunk_m, partials);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int nt = (g.D + kCovTile - 1) / kCovTile;
+  hipLaunchKernelGGL(pca_mean_final_kernel, dim3((D + 255) / 256), dim3(256), 0, s, partials, mean_blocks, D, ns, mu);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int nt = (D + kCovTile - 1) / kCovTile;
   const int npairs = nt * (nt + 1) / 2;
   const int chunk_c = (ns + cov_chunks - 1) / cov_chunks;
-  hipLaunchKernelGGL(pca_cov_kernel, dim3(npairs, cov_chunks), dim3(kBlock), 0, s, g, idx, ns, mu, chunk_c, cpart);
+  hipLaunchKernelGGL(pca_cov_kernel, dim3(npairs, cov_chunks), dim3(kBlock), 0, s, S, ns, D, mu, chunk_c, cpart);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(pca_cov_final_kernel, dim3((g.D * g.D + 255) / 256), dim3(256), 0, s, cpart, cov_chunks, g.D,
-                     ns, cov);
+  hipLaunchKernelGGL(pca_cov_final_kernel, dim3((D * D + 255) / 256), dim3(256), 0, s, cpart, cov_chunks, D, ns, cov);
   return hipGetLastError();
 }
 
 hipError_t launch_pca_project(const Guide &g, const double *mu, const double *V, int dim, float *out,
                               hipStream_t s) {
-  const int64_t N = (int64_t)g.H * g.W;
-  const size_t sm = sizeof(double) * ((size_t)g.D * dim + g.D);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(pca_project_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-  if (e != hipSuccess) return e;
-  int64_t blocks = (N + kBlock - 1) / kBlock;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(pca_project_kernel, dim3((int)blocks), dim3(kBlock), sm, s, g, N, mu, V, dim, out);
-  return hipGetLastError();
+  switch (dim) {
+#define NKF_DIM(n) \
+  case n:          \
+    return launch_project_dim<n>(g, mu, V, out, s);
+    NKF_DIM(1) NKF_DIM(2) NKF_DIM(3) NKF_DIM(4) NKF_DIM(5) NKF_DIM(6) NKF_DIM(7) NKF_DIM(8)
+    NKF_DIM(9) NKF_DIM(10) NKF_DIM(11) NKF_DIM(12) NKF_DIM(13) NKF_DIM(14) NKF_DIM(15) NKF_DIM(16)
+    NKF_DIM(17) NKF_DIM(18) NKF_DIM(19) NKF_DIM(20) NKF_DIM(21) NKF_DIM(22) NKF_DIM(23) NKF_DIM(24)
+    NKF_DIM(25) NKF_DIM(26) NKF_DIM(27) NKF_DIM(28) NKF_DIM(29) NKF_DIM(30) NKF_DIM(31) NKF_DIM(32)
+#undef NKF_DIM
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace nkf

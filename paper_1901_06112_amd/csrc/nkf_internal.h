@@ -117,8 +117,9 @@ hipError_t launch_bwd_reduce(const Guide &g, const float *c, int r, const double
 // ---- kernels_pca.hip ---------------------------------------------------------
 // PCA patch guide: sample moments (FP64), projection of every pixel's patch.
 int pca_max_dim();
+size_t pca_sample_floats(int D, int ns);
 hipError_t launch_pca_moments(const Guide &g, const int64_t *idx, int ns, int mean_blocks, int cov_chunks,
-                              double *partials, double *mu, double *cpart, double *cov, hipStream_t s);
+                              float *S, double *partials, double *mu, double *cpart, double *cov, hipStream_t s);
 hipError_t launch_pca_project(const Guide &g, const double *mu, const double *V, int dim, float *out,
                               hipStream_t s);
 

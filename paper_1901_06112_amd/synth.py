@@ -148,6 +148,11 @@ WORKLOADS = {
     "color_nlm_1024": dict(H=1024, W=1024, C=3, guide="patch", patch_radius=3, sigma_s=10.0,
                            S=10, sigma_r=10.0 * np.sqrt(147.0), r=128, iters=10, spatial="box",
                            seed=1004, landmark_seed=4),
+    # PCA-NLM: the NLM image, patches reduced by PCA to 25 dimensions, m0 = 31
+    # landmarks, theta = 3 x the noise level (Section IV)
+    "color_pca_nlm_1024": dict(H=1024, W=1024, C=3, guide="pca", patch_radius=3, pca_dim=25, sigma_s=10.0,
+                               S=10, sigma_r=90.0, r=31, iters=10, spatial="box", seed=1004,
+                               landmark_seed=4),
     "diff_batch8": dict(C=3, guide="self", sigma_s=3.0, S=9, sigma_r=30.0, r=32, iters=10,
                         spatial="gaussian", seed=1050, landmark_seed=5, n_images=8),
 }
@@ -168,7 +173,7 @@ def workload(name, h=None, w=None, seed=None):
         f = perlin_polygons_image(H, W, 30, 25.0, sd)
     elif name == "hyperspectral_512x128":
         f = hyperspectral_cube(H, W, prm["C"], 8, 0.02, sd)
-    elif name == "color_nlm_1024":
+    elif name in ("color_nlm_1024", "color_pca_nlm_1024"):
         f = rectangles_image(H, W, 12, 30.0, sd)
     elif name == "diff_batch8":
         f = rectangles_image(H, W, 12, 20.0, sd)

@@ -32,7 +32,9 @@ def test_library_exports_every_header_symbol():
 
 
 def test_seed_indices_match_oracle_draw():
-    for N, r, s in [(100, 100, 0), (4194304, 32, 2), (65536, 16, 1), (262144, 64, 12345678901234567)]:
+    # the last two: the PCA patch sample (65536 draws), the first of them a full shuffle
+    for N, r, s in [(100, 100, 0), (4194304, 32, 2), (65536, 16, 1), (262144, 64, 12345678901234567),
+                    (70000, 65536, 3), (1 << 20, 65536, 1004)]:
         np.testing.assert_array_equal(nkf.seed_indices(N, r, s), seeding.distinct_indices(N, r, s))
 
 
