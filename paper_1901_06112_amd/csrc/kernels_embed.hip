@@ -25,7 +25,10 @@ constexpr int kBlock = 256;
 
 // Tiles of TPX pixels (64, or 32 when the FP64 b tile of 64 pixels would not
 // fit in LDS); thread groups of TPX lanes take landmarks kg, kg + NG, ...
-template <int TPX>
+// DS > 0 (D == DS <= 4): the pixel's guide values are held in FP64 registers
+// and the landmarks in FP64 in LDS, so a distance term is one subtraction and
+// one FMA.
+template <int TPX, int DS>
 __global__ __launch_bounds__(kBlock) void embed_kernel(Guide g, int64_t N, const float *__restrict__ c,
                                                        int r, const double *__restrict__ F, int r_eff,
                                                        double inv2s2, float *__restrict__ u) {
@@ -34,24 +37,44 @@ __global__ __launch_bounds__(kBlock) void embed_kernel(Guide g, int64_t N, const
   const int D = g.D;
   double *bs = smem_d;                                              // [r][TPX]
   float *pt = reinterpret_cast<float *>(smem_d + (size_t)r * TPX);  // [D][TPX]
+  double *c64 = smem_d + (size_t)r * TPX;                           // DS > 0: [r][DS], in place of pt
   const int tid = threadIdx.x;
   const int px = tid & (TPX - 1);
   const int kg = __builtin_amdgcn_readfirstlane(tid / TPX);
+  if constexpr (DS > 0) {
+    for (int e = tid; e < r * DS; e += kBlock) c64[e] = (double)c[e];
+  }
   for (int64_t base = (int64_t)blockIdx.x * TPX; base < N; base += (int64_t)gridDim.x * TPX) {
     __syncthreads();
-    for (int e = tid; e < D * TPX; e += kBlock) {
-      const int d = e / TPX, q = e - d * TPX;
-      const int64_t x = base + q;
-      pt[e] = x < N ? guide_elem(g, x, d) : 0.0f;
-    }
-    __syncthreads();
-    for (int k = kg; k < r; k += NG) {
-      double acc = 0.0;
-      for (int d = 0; d < D; ++d) {
-        const double t = (double)pt[d * TPX + px] - (double)c[k * D + d];
-        acc = fma(t, t, acc);
+    if constexpr (DS > 0) {
+      const int64_t x = base + px;
+      double pv[DS > 0 ? DS : 1];
+#pragma unroll
+      for (int d = 0; d < DS; ++d) pv[d] = x < N ? (double)guide_elem(g, x, d) : 0.0;
+      for (int k = kg; k < r; k += NG) {
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < DS; ++d) {
+          const double t = pv[d] - c64[k * DS + d];
+          acc = fma(t, t, acc);
+        }
+        bs[k * TPX + px] = exp_neg64(acc * inv2s2);
       }
-      bs[k * TPX + px] = exp_neg64(acc * inv2s2);
+    } else {
+      for (int e = tid; e < D * TPX; e += kBlock) {
+        const int d = e / TPX, q = e - d * TPX;
+        const int64_t x = base + q;
+        pt[e] = x < N ? guide_elem(g, x, d) : 0.0f;
+      }
+      __syncthreads();
+      for (int k = kg; k < r; k += NG) {
+        double acc = 0.0;
+        for (int d = 0; d < D; ++d) {
+          const double t = (double)pt[d * TPX + px] - (double)c[k * D + d];
+          acc = fma(t, t, acc);
+        }
+        bs[k * TPX + px] = exp_neg64(acc * inv2s2);
+      }
     }
     __syncthreads();
     const int64_t x = base + px;
@@ -277,20 +300,34 @@ hipError_t launch_embed(const Guide &g, const float *c, int r, const double *F, 
                         float *u, hipStream_t s) {
   const int64_t N = (int64_t)g.H * g.W;
   const double inv2s2 = isinf(sigma_r) ? 0.0 : 1.0 / (2.0 * sigma_r * sigma_r);
-  auto lds = [&](int tpx) { return (sizeof(double) * r + sizeof(float) * g.D) * tpx; };
+  // DS > 0 keeps the landmarks as FP64 [r][D] where the generic form stages the guide tile
+  const bool small = g.D <= 4 && g.kind != GUIDE_PATCH;
+  auto lds = [&](int tpx) {
+    return sizeof(double) * r * tpx + std::max(sizeof(float) * g.D * tpx, small ? sizeof(double) * r * g.D : 0);
+  };
   const bool wide = lds(64) <= 160 * 1024;
   const int tpx = wide ? 64 : 32;
   const size_t sm = lds(tpx);
   int64_t blocks = (N + tpx - 1) / tpx;
   if (blocks > 16384) blocks = 16384;
-  const void *kern = wide ? reinterpret_cast<const void *>(embed_kernel<64>)
-                          : reinterpret_cast<const void *>(embed_kernel<32>);
-  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-  if (e != hipSuccess) return e;
-  if (wide)
-    hipLaunchKernelGGL(embed_kernel<64>, dim3((int)blocks), dim3(kBlock), sm, s, g, N, c, r, F, r_eff, inv2s2, u);
-  else
-    hipLaunchKernelGGL(embed_kernel<32>, dim3((int)blocks), dim3(kBlock), sm, s, g, N, c, r, F, r_eff, inv2s2, u);
+  const int ds = small ? g.D : 0;
+  const int key = (wide ? 100 : 0) + ds;
+  hipError_t e = hipSuccess;
+  switch (key) {
+#define NKF_EMBED(K, T, DSV)                                                                                  \
+  case K:                                                                                                     \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(embed_kernel<T, DSV>),                             \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);                             \
+    if (e != hipSuccess) return e;                                                                            \
+    hipLaunchKernelGGL((embed_kernel<T, DSV>), dim3((unsigned)blocks), dim3(kBlock), sm, s, g, N, c, r, F,   \
+                       r_eff, inv2s2, u);                                                                     \
+    break;
+    NKF_EMBED(100, 64, 0) NKF_EMBED(101, 64, 1) NKF_EMBED(102, 64, 2) NKF_EMBED(103, 64, 3) NKF_EMBED(104, 64, 4)
+    NKF_EMBED(0, 32, 0) NKF_EMBED(1, 32, 1) NKF_EMBED(2, 32, 2) NKF_EMBED(3, 32, 3) NKF_EMBED(4, 32, 4)
+#undef NKF_EMBED
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
