@@ -40,6 +40,7 @@ struct nkf_ctx {
   std::vector<hipEvent_t> event_pool;
   double host_ms[NKF_STAGE_COUNT] = {0};
   int host_count[NKF_STAGE_COUNT] = {0};
+  hipEvent_t copy_done = nullptr;  // the landmark copy of nkf_filter
   // the last PCA sample draw (it depends on N and the seed only)
   int64_t pca_draw_N = -1;
   uint64_t pca_draw_seed = 0;
@@ -395,13 +396,24 @@ void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r = kMa
   b.lm = cv.take<unsigned char>(mfma_landmark_scratch_bytes(rs.g, r));
 }
 
+// The landmark-independent part of the forward: the centring offsets f0 and,
+// for the 16-bit distance path, the guide mean.
+nkf_status run_pre(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, const FwdBufs &b) {
+  HIP_TRY(ctx, launch_center(rs.g.f, rs.N, rs.C, prm->center, b.f0, b.mm, ctx->stream));
+  if (use_mfma_distance(rs.g, prm->prec)) HIP_TRY(ctx, launch_guide_mean(rs.g, b.mu, b.mpart, ctx->stream));
+  return NKF_OK;
+}
+
+// pre_done: run_pre has been enqueued already
 nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, const float *c, const double *F,
-                   int r_eff, float *out, float *eta_out, const FwdBufs &b, bool conv = true) {
+                   int r_eff, float *out, float *eta_out, const FwdBufs &b, bool conv = true, bool pre_done = false) {
   {
     StageTimer tm(ctx, NKF_STAGE_EMBED);
-    HIP_TRY(ctx, launch_center(rs.g.f, rs.N, rs.C, prm->center, b.f0, b.mm, ctx->stream));
+    if (!pre_done) {
+      nkf_status st = run_pre(ctx, rs, prm, b);
+      if (st != NKF_OK) return st;
+    }
     if (use_mfma_distance(rs.g, prm->prec)) {
-      HIP_TRY(ctx, launch_guide_mean(rs.g, b.mu, b.mpart, ctx->stream));
       HIP_TRY(ctx, launch_embed_mfma(rs.g, c, prm->r, b.mu, F, b.F32, r_eff, prm->sigma_r, prm->prec, b.u,
                                      b.lm, ctx->stream));
     } else {
@@ -566,6 +578,7 @@ nkf_status nkf_destroy(nkf_ctx *ctx) {
     (void)hipEventDestroy(iv.b);
   }
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  if (ctx->copy_done) (void)hipEventDestroy(ctx->copy_done);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
@@ -787,7 +800,11 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
     HostTimer ht(ctx, NKF_STAGE_FACTOR);
     float *c_host = reinterpret_cast<float *>(ctx->pinned);
     HIP_TRY(ctx, hipMemcpyAsync(c_host, c, sizeof(float) * r * rs.D, hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (!ctx->copy_done) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->copy_done, hipEventDisableTiming));
+    HIP_TRY(ctx, hipEventRecord(ctx->copy_done, ctx->stream));
+    // landmark-independent work runs on the device while the host factors A
+    if ((st = run_pre(ctx, rs, prm, fb)) != NKF_OK) return st;
+    HIP_TRY(ctx, hipEventSynchronize(ctx->copy_done));
     std::vector<double> cd((size_t)r * rs.D);
     for (size_t i = 0; i < cd.size(); ++i) cd[i] = c_host[i];
     double *F_host = reinterpret_cast<double *>(ctx->pinned + ((sizeof(float) * r * rs.D + 255) & ~(size_t)255));
@@ -801,7 +818,7 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
     HIP_TRY(ctx, hipMemcpyAsync(Fd, F_host, sizeof(double) * r * r_eff, hipMemcpyHostToDevice, ctx->stream));
   }
   if (r_eff_out) *r_eff_out = r_eff;
-  return run_fwd(ctx, rs, prm, c, Fd, r_eff, out, eta_out, fb);
+  return run_fwd(ctx, rs, prm, c, Fd, r_eff, out, eta_out, fb, true, true);
 }
 
 nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, const float *p,
