@@ -50,7 +50,8 @@ typedef enum {
   NKF_ERR_INVALID_ARG = 1,   /* a size, pointer or parameter is out of range       */
   NKF_ERR_OUT_OF_MEMORY = 2, /* device/host allocation failed or workspace limit hit */
   NKF_ERR_HIP = 3,           /* a HIP runtime call failed                           */
-  NKF_ERR_NUMERICAL = 4,     /* every eigenvalue of A was truncated (r_eff == 0)    */
+  NKF_ERR_NUMERICAL = 4,     /* an eigensolver did not converge, or every eigenvalue
+                                of A was truncated (r_eff == 0)                      */
   NKF_ERR_UNSUPPORTED = 5    /* valid request outside what this build implements    */
 } nkf_status;
 
@@ -62,7 +63,8 @@ enum { NKF_GUIDE_EXPLICIT = 0, NKF_GUIDE_SELF = 1, NKF_GUIDE_PATCH = 2 };
 /* Input precision of the distance / embedding contraction (k-means assignment
  * and the cross kernel B).  FP32 is the plain form; BF16 and FP16 round the
  * centred guide and landmarks to 16 bits and accumulate in FP32, with the
- * squared norms kept in FP32/FP64.  Spatial convolutions are FP32 always. */
+ * squared norms kept in FP32/FP64.  The spatial convolutions are the same in
+ * every form: FP32 storage, FP64 accumulation within each pass. */
 enum { NKF_PREC_FP32 = 0, NKF_PREC_BF16 = 1, NKF_PREC_FP16 = 2 };
 
 typedef struct {
@@ -158,7 +160,8 @@ nkf_status nkf_patch_pca(nkf_ctx *ctx, int H, int W, int C, const float *f, int 
  * centroids_host [r, D]; eigvecs_host (nullable) [r, r], column j = q_j;
  * eigvals_host (nullable) [r] ascending; F_host [r, r] of which the first
  * *r_eff columns are written (columns follow ascending kept alpha).
- * Returns NKF_ERR_NUMERICAL when r_eff would be 0. */
+ * Returns NKF_ERR_NUMERICAL when r_eff would be 0 or the eigensolver does not
+ * converge. */
 nkf_status nkf_landmark_factor(int r, int D, const double *centroids_host, double sigma_r,
                                double tau, double *eigvecs_host, double *eigvals_host,
                                double *F_host, int *r_eff);
@@ -196,7 +199,8 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
 /* Stage timing.  When enabled, every stage a call enqueues is bracketed by
  * HIP events on the context's stream (host-side stages by the host clock).
  * Stages: 0 seeding, 1 k-means iterations, 2 landmark factor (host FP64,
- * including the wait for the landmarks), 3 centring + embedding,
+ * including the wait for the landmarks; nkf_filter runs the centring on the
+ * device meanwhile), 3 embedding (with the centring in nkf_filter_landmarks),
  * 4 convolutions + contraction, 5 backward. */
 enum { NKF_STAGE_SEED = 0, NKF_STAGE_KMEANS = 1, NKF_STAGE_FACTOR = 2, NKF_STAGE_EMBED = 3,
        NKF_STAGE_CONV = 4, NKF_STAGE_BACKWARD = 5, NKF_STAGE_COUNT = 6 };
