@@ -34,6 +34,10 @@ def _case(kind, h, w):
     if kind == "hyper":
         f, _ = synth.workload("hyperspectral_512x128", h, w)
         return f, None, "self", f.reshape(-1, f.shape[2]).astype(np.float64)
+    if kind == "explicit25":
+        f, _ = synth.workload("color_blf_256", h, w)
+        p = np.ascontiguousarray(synth.workload("hyperspectral_512x128", h, w)[0][:, :, :25] * 255.0)
+        return f, p, "explicit", p.reshape(-1, 25).astype(np.float64)
     if kind == "patch":
         f, _ = synth.workload("color_nlm_1024", h, w)
         pg = exact.patch_guide(f.astype(np.float64), 3)
@@ -48,8 +52,12 @@ def _near_tie(P, c, rel=2e-5):
     return (s[:, 1] - s[:, 0]) <= rel * scale + 1e-6
 
 
+# explicit25: D + 1 <= 64 (several pixels per wave instruction in the FP32 sums);
+# hyper and patch: D + 1 > 64 (64-dimension slices); hyper with r = 256: the
+# FP32 sums do not fit in LDS (FP64 sums in the block's slot)
 @pytest.mark.parametrize("kind,h,w,r", [("self3", 70, 90, 32), ("explicit2", 64, 64, 8),
-                                         ("hyper", 40, 36, 64), ("patch", 48, 40, 128)])
+                                         ("explicit25", 50, 46, 31), ("hyper", 40, 36, 64),
+                                         ("hyper", 40, 36, 256), ("patch", 48, 40, 128)])
 def test_seed_and_one_lloyd_step(kind, h, w, r):
     nkf = _nkf()
     f, p, guide, P = _case(kind, h, w)
