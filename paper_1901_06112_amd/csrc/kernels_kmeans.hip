@@ -192,6 +192,68 @@ __global__ __launch_bounds__(kBlock) void assign_generic_kernel(Guide g, int64_t
   }
 }
 
+// Per-cluster sums without atomics (D + 1 <= kBlock): thread t owns
+// dimension d = t % (D+1) (d = D is the count) of pixel stripe s = t / (D+1)
+// (ns = kBlock / (D+1) stripes, each a contiguous share of the block's
+// pixels).  It keeps a running FP32 sum while consecutive pixels of its
+// stripe share a label and adds it to its own LDS row sacc[s][L][d] when the
+// label changes: no other thread writes that word.  The stripes' rows are
+// added in stripe order, so the sums do not depend on timing.  Labels and
+// values are read eight pixels at a time, ahead of the sequential scan.
+constexpr int kOwnedBatch = 8;
+
+__global__ __launch_bounds__(kBlock) void accumulate_owned_kernel(Guide g, int64_t N, int64_t per_block,
+                                                                  const int *__restrict__ labels, int r,
+                                                                  double *__restrict__ partials) {
+  extern __shared__ float sacc[];  // [ns][r][D+1]
+  const int tid = threadIdx.x;
+  const int D = g.D, Dp = D + 1;
+  const int ns = kBlock / Dp;
+  const int rows = r * Dp;
+  for (int i = tid; i < ns * rows; i += kBlock) sacc[i] = 0.0f;
+  __syncthreads();
+  const int s = tid / Dp, d = tid - s * Dp;
+  if (s < ns) {
+    const int64_t x0 = (int64_t)blockIdx.x * per_block;
+    const int64_t x1 = x0 + per_block < N ? x0 + per_block : N;
+    const int64_t sp = (x1 - x0 + ns - 1) / ns;
+    const int64_t xs0 = x0 + s * sp;
+    const int64_t xs1 = xs0 + sp < x1 ? xs0 + sp : x1;
+    float *row = sacc + (size_t)s * rows;
+    float run = 0.0f;
+    int L = -1;
+    for (int64_t xb = xs0; xb < xs1; xb += kOwnedBatch) {
+      int lb[kOwnedBatch];
+      float vb[kOwnedBatch];
+#pragma unroll
+      for (int q = 0; q < kOwnedBatch; ++q) {
+        const int64_t x = xb + q;
+        const bool in = x < xs1;
+        lb[q] = in ? labels[x] : -1;
+        vb[q] = in ? (d < D ? guide_elem(g, x, d) : 1.0f) : 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < kOwnedBatch; ++q) {
+        if (lb[q] < 0) break;
+        if (lb[q] != L) {
+          if (L >= 0) row[L * Dp + d] += run;
+          run = 0.0f;
+          L = lb[q];
+        }
+        run += vb[q];
+      }
+    }
+    if (L >= 0) row[L * Dp + d] += run;
+  }
+  __syncthreads();
+  double *sums = partials + (size_t)blockIdx.x * rows;
+  for (int i = tid; i < rows; i += kBlock) {
+    double t = 0.0;
+    for (int q = 0; q < ns; ++q) t += (double)sacc[(size_t)q * rows + i];
+    sums[i] = t;
+  }
+}
+
 // Per-cluster sums of the guide values given labels, into this block's slot
 // partials[b][r][D+1]: accumulated in FP32 LDS when it fits (each block sums
 // at most a few thousand pixels), otherwise in FP64 directly in the slot
@@ -359,6 +421,21 @@ static hipError_t assign_accumulate(const Guide &g, const float *c, int r, doubl
   if (e != hipSuccess) return e;
   const size_t acc_bytes = sizeof(float) * (size_t)r * (g.D + 1);
   const int use_lds = acc_bytes <= 96 * 1024;
+  if (g.D + 1 <= kBlock) {
+    const int ns = kBlock / (g.D + 1);
+    const size_t own_bytes = acc_bytes * ns;
+    if (own_bytes <= 96 * 1024) {
+      // about 1024 pixels per block, at most kMaxPartialsGeneric blocks
+      *nparts = grid_for(N, 1024, kMaxPartialsGeneric);
+      const int64_t per_block = (N + *nparts - 1) / *nparts;
+      e = hipFuncSetAttribute(reinterpret_cast<const void *>(accumulate_owned_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)own_bytes);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(accumulate_owned_kernel, dim3(*nparts), dim3(kBlock), own_bytes, s, g, N, per_block, lab,
+                         r, partials);
+      return hipGetLastError();
+    }
+  }
   if (use_lds) {
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(accumulate_generic_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)acc_bytes);
