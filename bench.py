@@ -272,7 +272,8 @@ def leg_diff(steps, warmup):
         c = nkf.kmeans(ft, r=prm["r"], iters=prm["iters"], seed=prm["landmark_seed"])
         Q, al, F, reff = nkf.landmark_factor(c.cpu().numpy().astype(np.float64), prm["sigma_r"])
         G = torch.from_numpy(np.random.default_rng(1050 + i).normal(0, 1, f.shape).astype(np.float32)).cuda()
-        imgs.append((ft, c, Q, al, F, reff, G))
+        # the landmarks are fixed, so their factor stays on the device
+        imgs.append((ft, c, Q, al, torch.from_numpy(F).cuda(), reff, G))
     kw = dict(sigma_s=prm["sigma_s"], sigma_r=prm["sigma_r"], radius=prm["S"])
     npx = sum(h * w for h, w in sizes)
 

@@ -240,21 +240,30 @@ __global__ void minmax_kernel(const float *__restrict__ f, int64_t total, int C,
   }
 }
 
-// reps > 1: the replicated layout of the C <= 4 path
-__global__ void center_final_kernel(const unsigned *mm, int C, float *f0, int use_value, float value, int reps) {
+__global__ void center_final_kernel(const unsigned *mm, int C, float *f0, int use_value, float value) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= C) return;
   if (use_value) {
     f0[i] = value;
   } else {
-    unsigned a = mm[i], b = mm[C + i];
-    for (int q = 1; q < reps; ++q) {
-      a = min(a, mm[q * kMmSlot + i]);
-      b = max(b, mm[q * kMmSlot + C + i]);
-    }
-    const double lo = ord_decode(a), hi = ord_decode(b);
+    const double lo = ord_decode(mm[i]), hi = ord_decode(mm[C + i]);
     f0[i] = (float)(0.5 * (lo + hi));
   }
+}
+
+// The replicated layout of the C <= 4 path: wave c reduces channel c over
+// the kMmReps slots, one slot per lane.
+__global__ __launch_bounds__(256) void center_final_reps_kernel(const unsigned *mm, int C, float *f0) {
+  const int c = threadIdx.x / kWave, q = threadIdx.x % kWave;
+  if (c >= C) return;
+  unsigned a = q < kMmReps ? mm[q * kMmSlot + c] : 0xffffffffu;
+  unsigned b = q < kMmReps ? mm[q * kMmSlot + C + c] : 0u;
+#pragma unroll
+  for (int m = kWave / 2; m >= 1; m >>= 1) {
+    a = min(a, (unsigned)__shfl_xor((int)a, m, kWave));
+    b = max(b, (unsigned)__shfl_xor((int)b, m, kWave));
+  }
+  if (q == 0) f0[c] = (float)(0.5 * ((double)ord_decode(a) + (double)ord_decode(b)));
 }
 
 }  // namespace
@@ -263,7 +272,7 @@ hipError_t launch_center(const float *f, int64_t N, int C, double center, float 
                          hipStream_t s) {
   const int cb = (C + 255) / 256;
   if (isfinite(center)) {
-    hipLaunchKernelGGL(center_final_kernel, dim3(cb), dim3(256), 0, s, mm, C, f0, 1, (float)center, 1);
+    hipLaunchKernelGGL(center_final_kernel, dim3(cb), dim3(256), 0, s, mm, C, f0, 1, (float)center);
     return hipGetLastError();
   }
   hipError_t e;
@@ -279,7 +288,7 @@ hipError_t launch_center(const float *f, int64_t N, int C, double center, float 
       default: hipLaunchKernelGGL(minmax_small_kernel<4>, dim3(blocks), dim3(256), 0, s, f, total, mm); break;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(center_final_kernel, dim3(cb), dim3(256), 0, s, mm, C, f0, 0, 0.0f, kMmReps);
+    hipLaunchKernelGGL(center_final_reps_kernel, dim3(1), dim3(256), 0, s, mm, C, f0);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(mm_init_kernel, dim3(cb), dim3(256), 0, s, mm, C);
@@ -290,7 +299,7 @@ hipError_t launch_center(const float *f, int64_t N, int C, double center, float 
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(minmax_kernel, dim3((int)blocks), dim3(B), 2 * B * sizeof(unsigned), s, f, total, C, mm);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(center_final_kernel, dim3(cb), dim3(256), 0, s, mm, C, f0, 0, 0.0f, 1);
+  hipLaunchKernelGGL(center_final_kernel, dim3(cb), dim3(256), 0, s, mm, C, f0, 0, 0.0f);
   return hipGetLastError();
 }
 

@@ -279,8 +279,13 @@ def filter_landmarks(f, centroids, F, p=None, *, sigma_s=3.0, sigma_r=30.0, radi
     H, W, C = f.shape
     D = _guide_dim(f, p, guide, patch_radius)
     r = centroids.shape[0]
-    Ft = F if isinstance(F, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(F))
-    Ft = Ft.to(device=f.device, dtype=torch.float64).contiguous()
+    if isinstance(F, torch.Tensor):
+        Ft = F.to(device=f.device, dtype=torch.float64).contiguous()
+    else:
+        # a host factor goes through pinned memory, so the copy is queued on the
+        # stream instead of blocking until the stream drains
+        Fh = torch.from_numpy(np.ascontiguousarray(F, dtype=np.float64)).pin_memory()
+        Ft = Fh.to(device=f.device, non_blocking=True)
     r_eff = Ft.shape[1]
     prm = make_params(sigma_s=sigma_s, sigma_r=sigma_r, r=r, radius=radius, spatial=spatial, guide=guide,
                       patch_radius=patch_radius, precision=precision, center=center)
