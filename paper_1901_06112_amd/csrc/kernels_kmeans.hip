@@ -19,6 +19,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kMaxPartials = 1024;        // blocks of the small-D assignment
 constexpr int kMaxPartialsGeneric = 256;  // blocks of the generic accumulation
+constexpr int kMaxPartialsOwned = 1024;   // blocks of the owned-dimension accumulation
 
 __global__ void fill_f64_kernel(double *p, int64_t n, double v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -222,6 +223,17 @@ __global__ __launch_bounds__(kBlock) void accumulate_owned_kernel(Guide g, int64
     float *row = sacc + (size_t)s * rows;
     float run = 0.0f;
     int L = -1;
+    // patch guide: the thread's (dy, dx, channel) is fixed, and the pixel
+    // coordinates advance one column at a time along the stripe
+    const bool patch = g.kind == GUIDE_PATCH && d < D;
+    int pdy = 0, pdx = 0, pc = 0;
+    if (patch) {
+      const int T = 2 * g.pr + 1, q = d / g.C;
+      pc = d - q * g.C;
+      pdx = q % T - g.pr;
+      pdy = q / T - g.pr;
+    }
+    int cy = (int)(xs0 / g.W), cx = (int)(xs0 - (int64_t)cy * g.W);
     for (int64_t xb = xs0; xb < xs1; xb += kOwnedBatch) {
       int lb[kOwnedBatch];
       float vb[kOwnedBatch];
@@ -230,7 +242,18 @@ __global__ __launch_bounds__(kBlock) void accumulate_owned_kernel(Guide g, int64
         const int64_t x = xb + q;
         const bool in = x < xs1;
         lb[q] = in ? labels[x] : -1;
-        vb[q] = in ? (d < D ? guide_elem(g, x, d) : 1.0f) : 0.0f;
+        float v = 1.0f;
+        if (patch) {
+          const int yy = sym_index(cy + pdy, g.H), xq = sym_index(cx + pdx, g.W);
+          v = in ? g.f[((int64_t)yy * g.W + xq) * g.C + pc] : 0.0f;
+        } else if (d < D) {
+          v = in ? guide_elem(g, x, d) : 0.0f;
+        }
+        vb[q] = v;
+        if (++cx == g.W) {
+          cx = 0;
+          ++cy;
+        }
       }
 #pragma unroll
       for (int q = 0; q < kOwnedBatch; ++q) {
@@ -359,6 +382,12 @@ __global__ __launch_bounds__(kBlock) void update_kernel(const double *__restrict
   }
 }
 
+// the owned-dimension accumulation: D + 1 threads per stripe, and the
+// stripes' FP32 rows fit in 96 KB of LDS
+bool owned_applies(int r, int D) {
+  return D + 1 <= kBlock && sizeof(float) * (size_t)r * (D + 1) * (kBlock / (D + 1)) <= 96 * 1024;
+}
+
 int grid_for(int64_t n, int per_block, int cap) {
   int64_t b = (n + per_block - 1) / per_block;
   if (b > cap) b = cap;
@@ -421,20 +450,17 @@ static hipError_t assign_accumulate(const Guide &g, const float *c, int r, doubl
   if (e != hipSuccess) return e;
   const size_t acc_bytes = sizeof(float) * (size_t)r * (g.D + 1);
   const int use_lds = acc_bytes <= 96 * 1024;
-  if (g.D + 1 <= kBlock) {
-    const int ns = kBlock / (g.D + 1);
-    const size_t own_bytes = acc_bytes * ns;
-    if (own_bytes <= 96 * 1024) {
-      // about 1024 pixels per block, at most kMaxPartialsGeneric blocks
-      *nparts = grid_for(N, 1024, kMaxPartialsGeneric);
-      const int64_t per_block = (N + *nparts - 1) / *nparts;
-      e = hipFuncSetAttribute(reinterpret_cast<const void *>(accumulate_owned_kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)own_bytes);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(accumulate_owned_kernel, dim3(*nparts), dim3(kBlock), own_bytes, s, g, N, per_block, lab,
-                         r, partials);
-      return hipGetLastError();
-    }
+  if (owned_applies(r, g.D)) {
+    const size_t own_bytes = acc_bytes * (kBlock / (g.D + 1));
+    // about 1024 pixels per block: several blocks per CU even with one stripe
+    *nparts = grid_for(N, 1024, kMaxPartialsOwned);
+    const int64_t per_block = (N + *nparts - 1) / *nparts;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(accumulate_owned_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)own_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(accumulate_owned_kernel, dim3(*nparts), dim3(kBlock), own_bytes, s, g, N, per_block, lab, r,
+                       partials);
+    return hipGetLastError();
   }
   if (use_lds) {
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(accumulate_generic_kernel),
@@ -448,7 +474,8 @@ static hipError_t assign_accumulate(const Guide &g, const float *c, int r, doubl
 }
 
 size_t kmeans_partials_doubles(int r, int D) {
-  const int parts = D <= 4 ? kMaxPartials : kMaxPartialsGeneric;  // (the MFMA path: at most 256 blocks)
+  // (the MFMA path: at most 256 blocks)
+  const int parts = D <= 4 ? kMaxPartials : (owned_applies(r, D) ? kMaxPartialsOwned : kMaxPartialsGeneric);
   return (size_t)parts * r * (D + 1);
 }
 
