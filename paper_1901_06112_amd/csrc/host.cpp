@@ -446,6 +446,7 @@ struct KmBufs {
   int *lab_scratch;
   float *mu;
   void *lm;  // prepared 16-bit landmarks
+  float *ct; // transposed landmarks of the FP32 assignment
 };
 
 void carve_km(Carve &cv, const Resolved &rs, int r, KmBufs &b) {
@@ -453,6 +454,7 @@ void carve_km(Carve &cv, const Resolved &rs, int r, KmBufs &b) {
   b.lab_scratch = cv.take<int>(rs.N);
   b.mu = cv.take<float>(rs.D);
   b.lm = cv.take<unsigned char>(mfma_landmark_scratch_bytes(rs.g, r));
+  b.ct = cv.take<float>(kmeans_transposed_floats(r, rs.D));
 }
 
 nkf_status run_lloyd(nkf_ctx *ctx, const Resolved &rs, int r, float *c, int iters, int *labels,
@@ -468,7 +470,7 @@ nkf_status run_lloyd(nkf_ctx *ctx, const Resolved &rs, int r, float *c, int iter
   }
   for (int it = 0; it < iters; ++it)
     HIP_TRY(ctx, launch_kmeans_step(rs.g, c, r, b.sums, it + 1 == iters ? labels : nullptr, b.lab_scratch,
-                                    ctx->stream));
+                                    b.ct, ctx->stream));
   return NKF_OK;
 }
 

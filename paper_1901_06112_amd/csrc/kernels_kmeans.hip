@@ -126,50 +126,93 @@ __global__ __launch_bounds__(kBlock) void assign_small_kernel(const float *__res
 // ---- generic D: labels from a pixel tile in LDS ----------------------------
 constexpr int kTilePx = 64;
 
-__global__ __launch_bounds__(kBlock) void assign_generic_kernel(Guide g, int64_t N,
-                                                                const float *__restrict__ c, int r,
-                                                                int *__restrict__ labels) {
+// Register block of the generic assignment: clusters per distance pass.
+constexpr int kAssignRB = 8;
+
+// ct[d][k] = c[k][d] with rows padded to RP = r rounded up to kAssignRB
+// (zeros past r)
+__global__ void transpose_centroids_kernel(const float *__restrict__ c, int r, int D, int RP,
+                                           float *__restrict__ ct) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= D * RP) return;
+  const int d = e / RP, k = e - d * RP;
+  ct[e] = k < r ? c[k * D + d] : 0.0f;
+}
+
+// Nearest landmark of every pixel for any D (Algorithm 1, assignment): a
+// 64-pixel tile staged in LDS as [D][64]; wave kg scans the contiguous
+// cluster range [kg CW, (kg + 1) CW) (CW a multiple of kAssignRB) with the
+// landmarks transposed, so the clusters of a register block are 16-byte
+// scalar loads per dimension; the four waves' minima merge with the lower
+// index winning ties.  For a patch guide every thread stages dimensions
+// d = kg, kg + 4, ... of its own pixel, the patch offset of d read from a
+// per-block table.
+__global__ __launch_bounds__(kBlock) void assign_generic_kernel(Guide g, int64_t N, const float *__restrict__ ct,
+                                                                int RP, int r, int *__restrict__ labels) {
   extern __shared__ float smem[];
   float *pt = smem;                              // [D][64]
   float *sbest = smem + (size_t)g.D * kTilePx;   // [4][64]
   int *sidx = reinterpret_cast<int *>(sbest + 4 * kTilePx);
+  int *ptab = sidx + 4 * kTilePx;                // [D] channel | dx << 8 | dy << 16
   const int tid = threadIdx.x;
   const int px = tid & (kTilePx - 1);
   const int kg = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int D = g.D;
+  const bool patch = g.kind == GUIDE_PATCH;
+  if (patch) {
+    const int T = 2 * g.pr + 1;
+    for (int d = tid; d < D; d += kBlock) {
+      const int q = d / g.C;
+      ptab[d] = (d - q * g.C) | ((q % T) << 8) | ((q / T) << 16);
+    }
+  }
+  const int CW = ((r + 3) / 4 + kAssignRB - 1) / kAssignRB * kAssignRB;
+  const int k0 = kg * CW, k1 = min(r, k0 + CW);
   for (int64_t base = (int64_t)blockIdx.x * kTilePx; base < N; base += (int64_t)gridDim.x * kTilePx) {
     __syncthreads();
-    for (int e = tid; e < D * kTilePx; e += kBlock) {
-      const int d = e / kTilePx, q = e - d * kTilePx;
-      const int64_t x = base + q;
-      pt[e] = x < N ? guide_elem(g, x, d) : 0.0f;
+    if (patch) {
+      const int64_t x = base + px;
+      const int64_t xs = x < N ? x : N - 1;
+      const int y = (int)(xs / g.W), xx = (int)(xs - (int64_t)y * g.W);
+      for (int d = kg; d < D; d += 4) {
+        const int t = ptab[d];
+        const int yy = sym_index(y + (t >> 16) - g.pr, g.H);
+        const int xq = sym_index(xx + ((t >> 8) & 255) - g.pr, g.W);
+        const float v = g.f[((int64_t)yy * g.W + xq) * g.C + (t & 255)];
+        pt[d * kTilePx + px] = x < N ? v : 0.0f;
+      }
+    } else {
+      for (int e = tid; e < D * kTilePx; e += kBlock) {
+        const int d = e / kTilePx, q = e - d * kTilePx;
+        const int64_t x = base + q;
+        pt[e] = x < N ? guide_elem(g, x, d) : 0.0f;
+      }
     }
     __syncthreads();
     float best = FLT_MAX;
     int bi = 0;
-    // clusters k = kg + 4 * j, register-blocked four at a time
-    for (int j0 = 0; kg + 4 * j0 < r; j0 += 4) {
-      float acc[4] = {0.f, 0.f, 0.f, 0.f};
-      int kk[4];
+    for (int j0 = k0; j0 < k1; j0 += kAssignRB) {
+      float acc[kAssignRB];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = kg + 4 * (j0 + q);
-        kk[q] = k < r ? k : r - 1;
-      }
+      for (int q = 0; q < kAssignRB; ++q) acc[q] = 0.f;
       for (int d = 0; d < D; ++d) {
         const float v = pt[d * kTilePx + px];
+        const float4 *crow = reinterpret_cast<const float4 *>(ct + (size_t)d * RP + j0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float t = v - c[kk[q] * D + d];
-          acc[q] = fmaf(t, t, acc[q]);
+        for (int h = 0; h < kAssignRB / 4; ++h) {
+          const float4 cq = crow[h];
+          const float t0 = v - cq.x, t1 = v - cq.y, t2 = v - cq.z, t3 = v - cq.w;
+          acc[4 * h] = fmaf(t0, t0, acc[4 * h]);
+          acc[4 * h + 1] = fmaf(t1, t1, acc[4 * h + 1]);
+          acc[4 * h + 2] = fmaf(t2, t2, acc[4 * h + 2]);
+          acc[4 * h + 3] = fmaf(t3, t3, acc[4 * h + 3]);
         }
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = kg + 4 * (j0 + q);
-        if (k < r && acc[q] < best) {
+      for (int q = 0; q < kAssignRB; ++q) {
+        if (j0 + q < k1 && acc[q] < best) {
           best = acc[q];
-          bi = k;
+          bi = j0 + q;
         }
       }
     }
@@ -427,7 +470,7 @@ hipError_t launch_gather_landmarks(const Guide &g, const int64_t *idx, int r, fl
 }
 
 static hipError_t assign_accumulate(const Guide &g, const float *c, int r, double *partials, int *labels,
-                                    int *label_scratch, int *nparts, hipStream_t s) {
+                                    int *label_scratch, float *ct, int *nparts, hipStream_t s) {
   const bool contiguous = g.kind != GUIDE_PATCH || g.pr == 0;
   if (contiguous) {
     switch (g.D) {
@@ -440,12 +483,16 @@ static hipError_t assign_accumulate(const Guide &g, const float *c, int r, doubl
   }
   const int64_t N = (int64_t)g.H * g.W;
   int *lab = labels ? labels : label_scratch;
-  const size_t sm1 = sizeof(float) * ((size_t)g.D * kTilePx + 4 * kTilePx) + sizeof(int) * 4 * kTilePx;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(assign_generic_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1);
+  const size_t sm1 = sizeof(float) * ((size_t)g.D * kTilePx + 4 * kTilePx) + sizeof(int) * (4 * kTilePx + g.D);
+  const int RP = (r + kAssignRB - 1) / kAssignRB * kAssignRB;
+  hipLaunchKernelGGL(transpose_centroids_kernel, dim3((g.D * RP + 255) / 256), dim3(256), 0, s, c, r, g.D, RP, ct);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(assign_generic_kernel, dim3(grid_for(N, kTilePx, 8192)), dim3(kBlock), sm1, s, g, N,
-                     c, r, lab);
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(assign_generic_kernel),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(assign_generic_kernel, dim3(grid_for(N, kTilePx, 8192)), dim3(kBlock), sm1, s, g, N, ct,
+                     RP, r, lab);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t acc_bytes = sizeof(float) * (size_t)r * (g.D + 1);
@@ -473,6 +520,8 @@ static hipError_t assign_accumulate(const Guide &g, const float *c, int r, doubl
   return hipGetLastError();
 }
 
+size_t kmeans_transposed_floats(int r, int D) { return (size_t)D * (size_t)((r + kAssignRB - 1) / kAssignRB * kAssignRB); }
+
 size_t kmeans_partials_doubles(int r, int D) {
   // (the MFMA path: at most 256 blocks)
   const int parts = D <= 4 ? kMaxPartials : (owned_applies(r, D) ? kMaxPartialsOwned : kMaxPartialsGeneric);
@@ -490,9 +539,9 @@ hipError_t launch_kmeans_step_mfma(const Guide &g, float *c, int r, const float 
 }
 
 hipError_t launch_kmeans_step(const Guide &g, float *c, int r, double *partials, int *labels, int *label_scratch,
-                              hipStream_t s) {
+                              float *ct, hipStream_t s) {
   int nparts = 0;
-  hipError_t e = assign_accumulate(g, c, r, partials, labels, label_scratch, &nparts, s);
+  hipError_t e = assign_accumulate(g, c, r, partials, labels, label_scratch, ct, &nparts, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(update_kernel, dim3(r), dim3(kBlock), 0, s, partials, nparts, r, g.D,
                      static_cast<const float *>(nullptr), 0, c);

@@ -34,10 +34,13 @@ hipError_t launch_gather_landmarks(const Guide &g, const int64_t *idx, int r, fl
                                    hipStream_t s);
 // Size (doubles) of the per-block partial-sum buffer of one Lloyd step.
 size_t kmeans_partials_doubles(int r, int D);
+// Size (floats) of the transposed landmark copy [D][r rounded up to 8].
+size_t kmeans_transposed_floats(int r, int D);
 // One Lloyd iteration in place on c [r, D]: assignment (labels nullable),
-// per-block cluster sums into `partials`, ordered reduction and mean update.
+// per-block cluster sums into `partials`, ordered reduction and mean update;
+// ct is scratch of kmeans_transposed_floats(r, D) floats.
 hipError_t launch_kmeans_step(const Guide &g, float *c, int r, double *partials, int *labels,
-                              int *label_scratch, hipStream_t s);
+                              int *label_scratch, float *ct, hipStream_t s);
 
 // ---- kernels_mfma.hip -------------------------------------------------------
 // Distance step on MFMA with 16-bit centred operands (prec 1 = BF16, 2 = FP16).
