@@ -382,6 +382,7 @@ struct FwdBufs {
   float *F32;    // [r][r_eff] FP32 factor for the MFMA mix
   double *mpart; // partial sums of the centring offsets
   void *lm;      // prepared 16-bit landmarks
+  double *ct64;  // transposed FP64 landmarks of the FP32 embedding
 };
 
 void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r = kMaxLandmarks) {
@@ -394,6 +395,7 @@ void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r = kMa
   b.F32 = cv.take<float>((size_t)r * r_eff);
   b.mpart = cv.take<double>(guide_mean_scratch_doubles(rs.g));
   b.lm = cv.take<unsigned char>(mfma_landmark_scratch_bytes(rs.g, r));
+  b.ct64 = cv.take<double>(embed_scratch_doubles(rs.g, r));
 }
 
 // The landmark-independent part of the forward: the centring offsets f0 and,
@@ -417,7 +419,7 @@ nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, cons
       HIP_TRY(ctx, launch_embed_mfma(rs.g, c, prm->r, b.mu, F, b.F32, r_eff, prm->sigma_r, prm->prec, b.u,
                                      b.lm, ctx->stream));
     } else {
-      HIP_TRY(ctx, launch_embed(rs.g, c, prm->r, F, r_eff, prm->sigma_r, b.u, ctx->stream));
+      HIP_TRY(ctx, launch_embed(rs.g, c, prm->r, F, r_eff, prm->sigma_r, b.u, b.ct64, ctx->stream));
     }
   }
   if (!conv) return NKF_OK;

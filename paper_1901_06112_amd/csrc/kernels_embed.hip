@@ -23,26 +23,55 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Register block of the generic distance pass: clusters per pass.
+constexpr int kEmbedRB = 8;
+
+// ct64[d][k] = (double) c[k][d], rows padded to RP = r rounded up to
+// kEmbedRB with zeros.
+__global__ void transpose_landmarks64_kernel(const float *__restrict__ c, int r, int D, int RP,
+                                             double *__restrict__ ct64) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= D * RP) return;
+  const int d = e / RP, k = e - d * RP;
+  ct64[e] = k < r ? (double)c[k * D + d] : 0.0;
+}
+
 // Tiles of TPX pixels (64, or 32 when the FP64 b tile of 64 pixels would not
-// fit in LDS); thread groups of TPX lanes take landmarks kg, kg + NG, ...
+// fit in LDS); thread group kg (a wave when TPX = 64, a half-wave when 32)
+// takes landmarks [kg CW, (kg + 1) CW) in the distance pass and output planes
+// 8 kg, 8 kg + 8 NG, ... in the mix.
 // DS > 0 (D == DS <= 4): the pixel's guide values are held in FP64 registers
 // and the landmarks in FP64 in LDS, so a distance term is one subtraction and
-// one FMA.
+// one FMA.  DS == 0: the guide tile is staged in LDS as float [D][TPX] (a
+// patch guide through a per-block table of patch offsets) and the distances
+// run over kEmbedRB landmarks at a time with the transposed FP64 landmarks
+// ct64, eight independent FMA chains per lane.
 template <int TPX, int DS>
 __global__ __launch_bounds__(kBlock) void embed_kernel(Guide g, int64_t N, const float *__restrict__ c,
-                                                       int r, const double *__restrict__ F, int r_eff,
+                                                       const double *__restrict__ ct64, int RP, int r,
+                                                       const double *__restrict__ F, int r_eff,
                                                        double inv2s2, float *__restrict__ u) {
   constexpr int NG = kBlock / TPX;
   extern __shared__ double smem_d[];
   const int D = g.D;
   double *bs = smem_d;                                              // [r][TPX]
   float *pt = reinterpret_cast<float *>(smem_d + (size_t)r * TPX);  // [D][TPX]
+  int *ptab = reinterpret_cast<int *>(pt + (size_t)D * TPX);        // [D] channel | dx << 8 | dy << 16
   double *c64 = smem_d + (size_t)r * TPX;                           // DS > 0: [r][DS], in place of pt
   const int tid = threadIdx.x;
   const int px = tid & (TPX - 1);
-  const int kg = __builtin_amdgcn_readfirstlane(tid / TPX);
+  const int kg = TPX == kWave ? __builtin_amdgcn_readfirstlane(tid / TPX) : tid / TPX;
+  const bool patch = g.kind == GUIDE_PATCH;
   if constexpr (DS > 0) {
     for (int e = tid; e < r * DS; e += kBlock) c64[e] = (double)c[e];
+  } else {
+    if (patch) {
+      const int T = 2 * g.pr + 1;
+      for (int d = tid; d < D; d += kBlock) {
+        const int q = d / g.C;
+        ptab[d] = (d - q * g.C) | ((q % T) << 8) | ((q / T) << 16);
+      }
+    }
   }
   for (int64_t base = (int64_t)blockIdx.x * TPX; base < N; base += (int64_t)gridDim.x * TPX) {
     __syncthreads();
@@ -61,19 +90,43 @@ __global__ __launch_bounds__(kBlock) void embed_kernel(Guide g, int64_t N, const
         bs[k * TPX + px] = exp_neg64(acc * inv2s2);
       }
     } else {
-      for (int e = tid; e < D * TPX; e += kBlock) {
-        const int d = e / TPX, q = e - d * TPX;
-        const int64_t x = base + q;
-        pt[e] = x < N ? guide_elem(g, x, d) : 0.0f;
+      if (patch) {
+        const int64_t x = base + px;
+        const int64_t xs = x < N ? x : N - 1;
+        const int y = (int)(xs / g.W), xx = (int)(xs - (int64_t)y * g.W);
+        for (int d = kg; d < D; d += NG) {
+          const int t = ptab[d];
+          const int yy = sym_index(y + (t >> 16) - g.pr, g.H);
+          const int xq = sym_index(xx + ((t >> 8) & 255) - g.pr, g.W);
+          const float v = g.f[((int64_t)yy * g.W + xq) * g.C + (t & 255)];
+          pt[d * TPX + px] = x < N ? v : 0.0f;
+        }
+      } else {
+        for (int e = tid; e < D * TPX; e += kBlock) {
+          const int d = e / TPX, q = e - d * TPX;
+          const int64_t x = base + q;
+          pt[e] = x < N ? guide_elem(g, x, d) : 0.0f;
+        }
       }
       __syncthreads();
-      for (int k = kg; k < r; k += NG) {
-        double acc = 0.0;
+      const int CW = ((r + NG - 1) / NG + kEmbedRB - 1) / kEmbedRB * kEmbedRB;
+      const int k1 = min(r, (kg + 1) * CW);
+      for (int j0 = kg * CW; j0 < k1; j0 += kEmbedRB) {
+        double acc[kEmbedRB];
+#pragma unroll
+        for (int q = 0; q < kEmbedRB; ++q) acc[q] = 0.0;
         for (int d = 0; d < D; ++d) {
-          const double t = (double)pt[d * TPX + px] - (double)c[k * D + d];
-          acc = fma(t, t, acc);
+          const double v = (double)pt[d * TPX + px];
+          const double *crow = ct64 + (size_t)d * RP + j0;
+#pragma unroll
+          for (int q = 0; q < kEmbedRB; ++q) {
+            const double t = v - crow[q];
+            acc[q] = fma(t, t, acc[q]);
+          }
         }
-        bs[k * TPX + px] = exp_neg64(acc * inv2s2);
+#pragma unroll
+        for (int q = 0; q < kEmbedRB; ++q)
+          if (j0 + q < k1) bs[(j0 + q) * TPX + px] = exp_neg64(acc[q] * inv2s2);
       }
     }
     __syncthreads();
@@ -305,14 +358,20 @@ hipError_t launch_center(const float *f, int64_t N, int C, double center, float 
 
 size_t center_scratch_words(int C) { return C <= 4 ? (size_t)kMmReps * kMmSlot : 2 * (size_t)C; }
 
+size_t embed_scratch_doubles(const Guide &g, int r) {
+  const bool small = g.D <= 4 && g.kind != GUIDE_PATCH;
+  return small ? 0 : (size_t)g.D * (size_t)((r + kEmbedRB - 1) / kEmbedRB * kEmbedRB);
+}
+
 hipError_t launch_embed(const Guide &g, const float *c, int r, const double *F, int r_eff, double sigma_r,
-                        float *u, hipStream_t s) {
+                        float *u, double *ct64, hipStream_t s) {
   const int64_t N = (int64_t)g.H * g.W;
   const double inv2s2 = isinf(sigma_r) ? 0.0 : 1.0 / (2.0 * sigma_r * sigma_r);
   // DS > 0 keeps the landmarks as FP64 [r][D] where the generic form stages the guide tile
   const bool small = g.D <= 4 && g.kind != GUIDE_PATCH;
   auto lds = [&](int tpx) {
-    return sizeof(double) * r * tpx + std::max(sizeof(float) * g.D * tpx, small ? sizeof(double) * r * g.D : 0);
+    return sizeof(double) * r * tpx +
+           (small ? sizeof(double) * r * g.D : sizeof(float) * g.D * tpx + sizeof(int) * g.D);
   };
   const bool wide = lds(64) <= 160 * 1024;
   const int tpx = wide ? 64 : 32;
@@ -321,15 +380,21 @@ hipError_t launch_embed(const Guide &g, const float *c, int r, const double *F, 
   if (blocks > 16384) blocks = 16384;
   const int ds = small ? g.D : 0;
   const int key = (wide ? 100 : 0) + ds;
+  const int RP = (r + kEmbedRB - 1) / kEmbedRB * kEmbedRB;
   hipError_t e = hipSuccess;
+  if (!small) {
+    hipLaunchKernelGGL(transpose_landmarks64_kernel, dim3((g.D * RP + 255) / 256), dim3(256), 0, s, c, r, g.D, RP,
+                       ct64);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   switch (key) {
 #define NKF_EMBED(K, T, DSV)                                                                                  \
   case K:                                                                                                     \
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(embed_kernel<T, DSV>),                             \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);                             \
     if (e != hipSuccess) return e;                                                                            \
-    hipLaunchKernelGGL((embed_kernel<T, DSV>), dim3((unsigned)blocks), dim3(kBlock), sm, s, g, N, c, r, F,   \
-                       r_eff, inv2s2, u);                                                                     \
+    hipLaunchKernelGGL((embed_kernel<T, DSV>), dim3((unsigned)blocks), dim3(kBlock), sm, s, g, N, c, ct64, RP, \
+                       r, F, r_eff, inv2s2, u);                                                               \
     break;
     NKF_EMBED(100, 64, 0) NKF_EMBED(101, 64, 1) NKF_EMBED(102, 64, 2) NKF_EMBED(103, 64, 3) NKF_EMBED(104, 64, 4)
     NKF_EMBED(0, 32, 0) NKF_EMBED(1, 32, 1) NKF_EMBED(2, 32, 2) NKF_EMBED(3, 32, 3) NKF_EMBED(4, 32, 4)

@@ -72,8 +72,10 @@ size_t center_scratch_words(int C);
 hipError_t launch_center(const float *f, int64_t N, int C, double center, float *f0,
                          unsigned *scratch /*[2C]*/, hipStream_t s);
 // u[k][x] = sum_j F[j][k] exp(-|p(x) - c_j|^2 / (2 sigma_r^2)), planar [r_eff][N] float32.
+// ct64 is scratch of embed_scratch_doubles(g, r) doubles (transposed FP64 landmarks).
+size_t embed_scratch_doubles(const Guide &g, int r);
 hipError_t launch_embed(const Guide &g, const float *c, int r, const double *F, int r_eff,
-                        double sigma_r, float *u, hipStream_t s);
+                        double sigma_r, float *u, double *ct64, hipStream_t s);
 
 // ---- kernels_conv.hip -------------------------------------------------------
 struct ConvProblem {

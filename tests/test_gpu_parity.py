@@ -137,11 +137,14 @@ def test_tiny_images_and_single_landmark():
         _report(f"tiny{h}x{w}", g, go, eta, etao, TOL_255)
 
 
-def test_box_window_patch_guide():
+@pytest.mark.parametrize("r", [32, 256])
+def test_box_window_patch_guide(r):
+    """r = 256 with d = 147: the FP64 b tile of 64 pixels does not fit in LDS
+    beside the guide tile, so the embedding runs on 32-pixel tiles."""
     f, prm = synth.workload("color_nlm_1024", 64, 72)
     pg = exact.patch_guide(f.astype(np.float64), prm["patch_radius"])
     P = pg.reshape(-1, pg.shape[2])
-    c32 = _landmarks(P, 32, prm["landmark_seed"], 5)
+    c32 = _landmarks(P, r, prm["landmark_seed"], 5)
     g, eta, _ = _run_case(f, None, c32, 1.0, prm["sigma_r"], prm["S"], spatial="box", guide="patch",
                           patch_radius=prm["patch_radius"])
     go, etao = _oracle(f, pg, c32, 1.0, prm["sigma_r"], prm["S"], spatial="box")
@@ -155,7 +158,7 @@ def test_box_window_patch_guide():
     gg, oo = g.copy(), go.copy()
     gg[~keep] = 0.0
     oo[~keep] = 0.0
-    _report_conditioned("nlm_patch", f, pg, c32, 1.0, prm["sigma_r"], prm["S"], gg, oo, spatial="box")
+    _report_conditioned(f"nlm_patch_r{r}", f, pg, c32, 1.0, prm["sigma_r"], prm["S"], gg, oo, spatial="box")
 
 
 def test_hyperspectral_small():
