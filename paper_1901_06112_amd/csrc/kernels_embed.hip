@@ -36,8 +36,10 @@ __global__ void transpose_landmarks64_kernel(const float *__restrict__ c, int r,
   ct64[e] = k < r ? (double)c[k * D + d] : 0.0;
 }
 
-// Tiles of TPX pixels (64, or 32 when the FP64 b tile of 64 pixels would not
-// fit in LDS); thread group kg (a wave when TPX = 64, a half-wave when 32)
+// Blocks of BT threads (512 for the generic form, whose LDS tile leaves room
+// for one or two blocks per CU, so that each SIMD still holds two waves or
+// more) on tiles of TPX pixels (64, or 32 when the FP64 b tile of 64 pixels
+// would not fit in LDS); thread group kg (a wave when TPX = 64, a half-wave when 32)
 // takes landmarks [kg CW, (kg + 1) CW) in the distance pass and output planes
 // 8 kg, 8 kg + 8 NG, ... in the mix.
 // DS > 0 (D == DS <= 4): the pixel's guide values are held in FP64 registers
@@ -46,12 +48,12 @@ __global__ void transpose_landmarks64_kernel(const float *__restrict__ c, int r,
 // patch guide through a per-block table of patch offsets) and the distances
 // run over kEmbedRB landmarks at a time with the transposed FP64 landmarks
 // ct64, eight independent FMA chains per lane.
-template <int TPX, int DS>
-__global__ __launch_bounds__(kBlock) void embed_kernel(Guide g, int64_t N, const float *__restrict__ c,
-                                                       const double *__restrict__ ct64, int RP, int r,
-                                                       const double *__restrict__ F, int r_eff,
-                                                       double inv2s2, float *__restrict__ u) {
-  constexpr int NG = kBlock / TPX;
+template <int TPX, int DS, int BT>
+__global__ __launch_bounds__(BT) void embed_kernel(Guide g, int64_t N, const float *__restrict__ c,
+                                                   const double *__restrict__ ct64, int RP, int r,
+                                                   const double *__restrict__ F, int r_eff, double inv2s2,
+                                                   float *__restrict__ u) {
+  constexpr int NG = BT / TPX;
   extern __shared__ double smem_d[];
   const int D = g.D;
   double *bs = smem_d;                                              // [r][TPX]
@@ -63,11 +65,11 @@ __global__ __launch_bounds__(kBlock) void embed_kernel(Guide g, int64_t N, const
   const int kg = TPX == kWave ? __builtin_amdgcn_readfirstlane(tid / TPX) : tid / TPX;
   const bool patch = g.kind == GUIDE_PATCH;
   if constexpr (DS > 0) {
-    for (int e = tid; e < r * DS; e += kBlock) c64[e] = (double)c[e];
+    for (int e = tid; e < r * DS; e += BT) c64[e] = (double)c[e];
   } else {
     if (patch) {
       const int T = 2 * g.pr + 1;
-      for (int d = tid; d < D; d += kBlock) {
+      for (int d = tid; d < D; d += BT) {
         const int q = d / g.C;
         ptab[d] = (d - q * g.C) | ((q % T) << 8) | ((q / T) << 16);
       }
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void embed_kernel(Guide g, int64_t N, const
           pt[d * TPX + px] = x < N ? v : 0.0f;
         }
       } else {
-        for (int e = tid; e < D * TPX; e += kBlock) {
+        for (int e = tid; e < D * TPX; e += BT) {
           const int d = e / TPX, q = e - d * TPX;
           const int64_t x = base + q;
           pt[e] = x < N ? guide_elem(g, x, d) : 0.0f;
@@ -390,11 +392,11 @@ hipError_t launch_embed(const Guide &g, const float *c, int r, const double *F, 
   switch (key) {
 #define NKF_EMBED(K, T, DSV)                                                                                  \
   case K:                                                                                                     \
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(embed_kernel<T, DSV>),                             \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(embed_kernel<T, DSV, DSV ? 256 : 512>),            \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);                             \
     if (e != hipSuccess) return e;                                                                            \
-    hipLaunchKernelGGL((embed_kernel<T, DSV>), dim3((unsigned)blocks), dim3(kBlock), sm, s, g, N, c, ct64, RP, \
-                       r, F, r_eff, inv2s2, u);                                                               \
+    hipLaunchKernelGGL((embed_kernel<T, DSV, DSV ? 256 : 512>), dim3((unsigned)blocks), dim3(DSV ? 256 : 512), \
+                       sm, s, g, N, c, ct64, RP, r, F, r_eff, inv2s2, u);                                     \
     break;
     NKF_EMBED(100, 64, 0) NKF_EMBED(101, 64, 1) NKF_EMBED(102, 64, 2) NKF_EMBED(103, 64, 3) NKF_EMBED(104, 64, 4)
     NKF_EMBED(0, 32, 0) NKF_EMBED(1, 32, 1) NKF_EMBED(2, 32, 2) NKF_EMBED(3, 32, 3) NKF_EMBED(4, 32, 4)
