@@ -39,15 +39,17 @@ __global__ void transpose_landmarks64_kernel(const float *__restrict__ c, int r,
 // Blocks of BT threads (512 for the generic form, whose LDS tile leaves room
 // for one or two blocks per CU, so that each SIMD still holds two waves or
 // more) on tiles of TPX pixels (64, or 32 when the FP64 b tile of 64 pixels
-// would not fit in LDS); thread group kg (a wave when TPX = 64, a half-wave when 32)
-// takes landmarks [kg CW, (kg + 1) CW) in the distance pass and output planes
-// 8 kg, 8 kg + 8 NG, ... in the mix.
+// would not fit in LDS); thread group kg (a wave when TPX = 64, a half-wave
+// when 32) takes landmarks [kg CW, (kg + 1) CW) in the distance pass and
+// output planes 8 kg, 8 kg + 8 NG, ... in the mix.
 // DS > 0 (D == DS <= 4): the pixel's guide values are held in FP64 registers
 // and the landmarks in FP64 in LDS, so a distance term is one subtraction and
-// one FMA.  DS == 0: the guide tile is staged in LDS as float [D][TPX] (a
-// patch guide through a per-block table of patch offsets) and the distances
-// run over kEmbedRB landmarks at a time with the transposed FP64 landmarks
-// ct64, eight independent FMA chains per lane.
+// one FMA.  DS == 0: the distances run over kEmbedRB landmarks at a time with
+// the transposed FP64 landmarks ct64, eight independent FMA chains per lane.
+// An explicit or self guide is staged as float [D][TPX]; a patch guide takes
+// tiles of TPX pixels within one image row and stages only the window they
+// share, [2 pr + 1][TPX + 2 pr][C] (mirrored at the borders), walking the
+// patch dimensions d = (dy T + dx) C + c in that order.
 template <int TPX, int DS, int BT>
 __global__ __launch_bounds__(BT) void embed_kernel(Guide g, int64_t N, const float *__restrict__ c,
                                                    const double *__restrict__ ct64, int RP, int r,
@@ -57,31 +59,36 @@ __global__ __launch_bounds__(BT) void embed_kernel(Guide g, int64_t N, const flo
   extern __shared__ double smem_d[];
   const int D = g.D;
   double *bs = smem_d;                                              // [r][TPX]
-  float *pt = reinterpret_cast<float *>(smem_d + (size_t)r * TPX);  // [D][TPX]
-  int *ptab = reinterpret_cast<int *>(pt + (size_t)D * TPX);        // [D] channel | dx << 8 | dy << 16
+  float *pt = reinterpret_cast<float *>(smem_d + (size_t)r * TPX);  // [D][TPX], or the patch window
   double *c64 = smem_d + (size_t)r * TPX;                           // DS > 0: [r][DS], in place of pt
   const int tid = threadIdx.x;
   const int px = tid & (TPX - 1);
   const int kg = TPX == kWave ? __builtin_amdgcn_readfirstlane(tid / TPX) : tid / TPX;
-  const bool patch = g.kind == GUIDE_PATCH;
+  const bool patch = DS == 0 && g.kind == GUIDE_PATCH;
   if constexpr (DS > 0) {
     for (int e = tid; e < r * DS; e += BT) c64[e] = (double)c[e];
-  } else {
-    if (patch) {
-      const int T = 2 * g.pr + 1;
-      for (int d = tid; d < D; d += BT) {
-        const int q = d / g.C;
-        ptab[d] = (d - q * g.C) | ((q % T) << 8) | ((q / T) << 16);
-      }
-    }
   }
-  for (int64_t base = (int64_t)blockIdx.x * TPX; base < N; base += (int64_t)gridDim.x * TPX) {
+  const int T = 2 * g.pr + 1, WW = TPX + T - 1;
+  const int nch = (g.W + TPX - 1) / TPX;
+  const int64_t ntiles = patch ? (int64_t)g.H * nch : (N + TPX - 1) / TPX;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int64_t x;
+    bool valid;
+    int ty = 0, tx0 = 0;
+    if (patch) {
+      ty = (int)(tile / nch);
+      tx0 = (int)(tile - (int64_t)ty * nch) * TPX;
+      x = (int64_t)ty * g.W + tx0 + px;
+      valid = tx0 + px < g.W;
+    } else {
+      x = tile * TPX + px;
+      valid = x < N;
+    }
     __syncthreads();
     if constexpr (DS > 0) {
-      const int64_t x = base + px;
       double pv[DS > 0 ? DS : 1];
 #pragma unroll
-      for (int d = 0; d < DS; ++d) pv[d] = x < N ? (double)guide_elem(g, x, d) : 0.0;
+      for (int d = 0; d < DS; ++d) pv[d] = valid ? (double)guide_elem(g, x, d) : 0.0;
       for (int k = kg; k < r; k += NG) {
         double acc = 0.0;
 #pragma unroll
@@ -93,21 +100,25 @@ __global__ __launch_bounds__(BT) void embed_kernel(Guide g, int64_t N, const flo
       }
     } else {
       if (patch) {
-        const int64_t x = base + px;
-        const int64_t xs = x < N ? x : N - 1;
-        const int y = (int)(xs / g.W), xx = (int)(xs - (int64_t)y * g.W);
-        for (int d = kg; d < D; d += NG) {
-          const int t = ptab[d];
-          const int yy = sym_index(y + (t >> 16) - g.pr, g.H);
-          const int xq = sym_index(xx + ((t >> 8) & 255) - g.pr, g.W);
-          const float v = g.f[((int64_t)yy * g.W + xq) * g.C + (t & 255)];
-          pt[d * TPX + px] = x < N ? v : 0.0f;
+        // window rows ty - pr .. ty + pr, columns tx0 - pr .. tx0 + TPX - 1 + pr;
+        // columns past W - 1 + pr feed no valid pixel and are left at zero
+        const int rowlen = WW * g.C;
+        for (int e = tid; e < T * rowlen; e += BT) {
+          const int wr = e / rowlen, rem = e - wr * rowlen;
+          const int wc = rem / g.C, ch = rem - wc * g.C;
+          const int xs = tx0 - g.pr + wc;
+          float v = 0.0f;
+          if (xs < g.W + g.pr) {
+            const int yy = sym_index(ty - g.pr + wr, g.H), xq = sym_index(xs, g.W);
+            v = g.f[((int64_t)yy * g.W + xq) * g.C + ch];
+          }
+          pt[e] = v;
         }
       } else {
         for (int e = tid; e < D * TPX; e += BT) {
           const int d = e / TPX, q = e - d * TPX;
-          const int64_t x = base + q;
-          pt[e] = x < N ? guide_elem(g, x, d) : 0.0f;
+          const int64_t xe = tile * TPX + q;
+          pt[e] = xe < N ? guide_elem(g, xe, d) : 0.0f;
         }
       }
       __syncthreads();
@@ -117,13 +128,28 @@ __global__ __launch_bounds__(BT) void embed_kernel(Guide g, int64_t N, const flo
         double acc[kEmbedRB];
 #pragma unroll
         for (int q = 0; q < kEmbedRB; ++q) acc[q] = 0.0;
-        for (int d = 0; d < D; ++d) {
-          const double v = (double)pt[d * TPX + px];
-          const double *crow = ct64 + (size_t)d * RP + j0;
+        const double *crow = ct64 + j0;
+        if (patch) {
+          for (int dy = 0; dy < T; ++dy)
+            for (int dx = 0; dx < T; ++dx) {
+              const float *wp = pt + (dy * WW + dx + px) * g.C;
+              for (int ch = 0; ch < g.C; ++ch, crow += RP) {
+                const double v = (double)wp[ch];
 #pragma unroll
-          for (int q = 0; q < kEmbedRB; ++q) {
-            const double t = v - crow[q];
-            acc[q] = fma(t, t, acc[q]);
+                for (int q = 0; q < kEmbedRB; ++q) {
+                  const double t = v - crow[q];
+                  acc[q] = fma(t, t, acc[q]);
+                }
+              }
+            }
+        } else {
+          for (int d = 0; d < D; ++d, crow += RP) {
+            const double v = (double)pt[d * TPX + px];
+#pragma unroll
+            for (int q = 0; q < kEmbedRB; ++q) {
+              const double t = v - crow[q];
+              acc[q] = fma(t, t, acc[q]);
+            }
           }
         }
 #pragma unroll
@@ -132,7 +158,6 @@ __global__ __launch_bounds__(BT) void embed_kernel(Guide g, int64_t N, const flo
       }
     }
     __syncthreads();
-    const int64_t x = base + px;
     // thread group kg mixes output planes kb .. kb+7 (kb = 8 kg, 8 kg + 8 NG, ...):
     // one b read and one contiguous row segment of F per k feed 8 FMA chains
     for (int kb = 8 * kg; kb < r_eff; kb += 8 * NG) {
@@ -153,7 +178,7 @@ __global__ __launch_bounds__(BT) void embed_kernel(Guide g, int64_t N, const flo
             if (kb + q < r_eff) acc[q] = fma(Fr[q], bv, acc[q]);
         }
       }
-      if (x < N) {
+      if (valid) {
 #pragma unroll
         for (int q = 0; q < 8; ++q)
           if (kb + q < r_eff) u[(int64_t)(kb + q) * N + x] = (float)acc[q];
@@ -371,14 +396,18 @@ hipError_t launch_embed(const Guide &g, const float *c, int r, const double *F, 
   const double inv2s2 = isinf(sigma_r) ? 0.0 : 1.0 / (2.0 * sigma_r * sigma_r);
   // DS > 0 keeps the landmarks as FP64 [r][D] where the generic form stages the guide tile
   const bool small = g.D <= 4 && g.kind != GUIDE_PATCH;
+  const bool patch = g.kind == GUIDE_PATCH;
+  const int T = 2 * g.pr + 1;
   auto lds = [&](int tpx) {
-    return sizeof(double) * r * tpx +
-           (small ? sizeof(double) * r * g.D : sizeof(float) * g.D * tpx + sizeof(int) * g.D);
+    const size_t stage = small ? sizeof(double) * r * g.D
+                         : patch ? sizeof(float) * T * (tpx + T - 1) * g.C
+                                 : sizeof(float) * g.D * tpx;
+    return sizeof(double) * r * tpx + stage;
   };
   const bool wide = lds(64) <= 160 * 1024;
   const int tpx = wide ? 64 : 32;
   const size_t sm = lds(tpx);
-  int64_t blocks = (N + tpx - 1) / tpx;
+  int64_t blocks = patch ? (int64_t)g.H * ((g.W + tpx - 1) / tpx) : (N + tpx - 1) / tpx;
   if (blocks > 16384) blocks = 16384;
   const int ds = small ? g.D : 0;
   const int key = (wide ? 100 : 0) + ds;

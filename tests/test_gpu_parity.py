@@ -139,8 +139,7 @@ def test_tiny_images_and_single_landmark():
 
 @pytest.mark.parametrize("r", [32, 256])
 def test_box_window_patch_guide(r):
-    """r = 256 with d = 147: the FP64 b tile of 64 pixels does not fit in LDS
-    beside the guide tile, so the embedding runs on 32-pixel tiles."""
+    """W = 72: the embedding's row tiles of 64 pixels end in a partial tile."""
     f, prm = synth.workload("color_nlm_1024", 64, 72)
     pg = exact.patch_guide(f.astype(np.float64), prm["patch_radius"])
     P = pg.reshape(-1, pg.shape[2])
@@ -159,6 +158,19 @@ def test_box_window_patch_guide(r):
     gg[~keep] = 0.0
     oo[~keep] = 0.0
     _report_conditioned(f"nlm_patch_r{r}", f, pg, c32, 1.0, prm["sigma_r"], prm["S"], gg, oo, spatial="box")
+
+
+def test_explicit_wide_guide_many_landmarks():
+    """d = 160, r = 256: the FP64 b tile of 64 pixels and the guide tile do not
+    fit in LDS together, so the embedding runs on 32-pixel tiles."""
+    f, prm = synth.workload("hyperspectral_512x128", 32, 37)
+    p = np.concatenate([f, f[:, :, :32] ** 2], axis=2)
+    P = p.reshape(-1, p.shape[2]).astype(np.float64)
+    c32 = _landmarks(P, 256, prm["landmark_seed"], 5)
+    g, eta, _ = _run_case(f, p, c32, prm["sigma_s"], prm["sigma_r"], prm["S"])
+    go, etao = _oracle(f, p, c32, prm["sigma_s"], prm["sigma_r"], prm["S"])
+    _report_conditioned("explicit160_r256", f, p, c32, prm["sigma_s"], prm["sigma_r"], prm["S"], g, go,
+                        tol=TOL_255 / 255)
 
 
 def test_hyperspectral_small():
