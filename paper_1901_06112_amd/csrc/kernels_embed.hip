@@ -128,26 +128,21 @@ __global__ __launch_bounds__(BT) void embed_kernel(Guide g, int64_t N, const flo
         double acc[kEmbedRB];
 #pragma unroll
         for (int q = 0; q < kEmbedRB; ++q) acc[q] = 0.0;
-        const double *crow = ct64 + j0;
-        if (patch) {
-          for (int dy = 0; dy < T; ++dy)
-            for (int dx = 0; dx < T; ++dx) {
-              const float *wp = pt + (dy * WW + dx + px) * g.C;
-              for (int ch = 0; ch < g.C; ++ch, crow += RP) {
-                const double v = (double)wp[ch];
-#pragma unroll
-                for (int q = 0; q < kEmbedRB; ++q) {
-                  const double t = v - crow[q];
-                  acc[q] = fma(t, t, acc[q]);
-                }
-              }
-            }
-        } else {
-          for (int d = 0; d < D; ++d, crow += RP) {
-            const double v = (double)pt[d * TPX + px];
+        // runs of dimensions that are evenly spaced in the staged tile and
+        // consecutive in ct64: a patch row (T C values, d = (dy T + dx) C + c)
+        // per dy, else all D
+        const int runs = patch ? T : 1, run = patch ? T * g.C : D;
+        const int wstride = patch ? 1 : TPX;
+        for (int rw = 0; rw < runs; ++rw) {
+          const float *wp = patch ? pt + (rw * WW + px) * g.C : pt + px;
+          const double *crow = ct64 + (size_t)rw * run * RP + j0;
+#pragma unroll 4
+          for (int e = 0; e < run; ++e) {
+            const double v = (double)wp[e * wstride];
+            const double *cr = crow + (size_t)e * RP;
 #pragma unroll
             for (int q = 0; q < kEmbedRB; ++q) {
-              const double t = v - crow[q];
+              const double t = v - cr[q];
               acc[q] = fma(t, t, acc[q]);
             }
           }
