@@ -195,6 +195,8 @@ __global__ __launch_bounds__(kBlock) void assign_generic_kernel(Guide g, int64_t
       float acc[kAssignRB];
 #pragma unroll
       for (int q = 0; q < kAssignRB; ++q) acc[q] = 0.f;
+      // unrolled so that the scalar landmark loads of four steps are in flight together
+#pragma unroll 4
       for (int d = 0; d < D; ++d) {
         const float v = pt[d * kTilePx + px];
         const float4 *crow = reinterpret_cast<const float4 *>(ct + (size_t)d * RP + j0);
