@@ -238,16 +238,22 @@ __global__ __launch_bounds__(kBlock) void assign_generic_kernel(Guide g, int64_t
   }
 }
 
-// Per-cluster sums without atomics (D + 1 <= kBlock): thread t owns
+// Per-cluster sums without contention (D + 1 <= kBlock): thread t owns
 // dimension d = t % (D+1) (d = D is the count) of pixel stripe s = t / (D+1)
 // (ns = kBlock / (D+1) stripes, each a contiguous share of the block's
 // pixels).  It keeps a running FP32 sum while consecutive pixels of its
-// stripe share a label and adds it to its own LDS row sacc[s][L][d] when the
-// label changes: no other thread writes that word.  The stripes' rows are
-// added in stripe order, so the sums do not depend on timing.  Labels and
-// values are read eight pixels at a time, ahead of the sequential scan.
-constexpr int kOwnedBatch = 8;
+// stripe share a label and adds it to its own LDS word sacc[s][L][d] when the
+// label changes (no other thread touches that word, so the sum and its order
+// are fixed; a plain read and write, which measured faster than LDS atomics).
+// The stripes' rows are added in stripe order, so the sums do not depend on
+// timing.  Labels and values are read kOwnedBatch pixels at a time, ahead of
+// the sequential scan, with every address in bounds: a slot past the stripe
+// repeats the last label with value 0.  PATCH: the thread's (dy, dx, channel)
+// is fixed and the pixel coordinates advance one column at a time; otherwise
+// the value is p[x D + d] (an explicit guide, or the image itself, D = C).
+constexpr int kOwnedBatch = 16;
 
+template <bool PATCH>
 __global__ __launch_bounds__(kBlock) void accumulate_owned_kernel(Guide g, int64_t N, int64_t per_block,
                                                                   const int *__restrict__ labels, int r,
                                                                   double *__restrict__ partials) {
@@ -265,53 +271,59 @@ __global__ __launch_bounds__(kBlock) void accumulate_owned_kernel(Guide g, int64
     const int64_t sp = (x1 - x0 + ns - 1) / ns;
     const int64_t xs0 = x0 + s * sp;
     const int64_t xs1 = xs0 + sp < x1 ? xs0 + sp : x1;
-    float *row = sacc + (size_t)s * rows;
-    float run = 0.0f;
-    int L = -1;
-    // patch guide: the thread's (dy, dx, channel) is fixed, and the pixel
-    // coordinates advance one column at a time along the stripe
-    const bool patch = g.kind == GUIDE_PATCH && d < D;
-    int pdy = 0, pdx = 0, pc = 0;
-    if (patch) {
-      const int T = 2 * g.pr + 1, q = d / g.C;
-      pc = d - q * g.C;
-      pdx = q % T - g.pr;
-      pdy = q / T - g.pr;
-    }
-    int cy = (int)(xs0 / g.W), cx = (int)(xs0 - (int64_t)cy * g.W);
-    for (int64_t xb = xs0; xb < xs1; xb += kOwnedBatch) {
-      int lb[kOwnedBatch];
-      float vb[kOwnedBatch];
+    if (xs0 < xs1) {
+      float *row = sacc + (size_t)s * rows + d;
+      const bool cnt = d == D;
+      const int dd = cnt ? 0 : d;
+      int pdy = 0, pdx = 0, pc = 0;
+      if (PATCH) {
+        const int T = 2 * g.pr + 1, q = dd / g.C;
+        pc = dd - q * g.C;
+        pdx = q % T - g.pr;
+        pdy = q / T - g.pr;
+      }
+      const float *src = g.kind == GUIDE_EXPLICIT ? g.p : g.f;
+      int cy = (int)(xs0 / g.W), cx = (int)(xs0 - (int64_t)cy * g.W);
+      float run = 0.0f;
+      int L = labels[xs0];
+      for (int64_t xb = xs0; xb < xs1; xb += kOwnedBatch) {
+        int lb[kOwnedBatch];
+        float vb[kOwnedBatch];
+        int lprev = L;
 #pragma unroll
-      for (int q = 0; q < kOwnedBatch; ++q) {
-        const int64_t x = xb + q;
-        const bool in = x < xs1;
-        lb[q] = in ? labels[x] : -1;
-        float v = 1.0f;
-        if (patch) {
-          const int yy = sym_index(cy + pdy, g.H), xq = sym_index(cx + pdx, g.W);
-          v = in ? g.f[((int64_t)yy * g.W + xq) * g.C + pc] : 0.0f;
-        } else if (d < D) {
-          v = in ? guide_elem(g, x, d) : 0.0f;
+        for (int q = 0; q < kOwnedBatch; ++q) {
+          const int64_t x = xb + q;
+          const bool in = x < xs1;
+          const int64_t xa = in ? x : xs1 - 1;
+          const int lab = labels[xa];
+          float v;
+          if (PATCH) {
+            // cy passes H - 1 only after the image's last pixel; clamp it for the address
+            const int yy = sym_index(min(cy, g.H - 1) + pdy, g.H), xq = sym_index(cx + pdx, g.W);
+            v = g.f[((int64_t)yy * g.W + xq) * g.C + pc];
+            const int cx1 = cx + 1;
+            const bool wrap = cx1 == g.W;
+            cx = wrap ? 0 : cx1;
+            cy = wrap ? cy + 1 : cy;
+          } else {
+            v = src[xa * D + dd];
+          }
+          lb[q] = in ? lab : lprev;
+          lprev = lb[q];
+          vb[q] = in ? (cnt ? 1.0f : v) : 0.0f;
         }
-        vb[q] = v;
-        if (++cx == g.W) {
-          cx = 0;
-          ++cy;
+#pragma unroll
+        for (int q = 0; q < kOwnedBatch; ++q) {
+          if (lb[q] != L) {
+            row[(size_t)L * Dp] += run;
+            run = 0.0f;
+            L = lb[q];
+          }
+          run += vb[q];
         }
       }
-#pragma unroll
-      for (int q = 0; q < kOwnedBatch; ++q) {
-        if (lb[q] < 0) break;
-        if (lb[q] != L) {
-          if (L >= 0) row[L * Dp + d] += run;
-          run = 0.0f;
-          L = lb[q];
-        }
-        run += vb[q];
-      }
+      row[(size_t)L * Dp] += run;
     }
-    if (L >= 0) row[L * Dp + d] += run;
   }
   __syncthreads();
   double *sums = partials + (size_t)blockIdx.x * rows;
@@ -504,11 +516,11 @@ static hipError_t assign_accumulate(const Guide &g, const float *c, int r, doubl
     // about 1024 pixels per block: several blocks per CU even with one stripe
     *nparts = grid_for(N, 1024, kMaxPartialsOwned);
     const int64_t per_block = (N + *nparts - 1) / *nparts;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(accumulate_owned_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)own_bytes);
+    auto *kern = g.kind == GUIDE_PATCH ? accumulate_owned_kernel<true> : accumulate_owned_kernel<false>;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)own_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(accumulate_owned_kernel, dim3(*nparts), dim3(kBlock), own_bytes, s, g, N, per_block, lab, r,
-                       partials);
+    hipLaunchKernelGGL(kern, dim3(*nparts), dim3(kBlock), own_bytes, s, g, N, per_block, lab, r, partials);
     return hipGetLastError();
   }
   if (use_lds) {
