@@ -113,33 +113,29 @@ __global__ void pca_cov_final_kernel(const double *__restrict__ cpart, int nchun
   cov[e] = s / ns;
 }
 
-// g(x) = (p(x) - mu) V for one pixel per thread; V and mu in LDS.
+// g(x) = (p(x) - mu) V for one pixel per thread.  The patch dimension d is
+// the same in every lane, so row d of V and mu[d] are scalar loads (through
+// the scalar cache, each FMA takes its V entry from an SGPR pair); a patch
+// row of T C values is walked with its mirrored column offsets fixed per lane.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void pca_project_kernel(Guide g, int64_t N, const double *__restrict__ mu,
                                                              const double *__restrict__ V,
                                                              float *__restrict__ out) {
-  extern __shared__ double sm[];
-  const int D = g.D;
-  double *Vs = sm;              // [D][DIM]
-  double *ms = sm + D * DIM;    // [D]
-  for (int e = threadIdx.x; e < D * DIM; e += kBlock) Vs[e] = V[e];
-  for (int e = threadIdx.x; e < D; e += kBlock) ms[e] = mu[e];
-  __syncthreads();
   const int T = 2 * g.pr + 1, C = g.C;
   for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < N; x += (int64_t)gridDim.x * kBlock) {
     double acc[DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) acc[k] = 0.0;
     const int y = (int)(x / g.W), xx = (int)(x - (int64_t)y * g.W);
-    int d = 0;
+    const double *vr = V;
+    const double *mr = mu;
     for (int dy = 0; dy < T; ++dy) {
       const int yy = sym_index(y + dy - g.pr, g.H);
       const float *row = g.f + (int64_t)yy * g.W * C;
       for (int dx = 0; dx < T; ++dx) {
         const float *px = row + (int64_t)sym_index(xx + dx - g.pr, g.W) * C;
-        for (int c = 0; c < C; ++c, ++d) {
-          const double v = (double)px[c] - ms[d];
-          const double *vr = Vs + d * DIM;
+        for (int c = 0; c < C; ++c, vr += DIM, ++mr) {
+          const double v = (double)px[c] - *mr;
 #pragma unroll
           for (int k = 0; k < DIM; ++k) acc[k] = fma(v, vr[k], acc[k]);
         }
@@ -154,13 +150,9 @@ __global__ __launch_bounds__(kBlock) void pca_project_kernel(Guide g, int64_t N,
 template <int DIM>
 hipError_t launch_project_dim(const Guide &g, const double *mu, const double *V, float *out, hipStream_t s) {
   const int64_t N = (int64_t)g.H * g.W;
-  const size_t sm = sizeof(double) * ((size_t)g.D * DIM + g.D);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(pca_project_kernel<DIM>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-  if (e != hipSuccess) return e;
   int64_t blocks = (N + kBlock - 1) / kBlock;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(pca_project_kernel<DIM>, dim3((int)blocks), dim3(kBlock), sm, s, g, N, mu, V, out);
+  hipLaunchKernelGGL(pca_project_kernel<DIM>, dim3((int)blocks), dim3(kBlock), 0, s, g, N, mu, V, out);
   return hipGetLastError();
 }
 
