@@ -146,8 +146,10 @@ nkf_status nkf_kmeans_iterate(nkf_ctx *ctx, int H, int W, int C, const float *f,
  * explicit guide with D = dim.  eigvals_host (nullable, host [dim]): the kept
  * eigenvalues.  Limits: (2pr+1)^2 C <= 256 (else NKF_ERR_UNSUPPORTED) and
  * 1 <= dim <= min((2pr+1)^2 C, 32) (else NKF_ERR_INVALID_ARG).  Synchronises
- * the stream once (the covariance is decomposed on the host);
- * NKF_ERR_NUMERICAL if that eigensolver does not converge. */
+ * the stream once: the covariance is decomposed on the host (Householder
+ * tridiagonalisation, its eigenvalues by implicit QR, the `dim` leading
+ * eigenvectors by inverse iteration); NKF_ERR_NUMERICAL if that does not
+ * converge. */
 nkf_status nkf_patch_pca(nkf_ctx *ctx, int H, int W, int C, const float *f, int patch_radius, int dim,
                          uint64_t seed, float *guide_out, double *eigvals_host);
 

@@ -17,6 +17,7 @@
 
 namespace nkf {
 int sym_eig(int n, const double *A, double *w, double *V);
+int sym_eig_top(int n, const double *A, int k, double *w, double *V);
 }
 
 using namespace nkf;
@@ -731,18 +732,18 @@ nkf_status nkf_patch_pca(nkf_ctx *ctx, int H, int W, int C, const float *f, int 
   HIP_TRY(ctx, launch_pca_moments(g, idx_dev, ns, mb, cc, S, part, mu, cpart, cov, ctx->stream));
   HIP_TRY(ctx, hipMemcpyAsync(cov_host, cov, sizeof(double) * D * D, hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  std::vector<double> w(D), Q((size_t)D * D);
-  if (sym_eig(D, cov_host, w.data(), Q.data()) != 0)
+  // the dim largest eigenpairs (ascending in w, Q: D x dim)
+  std::vector<double> w(dim), Q((size_t)D * dim);
+  if (sym_eig_top(D, cov_host, dim, w.data(), Q.data()) != 0)
     return fail(ctx, NKF_ERR_NUMERICAL, "eigendecomposition of the patch covariance did not converge");
-  // the dim largest eigenvalues, descending; each vector's largest-magnitude
-  // entry (the first on ties) made positive
+  // descending; each vector's largest-magnitude entry (the first on ties) made positive
   for (int k = 0; k < dim; ++k) {
-    const int col = D - 1 - k;
+    const int col = dim - 1 - k;
     int jm = 0;
     for (int j = 1; j < D; ++j)
-      if (fabs(Q[(size_t)j * D + col]) > fabs(Q[(size_t)jm * D + col])) jm = j;
-    const double sg = Q[(size_t)jm * D + col] < 0.0 ? -1.0 : 1.0;
-    for (int j = 0; j < D; ++j) V_host[(size_t)j * dim + k] = sg * Q[(size_t)j * D + col];
+      if (fabs(Q[(size_t)j * dim + col]) > fabs(Q[(size_t)jm * dim + col])) jm = j;
+    const double sg = Q[(size_t)jm * dim + col] < 0.0 ? -1.0 : 1.0;
+    for (int j = 0; j < D; ++j) V_host[(size_t)j * dim + k] = sg * Q[(size_t)j * dim + col];
     if (eigvals_host) eigvals_host[k] = w[col];
   }
   HIP_TRY(ctx, hipMemcpyAsync(V, V_host, sizeof(double) * D * dim, hipMemcpyHostToDevice, ctx->stream));
