@@ -312,7 +312,7 @@ def main():
     ap.add_argument("--cpu-crop", type=int, default=1024)
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
     ap.add_argument("--leg", choices=sorted(LEGS), help="run one other workload only")
-    ap.add_argument("--leg-steps", type=int, default=3)
+    ap.add_argument("--leg-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, metavar="BYTES",
                     help="only run device copies of BYTES bytes (counter calibration)")
     a = ap.parse_args()
