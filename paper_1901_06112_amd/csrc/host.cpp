@@ -42,6 +42,7 @@ struct nkf_ctx {
   double host_ms[NKF_STAGE_COUNT] = {0};
   int host_count[NKF_STAGE_COUNT] = {0};
   hipEvent_t copy_done = nullptr;  // the landmark copy of nkf_filter
+  hipEvent_t pinned_free = nullptr;  // after the last queued copy through `pinned`
   // the last PCA sample draw (it depends on N and the seed only)
   int64_t pca_draw_N = -1;
   uint64_t pca_draw_seed = 0;
@@ -169,6 +170,21 @@ nkf_status ensure_pinned(nkf_ctx *ctx, size_t bytes) {
   }
   ctx->pinned = static_cast<char *>(p);
   ctx->pinned_bytes = bytes;
+  return NKF_OK;
+}
+
+// The pinned staging buffer is shared by the entry points of a context: each
+// records pinned_free after its last queued copy through it, and a call about
+// to write it from the host waits for that event, not for the whole stream,
+// so a call's host work can start while the previous call's kernels run.
+nkf_status pinned_acquire(nkf_ctx *ctx) {
+  if (ctx->pinned_free) HIP_TRY(ctx, hipEventSynchronize(ctx->pinned_free));
+  return NKF_OK;
+}
+
+nkf_status pinned_release(nkf_ctx *ctx) {
+  if (!ctx->pinned_free) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->pinned_free, hipEventDisableTiming));
+  HIP_TRY(ctx, hipEventRecord(ctx->pinned_free, ctx->stream));
   return NKF_OK;
 }
 
@@ -481,11 +497,12 @@ nkf_status run_seed(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, flo
   const int r = prm->r;
   nkf_status st = ensure_pinned(ctx, 64 * 1024 + sizeof(int64_t) * r);
   if (st != NKF_OK) return st;
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // pinned buffer may still feed an earlier copy
+  if ((st = pinned_acquire(ctx)) != NKF_OK) return st;
   int64_t *idx = reinterpret_cast<int64_t *>(ctx->pinned);
   draw_indices(rs.N, r, prm->seed, idx);
   StageTimer tm(ctx, NKF_STAGE_SEED);
   HIP_TRY(ctx, hipMemcpyAsync(idx_dev, idx, sizeof(int64_t) * r, hipMemcpyHostToDevice, ctx->stream));
+  if ((st = pinned_release(ctx)) != NKF_OK) return st;
   HIP_TRY(ctx, launch_gather_landmarks(rs.g, idx_dev, r, c, ctx->stream));
   return NKF_OK;
 }
@@ -584,6 +601,7 @@ nkf_status nkf_destroy(nkf_ctx *ctx) {
   }
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
   if (ctx->copy_done) (void)hipEventDestroy(ctx->copy_done);
+  if (ctx->pinned_free) (void)hipEventDestroy(ctx->pinned_free);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
@@ -723,8 +741,8 @@ nkf_status nkf_patch_pca(nkf_ctx *ctx, int H, int W, int C, const float *f, int 
       ctx->pca_draw_N = N;
       ctx->pca_draw_seed = seed;
     }
-    // the stream may still read the pinned buffer from an earlier call
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    // an earlier call's copy may still read the pinned buffer
+    if ((st = pinned_acquire(ctx)) != NKF_OK) return st;
     memcpy(idx_host, ctx->pca_draw.data(), sizeof(int64_t) * ns);
     HIP_TRY(ctx, hipMemcpyAsync(idx, idx_host, sizeof(int64_t) * ns, hipMemcpyHostToDevice, ctx->stream));
     idx_dev = idx;
@@ -747,6 +765,7 @@ nkf_status nkf_patch_pca(nkf_ctx *ctx, int H, int W, int C, const float *f, int 
     if (eigvals_host) eigvals_host[k] = w[col];
   }
   HIP_TRY(ctx, hipMemcpyAsync(V, V_host, sizeof(double) * D * dim, hipMemcpyHostToDevice, ctx->stream));
+  if ((st = pinned_release(ctx)) != NKF_OK) return st;
   HIP_TRY(ctx, launch_pca_project(g, mu, V, dim, guide_out, ctx->stream));
   return NKF_OK;
 }
@@ -821,6 +840,7 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
     for (int i = 0; i < r; ++i)
       for (int j = 0; j < r_eff; ++j) F_host[i * r_eff + j] = Fr[i * r + j];
     HIP_TRY(ctx, hipMemcpyAsync(Fd, F_host, sizeof(double) * r * r_eff, hipMemcpyHostToDevice, ctx->stream));
+    if ((st = pinned_release(ctx)) != NKF_OK) return st;
   }
   if (r_eff_out) *r_eff_out = r_eff;
   return run_fwd(ctx, rs, prm, c, Fd, r_eff, out, eta_out, fb, true, true);
@@ -884,7 +904,7 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
   if ((st = ensure_pinned(ctx, 64 * 1024 + sizeof(double) * host_doubles)) != NKF_OK) return st;
   Carve cv{ctx->ws};
   carve_all(cv);
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the pinned buffer may feed an earlier copy
+  if ((st = pinned_acquire(ctx)) != NKF_OK) return st;
   double *hF = reinterpret_cast<double *>(ctx->pinned);
   double *hred = hF + (size_t)r * r_eff;
   double *hsig = hred + (size_t)nred * (nR + 1);
@@ -894,6 +914,7 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
   {
     StageTimer tm(ctx, NKF_STAGE_BACKWARD);
     HIP_TRY(ctx, hipMemcpyAsync(Fd, hF, sizeof(double) * r * r_eff, hipMemcpyHostToDevice, ctx->stream));
+    if ((st = pinned_release(ctx)) != NKF_OK) return st;
     const bool have_fwd = out_fwd && eta_fwd;
     if ((st = run_fwd(ctx, rs, prm, centroids, Fd, r_eff, out_s, eta_s, fb, !have_fwd)) != NKF_OK) return st;
     const float *outv = have_fwd ? out_fwd : out_s, *etav = have_fwd ? eta_fwd : eta_s;
