@@ -1,10 +1,11 @@
 // Host FP64 symmetric eigensolver for the landmark Gram matrix A (Eq. (eigA)).
 //
 // Method (Golub & Van Loan, "Matrix Computations", Sections 8.3.1-8.3.3):
-// Householder reduction A = Q T Q^T to tridiagonal form, then implicit
-// symmetric QR steps with the Wilkinson shift on the unreduced blocks of T
-// (kept as its diagonal and off-diagonal), accumulating every reflection and
-// rotation into Q.  Cost O(n^3) with a small constant, n <= 256.
+// Householder reduction A = Q T Q^T to tridiagonal form (updating the lower
+// triangle only), then implicit symmetric QR steps with the Wilkinson shift
+// on the unreduced blocks of T (kept as its diagonal and off-diagonal),
+// accumulating every reflection and rotation into Q.  Cost O(n^3) with a small
+// constant, n <= 256.
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
@@ -34,7 +35,7 @@ int sym_eig_impl(int n, const double *A, double *w, double *V) {
       T[i * n + j] = T[j * n + i] = m;
     }
 
-  // ---- Householder tridiagonalisation -------------------------------------
+  // ---- Householder tridiagonalisation (lower triangle) ---------------------
   std::vector<double> v(n), p(n), q(n);
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;  // length of x = T[k+1:, k]
@@ -48,23 +49,31 @@ int sym_eig_impl(int n, const double *A, double *w, double *V) {
     for (int i = 1; i < m; ++i) v[i] = T[(k + 1 + i) * n + k];
     double vtv = v[0] * v[0] + sigma;
     const double beta = 2.0 / vtv;
-    // p = beta * T' v on the trailing block T' = T[k+1:, k+1:]
+    // p = beta * T' v on the trailing block T' = T[k+1:, k+1:], of which only
+    // the lower triangle is kept (rows j <= i and their transposes)
+    for (int i = 0; i < m; ++i) p[i] = 0.0;
     for (int i = 0; i < m; ++i) {
-      double acc = 0.0;
       const double *row = &T[(k + 1 + i) * n + (k + 1)];
-      for (int j = 0; j < m; ++j) acc += row[j] * v[j];
-      p[i] = beta * acc;
+      const double vi = v[i];
+      double acc = 0.0;
+      for (int j = 0; j < i; ++j) {
+        acc += row[j] * v[j];
+        p[j] += row[j] * vi;
+      }
+      p[i] += acc + row[i] * vi;
     }
+    for (int i = 0; i < m; ++i) p[i] *= beta;
     double ptv = 0.0;
     for (int i = 0; i < m; ++i) ptv += p[i] * v[i];
     const double kk = 0.5 * beta * ptv;
     for (int i = 0; i < m; ++i) q[i] = p[i] - kk * v[i];
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j)
-        T[(k + 1 + i) * n + (k + 1 + j)] -= v[i] * q[j] + q[i] * v[j];
-    const double newx = -sgn(x0) * mu;
-    T[(k + 1) * n + k] = T[k * n + k + 1] = newx;
-    for (int i = 1; i < m; ++i) T[(k + 1 + i) * n + k] = T[k * n + k + 1 + i] = 0.0;
+    for (int i = 0; i < m; ++i) {
+      double *row = &T[(k + 1 + i) * n + (k + 1)];
+      const double vi = v[i], qi = q[i];
+      for (int j = 0; j <= i; ++j) row[j] -= vi * q[j] + qi * v[j];
+    }
+    T[(k + 1) * n + k] = -sgn(x0) * mu;
+    for (int i = 1; i < m; ++i) T[(k + 1 + i) * n + k] = 0.0;
     // Q <- Q H on columns k+1..n-1
     for (int i = 0; i < n; ++i) {
       double acc = 0.0;
@@ -75,7 +84,7 @@ int sym_eig_impl(int n, const double *A, double *w, double *V) {
       for (int j = 0; j < m; ++j) roww[j] -= acc * v[j];
     }
   }
-  // ---- implicit symmetric QR with Wilkinson shift on the band -------------
+// ---- implicit symmetric QR with Wilkinson shift on the band -------------
   // d: diagonal, e[i]: entry (i+1, i); the eigenvector estimates are the rows
   // of Z = Q^T, so that a rotation in the (k, k+1) plane updates two
   // contiguous rows.
@@ -107,7 +116,8 @@ int sym_eig_impl(int n, const double *A, double *w, double *V) {
     double bulge = 0.0;
     for (int k = lo; k < hi; ++k) {
       // rotation G = [[c, s], [-s, c]] in the (k, k+1) plane with G (x, z)^T = (r, 0)^T
-      const double rr = hypot(x, z);
+      const double s2 = x * x + z * z;
+      const double rr = s2 > 1e-290 && s2 < 1e290 ? sqrt(s2) : hypot(x, z);
       double c = 1.0, s = 0.0;
       if (rr != 0.0) {
         c = x / rr;
