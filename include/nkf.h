@@ -201,9 +201,10 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
 /* Stage timing.  When enabled, every stage a call enqueues is bracketed by
  * HIP events on the context's stream (host-side stages by the host clock).
  * Stages: 0 seeding, 1 k-means iterations, 2 landmark factor (host FP64,
- * including the wait for the landmarks; nkf_filter runs the centring on the
- * device meanwhile), 3 embedding (with the centring in nkf_filter_landmarks),
- * 4 convolutions + contraction, 5 backward. */
+ * from the landmarks' arrival on the host to the queued copy of F; nkf_filter
+ * runs the centring on the device meanwhile), 3 embedding (with the centring
+ * in nkf_filter_landmarks), 4 convolutions + contraction, 5 backward.  Timing
+ * adds no synchronisation to a call. */
 enum { NKF_STAGE_SEED = 0, NKF_STAGE_KMEANS = 1, NKF_STAGE_FACTOR = 2, NKF_STAGE_EMBED = 3,
        NKF_STAGE_CONV = 4, NKF_STAGE_BACKWARD = 5, NKF_STAGE_COUNT = 6 };
 nkf_status nkf_enable_timing(nkf_ctx *ctx, int enable);

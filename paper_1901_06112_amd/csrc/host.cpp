@@ -819,9 +819,7 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
   if ((st = run_lloyd(ctx, rs, r, c, prm->kmeans_iters, nullptr, kb, prm->prec)) != NKF_OK) return st;
   // the one host round trip: landmarks to the host for the FP64 factor
   int r_eff = 0;
-  if (ctx->timing) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // keep k-means time out of the factor stage
   {
-    HostTimer ht(ctx, NKF_STAGE_FACTOR);
     float *c_host = reinterpret_cast<float *>(ctx->pinned);
     HIP_TRY(ctx, hipMemcpyAsync(c_host, c, sizeof(float) * r * rs.D, hipMemcpyDeviceToHost, ctx->stream));
     if (!ctx->copy_done) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->copy_done, hipEventDisableTiming));
@@ -829,6 +827,9 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
     // landmark-independent work runs on the device while the host factors A
     if ((st = run_pre(ctx, rs, prm, fb)) != NKF_OK) return st;
     HIP_TRY(ctx, hipEventSynchronize(ctx->copy_done));
+    // the factor stage is the host's work once the landmarks have arrived, so
+    // timing it needs no extra synchronisation
+    HostTimer ht(ctx, NKF_STAGE_FACTOR);
     std::vector<double> cd((size_t)r * rs.D);
     for (size_t i = 0; i < cd.size(); ++i) cd[i] = c_host[i];
     double *F_host = reinterpret_cast<double *>(ctx->pinned + ((sizeof(float) * r * rs.D + 255) & ~(size_t)255));
