@@ -38,9 +38,9 @@ def _case(kind, h, w):
         f, _ = synth.workload("color_blf_256", h, w)
         p = np.ascontiguousarray(synth.workload("hyperspectral_512x128", h, w)[0][:, :, :25] * 255.0)
         return f, p, "explicit", p.reshape(-1, 25).astype(np.float64)
-    if kind == "patch":
+    if kind in ("patch", "patch2"):
         f, _ = synth.workload("color_nlm_1024", h, w)
-        pg = exact.patch_guide(f.astype(np.float64), 3)
+        pg = exact.patch_guide(f.astype(np.float64), 3 if kind == "patch" else 2)
         return f, None, "patch", pg.reshape(-1, pg.shape[2])
     raise KeyError(kind)
 
@@ -54,21 +54,25 @@ def _near_tie(P, c, rel=2e-5):
 
 # explicit25: D + 1 <= 64 (several pixels per wave instruction in the FP32 sums);
 # hyper and patch: D + 1 > 64 (64-dimension slices); hyper with r = 256: the
-# FP32 sums do not fit in LDS (FP64 sums in the block's slot)
+# FP32 sums do not fit in LDS (FP64 sums in the block's slot); patch2 (5x5x3
+# patches, D + 1 = 76): three pixel stripes per block in the sums, each
+# crossing image rows of an odd width
 @pytest.mark.parametrize("kind,h,w,r", [("self3", 70, 90, 32), ("explicit2", 64, 64, 8),
                                          ("explicit25", 50, 46, 31), ("hyper", 40, 36, 64),
-                                         ("hyper", 40, 36, 256), ("patch", 48, 40, 128)])
+                                         ("hyper", 40, 36, 256), ("patch", 48, 40, 128),
+                                         ("patch2", 37, 53, 16)])
 def test_seed_and_one_lloyd_step(kind, h, w, r):
     nkf = _nkf()
     f, p, guide, P = _case(kind, h, w)
     ft = torch.from_numpy(f).cuda()
     pt = torch.from_numpy(p).cuda() if p is not None else None
-    c0 = nkf.kmeans(ft, pt, r=r, iters=0, seed=11, guide=guide)
+    pk = {"patch_radius": 2} if kind == "patch2" else {}
+    c0 = nkf.kmeans(ft, pt, r=r, iters=0, seed=11, guide=guide, **pk)
     torch.cuda.synchronize()
     idx = seeding.distinct_indices(P.shape[0], r, 11)
     np.testing.assert_array_equal(c0.cpu().numpy(), P[idx].astype(np.float32))
     c_start = c0.cpu().numpy().astype(np.float64)
-    c1, lab = nkf.kmeans_iterate(ft, c0, pt, iters=1, guide=guide, return_labels=True)
+    c1, lab = nkf.kmeans_iterate(ft, c0, pt, iters=1, guide=guide, return_labels=True, **pk)
     torch.cuda.synchronize()
     lab = lab.cpu().numpy().reshape(-1)
     lab_or, _ = kmeans.assign(P, c_start)

@@ -160,6 +160,25 @@ def test_box_window_patch_guide(r):
     _report_conditioned(f"nlm_patch_r{r}", f, pg, c32, 1.0, prm["sigma_r"], prm["S"], gg, oo, spatial="box")
 
 
+def test_patch_guide_radius2_odd_width():
+    """5x5x3 patches (d = 75) on a 37 x 53 image: the embedding's row tiles of
+    64 pixels are all partial, its staged window is 5 x 68 x 3."""
+    f, prm = synth.workload("color_nlm_1024", 37, 53, seed=8)
+    pg = exact.patch_guide(f.astype(np.float64), 2)
+    P = pg.reshape(-1, pg.shape[2])
+    c32 = _landmarks(P, 16, 3, 5)
+    sr = 30.0 * np.sqrt(75.0)  # nearly every pixel well conditioned at 16 landmarks
+    g, eta, _ = _run_case(f, None, c32, 1.0, sr, 4, spatial="box", guide="patch", patch_radius=2)
+    go, etao = _oracle(f, pg, c32, 1.0, sr, 4, spatial="box")
+    both = ~(etao > 0) & ~(eta > 0)
+    if both.any():
+        np.testing.assert_array_equal(g[both], f.astype(np.float64)[both])
+    gg, oo = g.copy(), go.copy()
+    gg[both] = 0.0
+    oo[both] = 0.0
+    _report_conditioned("nlm_patch_pr2", f, pg, c32, 1.0, sr, 4, gg, oo, spatial="box")
+
+
 def test_explicit_wide_guide_many_landmarks():
     """d = 160, r = 256: the FP64 b tile of 64 pixels and the guide tile do not
     fit in LDS together, so the embedding runs on 32-pixel tiles."""
