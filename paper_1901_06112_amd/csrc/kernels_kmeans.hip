@@ -514,7 +514,9 @@ static hipError_t assign_accumulate(const Guide &g, const float *c, int r, doubl
   if (owned_applies(r, g.D)) {
     const size_t own_bytes = acc_bytes * (kBlock / (g.D + 1));
     // about 1024 pixels per block: several blocks per CU even with one stripe
-    *nparts = grid_for(N, 1024, kMaxPartialsOwned);
+    // at least 256 pixels per block: up to kMaxPartialsOwned blocks, so that a
+    // 512 x 512 image still fills every CU several times
+    *nparts = grid_for(N, 256, kMaxPartialsOwned);
     const int64_t per_block = (N + *nparts - 1) / *nparts;
     auto *kern = g.kind == GUIDE_PATCH ? accumulate_owned_kernel<true> : accumulate_owned_kernel<false>;
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
