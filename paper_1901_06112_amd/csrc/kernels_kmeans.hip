@@ -393,22 +393,26 @@ __global__ __launch_bounds__(kBlock) void accumulate_generic_kernel(Guide g, int
 // c_k[d] = mu(d) + S_k[d] / n_k from the per-block partial sums (S of the
 // centred values when mu is given, of the raw values otherwise; mu_mod > 0
 // indexes mu by d % mu_mod).  An empty cluster keeps its centroid.  One block
-// per cluster; the D sums and the count (column D) are formed in groups of
-// up to kBlock columns, each column summed by G lanes (partial b on lane
+// per cluster of UB threads (1024 when D + 1 > 64, so that wide rows still get
+// several lanes per column; 256 otherwise, where the lane sums' ordered combine
+// would dominate); the D sums and the count (column D) are formed in groups
+// of up to UB columns, each column summed by G lanes (partial b on lane
 // b mod G, loads issued eight at a time) and the G lane sums added in lane
 // order: a fixed order, so the result does not depend on timing.
-__global__ __launch_bounds__(kBlock) void update_kernel(const double *__restrict__ partials, int nparts,
-                                                        int r, int D, const float *__restrict__ mu,
-                                                        int mu_mod, float *__restrict__ c) {
-  __shared__ double red[kBlock];
+template <int UB>
+__global__ __launch_bounds__(UB) void update_kernel(const double *__restrict__ partials, int nparts, int r, int D,
+                                                    const float *__restrict__ mu, int mu_mod,
+                                                    float *__restrict__ c) {
+  constexpr int kUpdBlock = UB;
+  __shared__ double red[kUpdBlock];
   __shared__ double tot[kMaxGuideDim + 1];
   const int k = blockIdx.x, tid = threadIdx.x;
   const int DA = D + 1;
   const size_t stride = (size_t)r * DA;
   const double *base = partials + (size_t)k * DA;
-  for (int m0 = 0; m0 < DA; m0 += kBlock) {
-    const int M = DA - m0 < kBlock ? DA - m0 : kBlock;
-    const int G = kBlock / M;
+  for (int m0 = 0; m0 < DA; m0 += kUpdBlock) {
+    const int M = DA - m0 < kUpdBlock ? DA - m0 : kUpdBlock;
+    const int G = kUpdBlock / M;
     const int m = tid % M, gl = tid / M;
     double s = 0.0;
     if (gl < G) {
@@ -433,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void update_kernel(const double *__restrict
   }
   const double n = tot[D];
   if (!(n > 0.0)) return;
-  for (int d = tid; d < D; d += kBlock) {
+  for (int d = tid; d < D; d += kUpdBlock) {
     const double off = mu ? (double)mu[mu_mod > 0 ? d % mu_mod : d] : 0.0;
     c[k * D + d] = (float)(off + tot[d] / n);
   }
@@ -544,14 +548,21 @@ size_t kmeans_partials_doubles(int r, int D) {
   return (size_t)parts * r * (D + 1);
 }
 
+static hipError_t launch_update(const double *partials, int nparts, int r, int D, const float *mu, int mu_mod,
+                                float *c, hipStream_t s) {
+  if (D + 1 > 64)
+    hipLaunchKernelGGL(update_kernel<1024>, dim3(r), dim3(1024), 0, s, partials, nparts, r, D, mu, mu_mod, c);
+  else
+    hipLaunchKernelGGL(update_kernel<256>, dim3(r), dim3(256), 0, s, partials, nparts, r, D, mu, mu_mod, c);
+  return hipGetLastError();
+}
+
 hipError_t launch_kmeans_step_mfma(const Guide &g, float *c, int r, const float *mu, int prec, double *partials,
                                    int *labels, void *lm_scratch, hipStream_t s) {
   int nparts = 0;
   hipError_t e = launch_lloyd_mfma(g, c, r, mu, prec, partials, labels, &nparts, lm_scratch, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(update_kernel, dim3(r), dim3(kBlock), 0, s, partials, nparts, r, g.D, mu,
-                     g.kind == GUIDE_PATCH ? g.C : 0, c);
-  return hipGetLastError();
+  return launch_update(partials, nparts, r, g.D, mu, g.kind == GUIDE_PATCH ? g.C : 0, c, s);
 }
 
 hipError_t launch_kmeans_step(const Guide &g, float *c, int r, double *partials, int *labels, int *label_scratch,
@@ -559,9 +570,7 @@ hipError_t launch_kmeans_step(const Guide &g, float *c, int r, double *partials,
   int nparts = 0;
   hipError_t e = assign_accumulate(g, c, r, partials, labels, label_scratch, ct, &nparts, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(update_kernel, dim3(r), dim3(kBlock), 0, s, partials, nparts, r, g.D,
-                     static_cast<const float *>(nullptr), 0, c);
-  return hipGetLastError();
+  return launch_update(partials, nparts, r, g.D, nullptr, 0, c, s);
 }
 
 }  // namespace nkf
