@@ -158,6 +158,10 @@ __global__ __launch_bounds__(BT) void embed_kernel(Guide g, int64_t N, const flo
     for (int kb = 8 * kg; kb < r_eff; kb += 8 * NG) {
       double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       if (kb + 8 <= r_eff) {
+        // generic form: unrolled so that several F row segments (scalar loads)
+        // are in flight together (no gain for D <= 4)
+        constexpr int kMixUnroll = DS == 0 ? 4 : 1;
+#pragma unroll kMixUnroll
         for (int k = 0; k < r; ++k) {
           const double bv = bs[k * TPX + px];
           const double *Fr = F + (size_t)k * r_eff + kb;
