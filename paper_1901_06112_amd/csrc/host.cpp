@@ -707,7 +707,7 @@ nkf_status nkf_patch_pca(nkf_ctx *ctx, int H, int W, int C, const float *f, int 
   const int64_t N = (int64_t)H * W;
   const int ns = N > kPcaSample ? kPcaSample : (int)N;
   const int mb = ns < 256 ? ns : 256;
-  const int cc = std::max(1, std::min(16, (ns + 63) / 64));
+  const int cc = std::max(1, std::min(64, (ns + 63) / 64));
   Guide g{GUIDE_PATCH, nullptr, f, H, W, C, D, pr};
   float *S;
   auto carve = [&](Carve &cv, int64_t *&idx, double *&part, double *&mu, double *&cpart, double *&cov, double *&V) {

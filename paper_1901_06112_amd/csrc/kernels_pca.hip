@@ -58,8 +58,9 @@ __global__ void pca_mean_final_kernel(const double *__restrict__ partials, int n
 
 // One 16 x 16 tile (ti <= tj) of sum_s (S_s - mu)(S_s - mu)^T over one chunk
 // of the sample: thread (a, b) owns entry (16 ti + a, 16 tj + b); the centred
-// values of 64 samples for both tiles' dimensions are staged in LDS per pass.
-// cpart[chunk][i][j] for the entries of tiles with ti <= tj.
+// values of 64 samples for both tiles' dimensions are staged in LDS per pass,
+// and each pass feeds four accumulators (samples s mod 4), added in that
+// order at the end.  cpart[chunk][i][j] for the entries of tiles with ti <= tj.
 __global__ __launch_bounds__(kBlock) void pca_cov_kernel(const float *__restrict__ S, int ns, int D,
                                                          const double *__restrict__ mu, int chunk,
                                                          double *__restrict__ cpart) {
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void pca_cov_kernel(const float *__restrict
   const int tj = ti + pidx;
   const int a = threadIdx.x / kCovTile, b = threadIdx.x % kCovTile;
   const int s0 = blockIdx.y * chunk, s1 = min(ns, s0 + chunk);
-  double acc = 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int sb = s0; sb < s1; sb += kCovBatch) {
     __syncthreads();
     for (int e = threadIdx.x; e < 2 * kCovBatch * kCovTile; e += kBlock) {
@@ -91,10 +92,10 @@ __global__ __launch_bounds__(kBlock) void pca_cov_kernel(const float *__restrict
     }
     __syncthreads();
 #pragma unroll 8
-    for (int s = 0; s < kCovBatch; ++s) acc = fma(xi[s][a], xj[s][b], acc);
+    for (int s = 0; s < kCovBatch; ++s) acc[s & 3] = fma(xi[s][a], xj[s][b], acc[s & 3]);
   }
   const int i = ti * kCovTile + a, j = tj * kCovTile + b;
-  if (i < D && j < D) cpart[((size_t)blockIdx.y * D + i) * D + j] = acc;
+  if (i < D && j < D) cpart[((size_t)blockIdx.y * D + i) * D + j] = ((acc[0] + acc[1]) + acc[2]) + acc[3];
 }
 
 // cov[i][j] = (sum over chunks, in order) / ns, from the computed triangle
