@@ -885,7 +885,7 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
 
   FwdBufs fb;
   float *out_s, *eta_s, *ab, *dud, *du, *df_s;
-  double *Fd, *red, *sig;
+  double *Fd, *red, *red2, *sig;
   auto carve_all = [&](Carve &cv) {
     carve_fwd(cv, rs, r_eff, fb);
     out_s = cv.take<float>((size_t)rs.N * C);
@@ -896,6 +896,7 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
     df_s = cv.take<float>(grad_f ? 1 : (size_t)rs.N * C);
     Fd = cv.take<double>((size_t)r * r_eff);
     red = cv.take<double>((size_t)nred * (nR + 1));
+    red2 = cv.take<double>(bwd_sum_scratch_doubles(nred, nR + 1));
     sig = cv.take<double>(2 * (size_t)nsig);
   };
   Carve dry{nullptr};
@@ -963,7 +964,11 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
                                    red, ctx->stream));
   }
   if (!want_R && !want_S) return NKF_OK;
-  HIP_TRY(ctx, hipMemcpyAsync(hred, red, sizeof(double) * nred * (nR + 1), hipMemcpyDeviceToHost, ctx->stream));
+  // the blocks' partials summed on the device; only the sums cross to the host
+  hipError_t serr = hipSuccess;
+  const double *red_sum = launch_bwd_sum_partials(red, nred, nR + 1, red2, ctx->stream, &serr);
+  HIP_TRY(ctx, serr);
+  HIP_TRY(ctx, hipMemcpyAsync(hred, red_sum, sizeof(double) * (nR + 1), hipMemcpyDeviceToHost, ctx->stream));
   if (want_S) {
     HIP_TRY(ctx, hipMemcpyAsync(hsig, sig, sizeof(double) * nb1, hipMemcpyDeviceToHost, ctx->stream));
   }
@@ -980,11 +985,8 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
     // dL/dA = -M (dL/dM) M,  dA_ij/dsigma_r = A_ij D_ij / sigma_r^3
     double sr_b = 0.0;
     std::vector<double> R((size_t)r * r, 0.0);
-    for (int b = 0; b < nred; ++b) {
-      const double *pb = hred + (size_t)b * (nR + 1);
-      sr_b += pb[0];
-      for (int e = 0; e < nR; ++e) R[e] += pb[1 + e];
-    }
+    sr_b = hred[0];
+    for (int e = 0; e < nR; ++e) R[e] = hred[1 + e];
     const double *Q = eigvecs_host, *al = eigvals_host;
     std::vector<double> GM((size_t)r * r, 0.0), M((size_t)r * r, 0.0), T1((size_t)r * r, 0.0);
     for (int i = 0; i < r; ++i)

@@ -255,6 +255,36 @@ size_t bwd_reduce_lds(int r, int r_eff, int D, int want_R) {
          sizeof(float) * ((size_t)D * kRTile + (size_t)r_eff * kRTile + (size_t)r_eff * kRS);
 }
 
+// out[grp][e] = in[b0][e] + in[b0 + 1][e] + ... over the rows b0 = grp * group
+// .. min(nrows, b0 + group) - 1, added in row order.
+__global__ void sum_rows_kernel(const double *__restrict__ in, int nrows, int width, int group,
+                                double *__restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= width) return;
+  const int b0 = blockIdx.y * group, b1 = min(nrows, b0 + group);
+  double s = 0.0;
+  for (int b = b0; b < b1; ++b) s += in[(size_t)b * width + e];
+  out[(size_t)blockIdx.y * width + e] = s;
+}
+
+constexpr int kSumGroup = 32;
+
+size_t bwd_sum_scratch_doubles(int nrows, int width) {
+  return (size_t)((nrows + kSumGroup - 1) / kSumGroup + 1) * width;
+}
+
+const double *launch_bwd_sum_partials(const double *partials, int nrows, int width, double *scratch,
+                                      hipStream_t s, hipError_t *err) {
+  const int ngroups = (nrows + kSumGroup - 1) / kSumGroup;
+  const dim3 blk(256), g1((width + 255) / 256, ngroups), g2((width + 255) / 256, 1);
+  double *out = scratch + (size_t)ngroups * width;
+  hipLaunchKernelGGL(sum_rows_kernel, g1, blk, 0, s, partials, nrows, width, kSumGroup, scratch);
+  if ((*err = hipGetLastError()) != hipSuccess) return nullptr;
+  hipLaunchKernelGGL(sum_rows_kernel, g2, blk, 0, s, scratch, ngroups, width, ngroups, out);
+  *err = hipGetLastError();
+  return out;
+}
+
 hipError_t launch_bwd_reduce(const Guide &g, const float *c, int r, const double *F, int r_eff, double sigma_r,
                              const float *du, const float *dud, float *dp, int want_R, double *partials,
                              hipStream_t s) {

@@ -117,6 +117,12 @@ size_t bwd_reduce_lds(int r, int r_eff, int D, int want_R);
 hipError_t launch_bwd_reduce(const Guide &g, const float *c, int r, const double *F, int r_eff,
                              double sigma_r, const float *du, const float *dud, float *dp, int want_R,
                              double *partials, hipStream_t s);
+// Column sums of partials [nrows][width] on the device: groups of 32 rows in
+// row order, then the groups in order.  Returns the device pointer of the
+// width sums inside scratch (bwd_sum_scratch_doubles(nrows, width) doubles).
+size_t bwd_sum_scratch_doubles(int nrows, int width);
+const double *launch_bwd_sum_partials(const double *partials, int nrows, int width, double *scratch,
+                                      hipStream_t s, hipError_t *err);
 
 
 // ---- kernels_pca.hip ---------------------------------------------------------
