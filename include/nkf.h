@@ -102,6 +102,15 @@ const char *nkf_last_error(const nkf_ctx *ctx);
 /* Cap on the workspace size in bytes (0 = no cap).  A call that would need
  * more fails with NKF_ERR_OUT_OF_MEMORY before enqueuing work. */
 nkf_status nkf_set_workspace_limit(nkf_ctx *ctx, size_t bytes);
+/* Tile geometry of the convolution kernels (forward and backward): each
+ * block streams its output tile in chunks of rows, and by default the number
+ * of chunks per tile is the largest that still gives enough blocks to fill
+ * the GPU, so small images run one chunk per tile.  nch > 0 requests nch
+ * chunks per tile (capped by each kernel's register budget and by the rows
+ * the image has), e.g. to exercise the multi-chunk row ring of large images
+ * on small ones; 0 restores the automatic choice.  Results are the same up to
+ * rounding order.  NKF_ERR_INVALID_ARG for nch < 0. */
+nkf_status nkf_set_conv_chunks(nkf_ctx *ctx, int nch);
 /* Bytes of workspace currently held by the context. */
 size_t nkf_workspace_bytes(const nkf_ctx *ctx);
 

@@ -1,18 +1,13 @@
 """Nystrom fast kernel filter in the paper's own form.  Test infrastructure only.
 
-Section III and Algorithm 1 (Fast Kernel Filtering):
-
-* landmarks mu_1..mu_m0 (k-means centroids, see ``oracle.kmeans``);
-* A(i, j) = k(mu_i, mu_j)                      -- Eq. (defA)
-* A = sum_k alpha_k w_k w_k^T                  -- Eq. (eigA)
-* B(i, j) = k(mu_i, r_j)                       -- Eq. (defB)
-* v_k = B^T w_k / alpha_k                      -- Eq. (vk)
-* d_k(x) = v_k(iota(x)), h_k = d_k f
-* zeta += alpha_k d_k (w * h_k),  eta += alpha_k d_k (w * d_k)   -- the two
-  accumulation steps of Algorithm 1, i.e. Eqs. (finalnum), (finalden)
-* g_hat = zeta / eta.
-
-The index map iota is notational: v_k(iota(x)) is evaluated from p(x) directly.
+Section III: the range kernel k(p(x), p(y)) of Eq. (num1) is replaced by
+its Nystrom approximation built from r landmarks mu_1..mu_r (k-means
+centroids, see ``oracle.kmeans``).  The landmark Gram matrix A (Eq. (defA))
+is decomposed as A = sum_k alpha_k w_k w_k^T (Eq. (eigA)); the eigenvectors
+extend to every guide value through the cross kernel B (Eq. (defB)) as
+v_k = B^T w_k / alpha_k (Eq. (vk)), and K_hat = sum_k alpha_k v_k v_k^T
+(Eq. (hatK)).  With that kernel the filter becomes a sum over k of spatial
+convolutions of v_k f and v_k (Eqs. (finalnum), (finalden)).
 
 Readings where the paper is silent:
 * eigenvalues alpha_k <= tau * max(alpha) (tau = 1e-10) are dropped, which
@@ -94,25 +89,34 @@ def conv_zero(img, w1):
 
 def nystrom_filter(f, p, c, sigma_s, sigma_r, S, spatial="gaussian", tau=DEFAULT_TAU,
                    return_eta=False):
-    """Algorithm 1 with given landmarks ``c`` [r, D].  ``f`` [H, W, C],
-    ``p`` [H, W, D].  Returns g_hat [H, W, C] (and eta_hat [H, W])."""
+    """The fast filter of Section III with given landmarks ``c`` [r, D].
+    ``f`` [H, W, C], ``p`` [H, W, D].  Returns g_hat [H, W, C] (and eta_hat [H, W]).
+
+    Eq. (num1) with the range kernel replaced by the rank-r_eff expansion
+    K_hat(x, y) = sum_k alpha_k v_k(x) v_k(y) of Eq. (hatK) (v_k from Eq. (vk),
+    read at the guide values p(x) and p(y)).  Exchanging the window sum with
+    the sum over k leaves, for every k, one spatial convolution of v_k f and
+    one of v_k (Eqs. (finalnum), (finalden)):
+
+        zeta(x) = sum_k alpha_k v_k(x) (w * (v_k f))(x),
+        eta(x)  = sum_k alpha_k v_k(x) (w * v_k)(x),   g_hat = zeta / eta.
+    """
     f = np.asarray(f, np.float64)
     p = np.asarray(p, np.float64)
     H, W, C = f.shape
-    P = p.reshape(H * W, -1)
     w1 = spatial_taps(sigma_s, S, spatial)
-    alpha, Wv = landmark_eig(c, sigma_r, tau)
-    Bt = cross_kernel_sr(c, P, sigma_r)          # [N, r]
+    # all extrapolated eigenvectors at once: column k of V is v_k over the pixels
+    alpha, V = extrapolated_eigvecs(c, p.reshape(H * W, -1), sigma_r, tau)
+    V = V.reshape(H, W, -1)
     zeta = np.zeros((H, W, C))
     eta = np.zeros((H, W))
-    for k in range(len(alpha)):
-        vk = (Bt @ Wv[:, k]) / alpha[k]           # Eq. (vk)
-        d = vk.reshape(H, W)                      # d_k(x) = v_k(iota(x))
-        h = d[:, :, None] * f                     # h_k = d_k f
-        zeta += alpha[k] * d[:, :, None] * conv_zero(h, w1)
-        eta += alpha[k] * d * conv_zero(d, w1)
+    for k, a_k in enumerate(alpha):
+        v = V[:, :, k]
+        zeta += a_k * v[:, :, None] * conv_zero(v[:, :, None] * f, w1)
+        eta += a_k * v * conv_zero(v, w1)
     with np.errstate(invalid="ignore", divide="ignore"):
         g = zeta / eta[:, :, None]
+    # eta_hat carries no positivity guarantee: such pixels keep f(x)
     bad = ~(eta > 0) | ~np.isfinite(eta)
     if bad.any():
         g[bad] = f[bad]
@@ -206,3 +210,34 @@ def storage_error_bound(f, p, c, sigma_s, sigma_r, S, spatial="gaussian", tau=DE
         B = (zabs + np.abs(gt) * eabs[:, :, None]) / np.abs(eta)[:, :, None]
     B[~np.isfinite(B)] = np.inf
     return B
+
+
+def storage_error_bound_at(f, p, c, sigma_s, sigma_r, S, coords, spatial="gaussian", tau=DEFAULT_TAU,
+                           center=None):
+    """``storage_error_bound`` (the |u_k| form) at the listed pixels only,
+    from each pixel's window: coords [M, 2] of (y, x); ``center`` is the
+    per-channel f0 (default: (min + max) / 2 of f).  Returns [M, C]."""
+    f = np.asarray(f, np.float64)
+    p = np.asarray(p, np.float64)
+    H, W, C = f.shape
+    f0 = 0.5 * (f.min(axis=(0, 1)) + f.max(axis=(0, 1))) if center is None else np.asarray(center, np.float64)
+    w1 = spatial_taps(sigma_s, S, spatial)
+    alpha, Wv = landmark_eig(c, sigma_r, tau)
+    Fm = Wv / np.sqrt(alpha)[None, :]
+    out = np.empty((len(coords), C))
+    for i, (y, x) in enumerate(np.asarray(coords)):
+        ya, yb = max(0, y - S), min(H, y + S + 1)
+        xa, xb = max(0, x - S), min(W, x + S + 1)
+        u_win = cross_kernel_sr(c, p[ya:yb, xa:xb].reshape(-1, p.shape[2]), sigma_r) @ Fm   # [n, r_eff]
+        u_x = (cross_kernel_sr(c, p[y, x][None, :], sigma_r) @ Fm)[0]
+        wsp = np.outer(w1[ya - y + S:yb - y + S], w1[xa - x + S:xb - x + S]).ravel()
+        fc = f[ya:yb, xa:xb].reshape(-1, C) - f0
+        eta = u_x @ (u_win * wsp[:, None]).sum(axis=0)
+        zeta = ((u_win * wsp[:, None]) @ u_x) @ fc
+        eabs = np.abs(u_x) @ (np.abs(u_win) * wsp[:, None]).sum(axis=0)
+        zabs = ((np.abs(u_win) * wsp[:, None]) @ np.abs(u_x)) @ np.abs(fc)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            out[i] = (zabs + np.abs(zeta / eta) * eabs) / abs(eta)
+    out[~np.isfinite(out)] = np.inf
+    return out
+

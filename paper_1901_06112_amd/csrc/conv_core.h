@@ -55,6 +55,7 @@ enum Mode { MODE_FWD = 0, MODE_DUDIR = 1, MODE_SIGS = 2, MODE_ADJ = 3 };
 struct ConvArgs {
   int H, W, C, r_eff;
   int nch;          // output chunks (of RC rows) per tile
+  int force_nch;    // > 0: chunks per tile requested by the caller (0: chosen from the grid size)
   int tiles_x, tiles_y, nblocks;
   int ch_per_block; // channel planes per block
   const float *f;
@@ -616,7 +617,10 @@ hipError_t launch_one(ConvArgs a, hipStream_t s, int ch_per_block, int nchunks_c
     const int th = n * RC;
     return (int64_t)a.tiles_x * ((a.H + th - 1) / th) * nchunks_c;
   };
-  while (nch > 1 && blocks(nch) < min_blocks) --nch;
+  if (a.force_nch > 0)
+    nch = a.force_nch < K::NCH_MAX ? a.force_nch : K::NCH_MAX;
+  else
+    while (nch > 1 && blocks(nch) < min_blocks) --nch;
   // do not use more chunks than the image needs
   const int need = (a.H + RC - 1) / RC;
   if (nch > need) nch = need;

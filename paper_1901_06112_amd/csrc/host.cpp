@@ -44,6 +44,7 @@ struct nkf_ctx {
   hipEvent_t copy_done = nullptr;  // the landmark copy of nkf_filter
   hipEvent_t pinned_free = nullptr;  // after the last queued copy through `pinned`
   // the last PCA sample draw (it depends on N and the seed only)
+  int conv_chunks = 0;  // nkf_set_conv_chunks
   int64_t pca_draw_N = -1;
   uint64_t pca_draw_seed = 0;
   std::vector<int64_t> pca_draw;
@@ -455,6 +456,7 @@ nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, cons
   pb.eta_out = eta_out;
   pb.eta_buf = b.eta_buf;
   pb.f_planar = b.f_planar;
+  pb.force_nch = ctx->conv_chunks;
   StageTimer tm(ctx, NKF_STAGE_CONV);
   HIP_TRY(ctx, launch_conv_contract(pb, ctx->stream));
   return NKF_OK;
@@ -609,6 +611,13 @@ nkf_status nkf_destroy(nkf_ctx *ctx) {
 }
 
 const char *nkf_last_error(const nkf_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+nkf_status nkf_set_conv_chunks(nkf_ctx *ctx, int nch) {
+  if (!ctx) return fail(nullptr, NKF_ERR_INVALID_ARG, "ctx is NULL");
+  if (nch < 0) return fail(ctx, NKF_ERR_INVALID_ARG, "nch must be >= 0 (got %d)", nch);
+  ctx->conv_chunks = nch;
+  return NKF_OK;
+}
 
 nkf_status nkf_set_workspace_limit(nkf_ctx *ctx, size_t bytes) {
   if (!ctx) return fail(nullptr, NKF_ERR_INVALID_ARG, "ctx is NULL");
@@ -935,6 +944,7 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
     bp.eta = etav;
     bp.wr = rs.taps;
     bp.wc = rs.taps;
+    bp.force_nch = ctx->conv_chunks;
     bp.mode = 1;
     bp.plane_out = dud;
     HIP_TRY(ctx, launch_bwd_conv(bp, ctx->stream));

@@ -228,6 +228,7 @@ hipError_t launch_bwd_conv(const BwdConvProblem &pb, hipStream_t s) {
   a.G = pb.G;
   a.eta = pb.eta;
   a.partials = pb.partials;
+  a.force_nch = pb.force_nch;
   for (int t = 0; t < 2 * kMaxRadius + 1; ++t) {
     a.wr[t] = (double)pb.wr.w[t];
     a.wc[t] = (double)pb.wc.w[t];

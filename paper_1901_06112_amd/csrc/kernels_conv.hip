@@ -67,6 +67,7 @@ hipError_t launch_conv_contract(const ConvProblem &pb, hipStream_t s) {
   a.eta_out = pb.eta_out;
   a.eta_buf = pb.eta_buf;
   a.fpl = pb.C > 3 ? pb.f_planar : nullptr;
+  a.force_nch = pb.force_nch;
   for (int t = 0; t < 2 * kMaxRadius + 1; ++t) a.wr[t] = a.wc[t] = (double)pb.taps.w[t];
   switch (pb.S) {
 #define NKF_CASE(SV) \

@@ -33,6 +33,7 @@ hipError_t launch_conv_contract_box(const ConvProblem &pb, hipStream_t s) {
   a.out = pb.out;
   a.eta_out = pb.eta_out;
   a.eta_buf = pb.eta_buf;
+  a.force_nch = pb.force_nch;
   for (int t = 0; t < 2 * kMaxRadius + 1; ++t) a.wr[t] = a.wc[t] = 1.0;
   switch (pb.S) {
 #define NKF_CASE(SV) \

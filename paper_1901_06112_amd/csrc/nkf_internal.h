@@ -89,6 +89,7 @@ struct ConvProblem {
   float *eta_buf;     // [N] scratch used when C > 3 (eta pass, then channel chunks)
   float *f_planar;    // [C][N] scratch used when C > 3 (f transposed to planes)
   int box;            // box spatial kernel (all taps 1): sliding sums for C <= 3
+  int force_nch;      // > 0: row chunks per tile (tile-geometry control); 0: automatic
 };
 hipError_t launch_conv_contract(const ConvProblem &pb, hipStream_t s);
 // Box-kernel form for C <= 3 (kernels_conv_box.hip).
@@ -105,6 +106,7 @@ struct BwdConvProblem {
   double *partials;
   Taps wr, wc;
   int *nblocks_out;
+  int force_nch;      // as in ConvProblem
 };
 int bwd_conv_max_blocks(int H, int W);
 hipError_t launch_bwd_ab(int64_t N, int C, const float *G, const float *out, const float *eta,

@@ -29,6 +29,7 @@ EXPORTS = [
     "nkf_last_error", "nkf_set_workspace_limit", "nkf_workspace_bytes", "nkf_filter", "nkf_kmeans",
     "nkf_kmeans_iterate", "nkf_landmark_factor", "nkf_filter_landmarks", "nkf_filter_backward",
     "nkf_seed_indices", "nkf_spatial_taps", "nkf_enable_timing", "nkf_stage_times", "nkf_patch_pca",
+    "nkf_set_conv_chunks",
 ]
 STAGES = ["seed", "kmeans", "factor", "embed", "conv", "backward"]
 
@@ -83,6 +84,7 @@ def load_library(path=LIB_PATH):
             "nkf_patch_pca": (I, [P, I, I, I, P, I, I, U64, P, P]),
             "nkf_enable_timing": (I, [P, I]),
             "nkf_stage_times": (I, [P, P, P, I]),
+            "nkf_set_conv_chunks": (I, [P, I]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -323,6 +325,13 @@ def enable_timing(t, enable=True):
     the current stream."""
     ctx = _cur_ctx(t)
     _check(load_library().nkf_enable_timing(ctx, 1 if enable else 0), ctx)
+
+
+def set_conv_chunks(t, nch):
+    """Row chunks per convolution tile for the context of ``t``'s device and
+    the current stream (0: automatic); see nkf_set_conv_chunks."""
+    ctx = _cur_ctx(t)
+    _check(load_library().nkf_set_conv_chunks(ctx, int(nch)), ctx)
 
 
 def stage_times(t, reset=True):

@@ -117,3 +117,42 @@ def test_distinct_indices():
     assert sorted(perm.tolist()) == list(range(50))
     with pytest.raises(ValueError):
         seeding.distinct_indices(5, 6, 0)
+
+
+def test_distinct_indices_hand_derived_draw():
+    """The draw order j = i + next() mod (N - i), with the swaps of a partial
+    Fisher-Yates shuffle, against draws derived by hand from the published
+    SplitMix64 outputs (tests/golden/fisher_yates_seed1234567.json); the
+    N = 10 case reuses a position that an earlier step moved."""
+    fx = json.load(open(os.path.join(GOLDEN, "fisher_yates_seed1234567.json")))
+    for case in fx["cases"]:
+        got = seeding.distinct_indices(case["N"], case["r"], fx["seed"])
+        assert got.tolist() == case["idx"], case["N"]
+
+
+def test_psnr_known_values():
+    """PSNR = 10 log10(peak^2 / MSE): values fixed by the definition, at peaks
+    1 and 255."""
+    a = np.zeros((8, 8, 3))
+    # peak 1, every error 0.1: MSE 0.01 -> exactly 20 dB
+    assert exact.psnr(a + 0.1, a, peak=1.0) == pytest.approx(20.0, abs=1e-12)
+    # peak 255, every error 25.5 (a tenth of the peak): 20 dB
+    assert exact.psnr(a + 25.5, a, peak=255.0) == pytest.approx(20.0, abs=1e-12)
+    # every error 1 on the 0..255 scale: 20 log10(255) = 48.1308036... dB
+    assert exact.psnr(a + 1.0, a) == pytest.approx(48.13080360867910, abs=1e-10)
+    # errors of opposite sign count alike; half the pixels wrong by 2:
+    # MSE 2 -> 48.1308 - 10 log10(2) = 45.1205 dB
+    b = a.copy()
+    b[::2] += 2.0
+    b[1::2] -= 0.0
+    assert exact.psnr(b, a) == pytest.approx(45.12050365203929, abs=1e-10)
+    c = a.copy()
+    c[::2] -= 2.0
+    assert exact.psnr(c, a) == exact.psnr(b, a)
+    # identical images: infinite
+    assert exact.psnr(a, a) == np.inf
+    # symmetric in its arguments and invariant to a common scale of data and peak
+    rng = np.random.default_rng(4)
+    x, y = rng.uniform(0, 255, (2, 16, 16, 3))
+    assert exact.psnr(x, y) == pytest.approx(exact.psnr(y, x), abs=1e-12)
+    assert exact.psnr(x / 255.0, y / 255.0, peak=1.0) == pytest.approx(exact.psnr(x, y), abs=1e-9)

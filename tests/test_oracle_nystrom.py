@@ -238,3 +238,18 @@ def test_storage_bound_covers_injected_perturbations(C, r, seed, perturb_b):
         g1 = _perturbed_pipeline(f, f, c, 1.5, 30.0, 3, "gaussian", delta, rng, True)
         ok = np.isfinite(Bp)
         assert (np.abs(g1 - g0)[ok] / (stages * delta * Bp[ok])).max() > 1.0
+
+
+@pytest.mark.parametrize("spatial", ["gaussian", "box"])
+def test_storage_bound_at_pixels_equals_full_bound(spatial):
+    """The window-by-window evaluation of the storage bound agrees with the
+    whole-image one (which the perturbation test above pins) at interior,
+    border and corner pixels."""
+    f, _ = synth.workload("color_blf_256", 26, 31, seed=77)
+    f = f.astype(np.float64)
+    P = f.reshape(-1, 3)
+    c, _, _ = kmeans.lloyd(P, P[seeding.distinct_indices(P.shape[0], 9, 5)], 4)
+    B = nystrom.storage_error_bound(f, f, c, 1.5, 30.0, 3, spatial)
+    coords = np.array([[0, 0], [25, 30], [0, 30], [13, 17], [2, 3], [24, 1]])
+    Bat = nystrom.storage_error_bound_at(f, f, c, 1.5, 30.0, 3, coords, spatial)
+    np.testing.assert_allclose(Bat, B[coords[:, 0], coords[:, 1]], rtol=1e-9)
