@@ -185,6 +185,24 @@ nkf_status nkf_filter_landmarks(nkf_ctx *ctx, int H, int W, int C, const float *
                                 const float *p, const nkf_params *prm, const float *centroids,
                                 const double *F, int r_eff, float *out, float *eta_out);
 
+/* nkf_filter_landmarks for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments, kernels and results as nkf_filter_landmarks,
+ * but its scratch (the embedding planes, centring offsets, staged landmarks)
+ * lives in a fixed 64 MiB device array that the library holds on each GPU it
+ * runs on until the process ends; the call allocates nothing and never uses
+ * the context's workspace.  The context supplies the stream and the device
+ * (the array's address on that device is taken by nkf_create).  A problem
+ * whose scratch exceeds 64 MiB (about r_eff * H * W * 4 bytes plus a few
+ * hundred KiB) returns NKF_ERR_OUT_OF_MEMORY before any work is enqueued.
+ * Every call on one GPU shares that GPU's array, whatever the context: calls
+ * that overlap in time on one GPU (different streams, threads or contexts)
+ * race on it and give undefined results; calls ordered on one stream are
+ * safe.  Stage timing is not recorded for this call. */
+nkf_status nkf_filter_landmarks_noalloc(nkf_ctx *ctx, int H, int W, int C, const float *f, int D,
+                                        const float *p, const nkf_params *prm, const float *centroids,
+                                        const double *F, int r_eff, float *out, float *eta_out);
+
 /* Backward of nkf_filter_landmarks for L with dL/dg_hat = grad_out [H, W, C],
  * landmarks held fixed and the window radius S held fixed.
  * eigvecs_host [r, r] / eigvals_host [r] as returned by nkf_landmark_factor

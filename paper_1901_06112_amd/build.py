@@ -35,6 +35,7 @@ SOURCES = [
     "kernels_bwd.hip",
     "kernels_mfma.hip",
     "kernels_pca.hip",
+    "static_scratch.hip",
 ]
 
 COMMON = [

@@ -543,6 +543,9 @@ nkf_status nkf_create(nkf_ctx **out, void *hip_stream) {
     delete c;
     return fail(nullptr, NKF_ERR_HIP, "hipGetDevice failed (no GPU?)");
   }
+  // device address of this device's static scratch (allocation-free entry
+  // point); a failed lookup only disables that entry point
+  (void)static_scratch_init(c->device);
   *out = c;
   return NKF_OK;
 }
@@ -794,6 +797,35 @@ nkf_status nkf_filter_landmarks(nkf_ctx *ctx, int H, int W, int C, const float *
   Carve cv{ctx->ws};
   carve_fwd(cv, rs, r_eff, fb);
   return run_fwd(ctx, rs, prm, centroids, F, r_eff, out, eta_out, fb);
+}
+
+nkf_status nkf_filter_landmarks_noalloc(nkf_ctx *ctx, int H, int W, int C, const float *f, int D,
+                                        const float *p, const nkf_params *prm, const float *centroids,
+                                        const double *F, int r_eff, float *out, float *eta_out) {
+  Resolved rs;
+  nkf_status st = validate(ctx, H, W, C, f, D, p, prm, rs);
+  if (st != NKF_OK) return st;
+  if (!centroids || !F || !out) return fail(ctx, NKF_ERR_INVALID_ARG, "centroids, F and out are required");
+  if (r_eff < 1 || r_eff > prm->r) return fail(ctx, NKF_ERR_INVALID_ARG, "need 1 <= r_eff <= r");
+  Carve dry{nullptr};
+  FwdBufs fb;
+  carve_fwd(dry, rs, r_eff, fb, prm->r);
+  if (dry.off > static_scratch_bytes())
+    return fail(ctx, NKF_ERR_OUT_OF_MEMORY,
+                "this problem needs %zu bytes of scratch; the static scratch holds %zu (use nkf_filter_landmarks)",
+                dry.off, static_scratch_bytes());
+  void *base = nullptr;
+  const hipError_t e = static_scratch_ptr(ctx->device, &base);
+  if (e != hipSuccess)
+    return fail(ctx, NKF_ERR_HIP, "static scratch of device %d unavailable: %s", ctx->device, hipGetErrorString(e));
+  Carve cv{static_cast<char *>(base)};
+  carve_fwd(cv, rs, r_eff, fb, prm->r);
+  // no stage events either: the call enqueues kernels only
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  st = run_fwd(ctx, rs, prm, centroids, F, r_eff, out, eta_out, fb);
+  ctx->timing = timing;
+  return st;
 }
 
 nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, const float *p,

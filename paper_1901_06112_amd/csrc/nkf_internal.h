@@ -127,6 +127,15 @@ const double *launch_bwd_sum_partials(const double *partials, int nrows, int wid
                                       hipStream_t s, hipError_t *err);
 
 
+// ---- static_scratch.hip ------------------------------------------------------
+// Fixed-size device array of the allocation-free forward entry point.
+size_t static_scratch_bytes();
+// Takes the device address of `device`'s copy (once per device; `device` must
+// be current).  Returns the lookup's status on every later call.
+hipError_t static_scratch_init(int device);
+// The address found by static_scratch_init (hipErrorNotInitialized before it).
+hipError_t static_scratch_ptr(int device, void **out);
+
 // ---- kernels_pca.hip ---------------------------------------------------------
 // PCA patch guide: sample moments (FP64), projection of every pixel's patch.
 int pca_max_dim();

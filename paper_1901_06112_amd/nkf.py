@@ -29,7 +29,7 @@ EXPORTS = [
     "nkf_last_error", "nkf_set_workspace_limit", "nkf_workspace_bytes", "nkf_filter", "nkf_kmeans",
     "nkf_kmeans_iterate", "nkf_landmark_factor", "nkf_filter_landmarks", "nkf_filter_backward",
     "nkf_seed_indices", "nkf_spatial_taps", "nkf_enable_timing", "nkf_stage_times", "nkf_patch_pca",
-    "nkf_set_conv_chunks",
+    "nkf_set_conv_chunks", "nkf_filter_landmarks_noalloc",
 ]
 STAGES = ["seed", "kmeans", "factor", "embed", "conv", "backward"]
 
@@ -78,6 +78,7 @@ def load_library(path=LIB_PATH):
             "nkf_kmeans_iterate": (I, [P, I, I, I, P, I, P, PP, P, I, P]),
             "nkf_landmark_factor": (I, [I, I, P, D, D, P, P, P, ct.POINTER(I)]),
             "nkf_filter_landmarks": (I, [P, I, I, I, P, I, P, PP, P, P, I, P, P]),
+            "nkf_filter_landmarks_noalloc": (I, [P, I, I, I, P, I, P, PP, P, P, I, P, P]),
             "nkf_filter_backward": (I, [P, I, I, I, P, I, P, PP, P, P, P, I, P, P, P, P, P, P, P]),
             "nkf_seed_indices": (I, [ct.c_int64, I, U64, P]),
             "nkf_spatial_taps": (I, [I, D, I, ct.POINTER(I), P]),
@@ -273,9 +274,11 @@ def landmark_factor(centroids, sigma_r, tau=1e-10):
 
 def filter_landmarks(f, centroids, F, p=None, *, sigma_s=3.0, sigma_r=30.0, radius=-1,
                      spatial="gaussian", guide=None, patch_radius=3, precision="fp32", center=None,
-                     return_eta=False, out=None, eta=None):
+                     return_eta=False, out=None, eta=None, noalloc=False):
     """Forward pass with given landmarks [r, D] and factor F [r, r_eff]
-    (float64; host or device)."""
+    (float64; host or device).  noalloc=True calls the allocation-free entry
+    point (the library's fixed device scratch instead of its workspace; pass
+    F, out and eta as device tensors for a call that allocates nothing)."""
     if guide is None:
         guide = "explicit" if p is not None else "self"
     H, W, C = f.shape
@@ -296,7 +299,9 @@ def filter_landmarks(f, centroids, F, p=None, *, sigma_s=3.0, sigma_r=30.0, radi
     if return_eta and eta is None:
         eta = torch.empty((H, W), dtype=torch.float32, device=f.device)
     ctx = _cur_ctx(f)
-    _check(load_library().nkf_filter_landmarks(ctx, H, W, C, _dev_f32(f, "f"), D,
+    lib = load_library()
+    fn = lib.nkf_filter_landmarks_noalloc if noalloc else lib.nkf_filter_landmarks
+    _check(fn(ctx, H, W, C, _dev_f32(f, "f"), D,
                                                _dev_f32(p, "p") if guide == "explicit" else ct.c_void_p(0),
                                                ct.byref(prm), _dev_f32(centroids, "centroids"),
                                                ct.c_void_p(Ft.data_ptr()), int(r_eff), _ptr(out),
