@@ -63,8 +63,11 @@ enum { NKF_GUIDE_EXPLICIT = 0, NKF_GUIDE_SELF = 1, NKF_GUIDE_PATCH = 2 };
 /* Input precision of the distance / embedding contraction (k-means assignment
  * and the cross kernel B).  FP32 is the plain form; BF16 and FP16 round the
  * centred guide and landmarks to 16 bits and accumulate in FP32, with the
- * squared norms kept in FP32/FP64.  The spatial convolutions are the same in
- * every form: FP32 storage, FP64 accumulation within each pass. */
+ * squared norms kept in FP32/FP64.  The Gaussian-window convolutions store
+ * FP32 and accumulate each pass in FP64 in every form; the box window on up
+ * to three channels keeps its window sums and the contraction in FP64, with
+ * the embedding planes stored in FP64 in the plain form and FP32 in the
+ * 16-bit forms. */
 enum { NKF_PREC_FP32 = 0, NKF_PREC_BF16 = 1, NKF_PREC_FP16 = 2 };
 
 typedef struct {
@@ -80,7 +83,8 @@ typedef struct {
   uint64_t seed;           /* SplitMix64 seed of the k-means initialisation                      */
   double eig_rel_tol;      /* tau: eigenvalues alpha <= tau * max(alpha) are dropped (>= 0)      */
   double center;           /* f0 subtracted before and added after the filter (exact by affine
-                              equivariance); NAN means per-channel (min + max) / 2 of f          */
+                              equivariance); NAN means per-channel (min + max) / 2 of f.  The
+                              box window on C <= 3 sums in FP64 and needs no centring        */
 } nkf_params;
 
 /* Fills defaults: sigma_s 3, sigma_r 30, r 16, radius -1, Gaussian, SELF
@@ -102,7 +106,8 @@ const char *nkf_last_error(const nkf_ctx *ctx);
 /* Cap on the workspace size in bytes (0 = no cap).  A call that would need
  * more fails with NKF_ERR_OUT_OF_MEMORY before enqueuing work. */
 nkf_status nkf_set_workspace_limit(nkf_ctx *ctx, size_t bytes);
-/* Tile geometry of the convolution kernels (forward and backward): each
+/* Tile geometry of the Gaussian-window convolution kernels (forward and
+ * backward; the box-window kernel has fixed tiles): each
  * block streams its output tile in chunks of rows, and by default the number
  * of chunks per tile is the largest that still gives enough blocks to fill
  * the GPU, so small images run one chunk per tile.  nch > 0 requests nch

@@ -31,7 +31,7 @@ SOURCES = [
     "kernels_kmeans.hip",
     "kernels_embed.hip",
     "kernels_conv.hip",
-    "kernels_conv_box.hip",
+    "kernels_box.hip",
     "kernels_bwd.hip",
     "kernels_mfma.hip",
     "kernels_pca.hip",

@@ -45,6 +45,7 @@ struct nkf_ctx {
   hipEvent_t pinned_free = nullptr;  // after the last queued copy through `pinned`
   // the last PCA sample draw (it depends on N and the seed only)
   int conv_chunks = 0;  // nkf_set_conv_chunks
+  int num_cu = 0;       // compute units of the device
   int64_t pca_draw_N = -1;
   uint64_t pca_draw_seed = 0;
   std::vector<int64_t> pca_draw;
@@ -389,11 +390,31 @@ nkf_status factor(nkf_ctx *ctx, int r, int D, const double *c, double sigma_r, d
   return NKF_OK;
 }
 
+// The box window on up to three channels runs the FP64 box kernel; its plain
+// form (FP32 distances) keeps the embedding planes in FP64 as well.  The
+// backward's conv modes read FP32 planes, so it never asks for them.
+bool box_path(const Resolved &rs) { return rs.box && rs.C <= 3; }
+bool fwd_u64(const Resolved &rs, int prec) { return box_path(rs) && !use_mfma_distance(rs.g, prec); }
+
+// Partial-sum scratch of the box kernel for any r_eff <= r (its split count
+// depends on r_eff only through min(r_eff, 8)).
+size_t box_part_doubles(const Resolved &rs, int r, int num_cu, bool u64) {
+  if (!box_path(rs)) return 0;
+  size_t m = 0;
+  for (int re = 1; re <= (r < 8 ? r : 8); ++re) {
+    const size_t v = box_partials_doubles(rs.H, rs.W, rs.S, re, num_cu, u64 ? 1 : 0);
+    if (v > m) m = v;
+  }
+  return m;
+}
+
 // Workspace of the forward path after the landmarks are known.
 struct FwdBufs {
   float *f0;
   unsigned *mm;
-  float *u;
+  float *u;      // FP32 planes, or
+  double *u64;   // FP64 planes (box kernel, plain form)
+  double *box_part;
   float *eta_buf;
   float *f_planar;  // [C][N] when C > 3
   float *mu;     // [D] centring of the 16-bit distance path
@@ -403,10 +424,12 @@ struct FwdBufs {
   double *ct64;  // transposed FP64 landmarks of the FP32 embedding
 };
 
-void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r = kMaxLandmarks) {
+void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r, bool u64, int num_cu) {
   b.f0 = cv.take<float>(rs.C);
   b.mm = cv.take<unsigned>(center_scratch_words(rs.C));
-  b.u = cv.take<float>((size_t)r_eff * rs.N);
+  b.u = u64 ? nullptr : cv.take<float>((size_t)r_eff * rs.N);
+  b.u64 = u64 ? cv.take<double>((size_t)r_eff * rs.N) : nullptr;
+  b.box_part = cv.take<double>(box_part_doubles(rs, r_eff, num_cu, u64));
   b.eta_buf = cv.take<float>(rs.C > 3 ? rs.N : 1);
   b.f_planar = cv.take<float>(rs.C > 3 ? (size_t)rs.C * rs.N : 1);
   b.mu = cv.take<float>(rs.D);
@@ -437,10 +460,28 @@ nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, cons
       HIP_TRY(ctx, launch_embed_mfma(rs.g, c, prm->r, b.mu, F, b.F32, r_eff, prm->sigma_r, prm->prec, b.u,
                                      b.lm, ctx->stream));
     } else {
-      HIP_TRY(ctx, launch_embed(rs.g, c, prm->r, F, r_eff, prm->sigma_r, b.u, b.ct64, ctx->stream));
+      HIP_TRY(ctx, launch_embed(rs.g, c, prm->r, F, r_eff, prm->sigma_r, b.u, b.ct64, ctx->stream, b.u64));
     }
   }
   if (!conv) return NKF_OK;
+  if (box_path(rs)) {
+    BoxProblem bx{};
+    bx.H = rs.H;
+    bx.W = rs.W;
+    bx.C = rs.C;
+    bx.S = rs.S;
+    bx.r_eff = r_eff;
+    bx.f = rs.g.f;
+    bx.u = b.u64 ? static_cast<const void *>(b.u64) : static_cast<const void *>(b.u);
+    bx.u_fp64 = b.u64 != nullptr;
+    bx.out = out;
+    bx.eta_out = eta_out;
+    bx.part = b.box_part;
+    bx.num_cu = ctx->num_cu;
+    StageTimer tm(ctx, NKF_STAGE_CONV);
+    HIP_TRY(ctx, launch_box(bx, ctx->stream));
+    return NKF_OK;
+  }
   ConvProblem pb{};
   pb.H = rs.H;
   pb.W = rs.W;
@@ -546,6 +587,10 @@ nkf_status nkf_create(nkf_ctx **out, void *hip_stream) {
   // device address of this device's static scratch (allocation-free entry
   // point); a failed lookup only disables that entry point
   (void)static_scratch_init(c->device);
+  if (hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    c->num_cu = 0;
+  }
   *out = c;
   return NKF_OK;
 }
@@ -792,10 +837,11 @@ nkf_status nkf_filter_landmarks(nkf_ctx *ctx, int H, int W, int C, const float *
   if (r_eff < 1 || r_eff > prm->r) return fail(ctx, NKF_ERR_INVALID_ARG, "need 1 <= r_eff <= r");
   Carve dry{nullptr};
   FwdBufs fb;
-  carve_fwd(dry, rs, r_eff, fb);
+  const bool u64 = fwd_u64(rs, prm->prec);
+  carve_fwd(dry, rs, r_eff, fb, kMaxLandmarks, u64, ctx->num_cu);
   if ((st = ensure_workspace(ctx, dry.off)) != NKF_OK) return st;
   Carve cv{ctx->ws};
-  carve_fwd(cv, rs, r_eff, fb);
+  carve_fwd(cv, rs, r_eff, fb, kMaxLandmarks, u64, ctx->num_cu);
   return run_fwd(ctx, rs, prm, centroids, F, r_eff, out, eta_out, fb);
 }
 
@@ -809,7 +855,8 @@ nkf_status nkf_filter_landmarks_noalloc(nkf_ctx *ctx, int H, int W, int C, const
   if (r_eff < 1 || r_eff > prm->r) return fail(ctx, NKF_ERR_INVALID_ARG, "need 1 <= r_eff <= r");
   Carve dry{nullptr};
   FwdBufs fb;
-  carve_fwd(dry, rs, r_eff, fb, prm->r);
+  const bool u64 = fwd_u64(rs, prm->prec);
+  carve_fwd(dry, rs, r_eff, fb, prm->r, u64, ctx->num_cu);
   if (dry.off > static_scratch_bytes())
     return fail(ctx, NKF_ERR_OUT_OF_MEMORY,
                 "this problem needs %zu bytes of scratch; the static scratch holds %zu (use nkf_filter_landmarks)",
@@ -819,7 +866,7 @@ nkf_status nkf_filter_landmarks_noalloc(nkf_ctx *ctx, int H, int W, int C, const
   if (e != hipSuccess)
     return fail(ctx, NKF_ERR_HIP, "static scratch of device %d unavailable: %s", ctx->device, hipGetErrorString(e));
   Carve cv{static_cast<char *>(base)};
-  carve_fwd(cv, rs, r_eff, fb, prm->r);
+  carve_fwd(cv, rs, r_eff, fb, prm->r, u64, ctx->num_cu);
   // no stage events either: the call enqueues kernels only
   const bool timing = ctx->timing;
   ctx->timing = false;
@@ -841,7 +888,7 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
     c = cv.take<float>((size_t)r * rs.D);
     idx = cv.take<int64_t>(r);
     Fd = cv.take<double>((size_t)r * r);
-    carve_fwd(cv, rs, r, fb);
+    carve_fwd(cv, rs, r, fb, kMaxLandmarks, fwd_u64(rs, prm->prec), ctx->num_cu);
   };
   KmBufs kb;
   FwdBufs fb;
@@ -928,7 +975,7 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
   float *out_s, *eta_s, *ab, *dud, *du, *df_s;
   double *Fd, *red, *red2, *sig;
   auto carve_all = [&](Carve &cv) {
-    carve_fwd(cv, rs, r_eff, fb);
+    carve_fwd(cv, rs, r_eff, fb, kMaxLandmarks, false, ctx->num_cu);
     out_s = cv.take<float>((size_t)rs.N * C);
     eta_s = cv.take<float>(rs.N);
     ab = cv.take<float>((size_t)rs.N * 4);

@@ -54,7 +54,6 @@ hipError_t launch_S(ConvArgs a, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_conv_contract(const ConvProblem &pb, hipStream_t s) {
-  if (pb.box && pb.C <= 3) return launch_conv_contract_box(pb, s);
   ConvArgs a{};
   a.H = pb.H;
   a.W = pb.W;

@@ -54,7 +54,7 @@ template <int TPX, int DS, int BT>
 __global__ __launch_bounds__(BT) void embed_kernel(Guide g, int64_t N, const float *__restrict__ c,
                                                    const double *__restrict__ ct64, int RP, int r,
                                                    const double *__restrict__ F, int r_eff, double inv2s2,
-                                                   float *__restrict__ u) {
+                                                   float *__restrict__ u, double *__restrict__ u64) {
   constexpr int NG = BT / TPX;
   extern __shared__ double smem_d[];
   const int D = g.D;
@@ -180,7 +180,12 @@ __global__ __launch_bounds__(BT) void embed_kernel(Guide g, int64_t N, const flo
       if (valid) {
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-          if (kb + q < r_eff) u[(int64_t)(kb + q) * N + x] = (float)acc[q];
+          if (kb + q < r_eff) {
+            if (u64)
+              u64[(int64_t)(kb + q) * N + x] = acc[q];
+            else
+              u[(int64_t)(kb + q) * N + x] = (float)acc[q];
+          }
       }
     }
   }
@@ -390,7 +395,7 @@ size_t embed_scratch_doubles(const Guide &g, int r) {
 }
 
 hipError_t launch_embed(const Guide &g, const float *c, int r, const double *F, int r_eff, double sigma_r,
-                        float *u, double *ct64, hipStream_t s) {
+                        float *u, double *ct64, hipStream_t s, double *u64) {
   const int64_t N = (int64_t)g.H * g.W;
   const double inv2s2 = isinf(sigma_r) ? 0.0 : 1.0 / (2.0 * sigma_r * sigma_r);
   // DS > 0 keeps the landmarks as FP64 [r][D] where the generic form stages the guide tile
@@ -424,7 +429,7 @@ hipError_t launch_embed(const Guide &g, const float *c, int r, const double *F, 
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);                             \
     if (e != hipSuccess) return e;                                                                            \
     hipLaunchKernelGGL((embed_kernel<T, DSV, DSV ? 256 : 512>), dim3((unsigned)blocks), dim3(DSV ? 256 : 512), \
-                       sm, s, g, N, c, ct64, RP, r, F, r_eff, inv2s2, u);                                     \
+                       sm, s, g, N, c, ct64, RP, r, F, r_eff, inv2s2, u, u64);                                \
     break;
     NKF_EMBED(100, 64, 0) NKF_EMBED(101, 64, 1) NKF_EMBED(102, 64, 2) NKF_EMBED(103, 64, 3) NKF_EMBED(104, 64, 4)
     NKF_EMBED(0, 32, 0) NKF_EMBED(1, 32, 1) NKF_EMBED(2, 32, 2) NKF_EMBED(3, 32, 3) NKF_EMBED(4, 32, 4)

@@ -74,8 +74,9 @@ hipError_t launch_center(const float *f, int64_t N, int C, double center, float 
 // u[k][x] = sum_j F[j][k] exp(-|p(x) - c_j|^2 / (2 sigma_r^2)), planar [r_eff][N] float32.
 // ct64 is scratch of embed_scratch_doubles(g, r) doubles (transposed FP64 landmarks).
 size_t embed_scratch_doubles(const Guide &g, int r);
+// u64 (nullable): write the planes as FP64 [r_eff][N] there instead of u.
 hipError_t launch_embed(const Guide &g, const float *c, int r, const double *F, int r_eff,
-                        double sigma_r, float *u, double *ct64, hipStream_t s);
+                        double sigma_r, float *u, double *ct64, hipStream_t s, double *u64 = nullptr);
 
 // ---- kernels_conv.hip -------------------------------------------------------
 struct ConvProblem {
@@ -92,8 +93,24 @@ struct ConvProblem {
   int force_nch;      // > 0: row chunks per tile (tile-geometry control); 0: automatic
 };
 hipError_t launch_conv_contract(const ConvProblem &pb, hipStream_t s);
-// Box-kernel form for C <= 3 (kernels_conv_box.hip).
-hipError_t launch_conv_contract_box(const ConvProblem &pb, hipStream_t s);
+
+// ---- kernels_box.hip --------------------------------------------------------
+// Box-window convolutions + contraction + normalisation for C <= 3 with FP64
+// sums throughout; u is FP64 (u_fp64) or FP32 planes [r_eff][N].
+struct BoxProblem {
+  int H, W, C, S, r_eff;
+  const float *f;     // [H, W, C]
+  const void *u;      // [r_eff][N], double when u_fp64 else float
+  int u_fp64;
+  float *out;         // [H, W, C]
+  float *eta_out;     // nullable [N]
+  double *part;       // box_partials_doubles(...) doubles (unused when that is 0)
+  int num_cu;         // compute units of the device (0: 256)
+};
+// k ranges per tile and the partial-sum scratch they need.
+int box_splits(int H, int W, int S, int r_eff, int num_cu, int u_fp64);
+size_t box_partials_doubles(int H, int W, int S, int r_eff, int num_cu, int u_fp64);
+hipError_t launch_box(const BoxProblem &pb, hipStream_t s);
 
 // ---- kernels_bwd.hip --------------------------------------------------------
 // Backward passes (C <= 3).  mode 1: du_dir planes; 2: sigma_s partial sums

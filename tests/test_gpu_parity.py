@@ -84,6 +84,17 @@ def _report_conditioned(name, f, p, c32, sigma_s, sigma_r, S, g, go, spatial="ga
         assert np.all(err[~well] <= bound[~well])
 
 
+def _report_box(name, g, go, tol=TOL_255):
+    """The box-window kernel keeps u, the window sums and the contraction in
+    FP64: 1e-4 on every entry, including the pixels whose FP32-storage bound
+    would exceed it."""
+    err = np.abs(g - go)
+    i = np.unravel_index(np.argmax(err), err.shape)
+    print(f"[{name}] max|dg|={err.max():.3e} at {i} p99.9={np.quantile(err, 0.999):.3e} over {err.size} entries",
+          flush=True)
+    assert err.max() <= tol, f"{name}: max abs error {err.max():.3e} > {tol}"
+
+
 @pytest.mark.parametrize("h,w", [(96, 80), (37, 101)])
 def test_color_blf_small(h, w):
     f, prm = synth.workload("color_blf_256", h, w)
@@ -157,7 +168,7 @@ def test_box_window_patch_guide(r):
     gg, oo = g.copy(), go.copy()
     gg[~keep] = 0.0
     oo[~keep] = 0.0
-    _report_conditioned(f"nlm_patch_r{r}", f, pg, c32, 1.0, prm["sigma_r"], prm["S"], gg, oo, spatial="box")
+    _report_box(f"nlm_patch_r{r}", gg, oo)
 
 
 def test_patch_guide_radius2_odd_width():
@@ -176,7 +187,7 @@ def test_patch_guide_radius2_odd_width():
     gg, oo = g.copy(), go.copy()
     gg[both] = 0.0
     oo[both] = 0.0
-    _report_conditioned("nlm_patch_pr2", f, pg, c32, 1.0, sr, 4, gg, oo, spatial="box")
+    _report_box("nlm_patch_pr2", gg, oo)
 
 
 def test_explicit_wide_guide_many_landmarks():
@@ -259,7 +270,7 @@ def test_box_window_colour_and_gray(C, S, h, w):
     c32 = _landmarks(P, 12, 3, 5)
     g, eta, _ = _run_case(f, f, c32, 1.0, 30.0, S, spatial="box", guide="self")
     go, etao = _oracle(f, f, c32, 1.0, 30.0, S, spatial="box")
-    _report_conditioned(f"box_C{C}_S{S}", f, f, c32, 1.0, 30.0, S, g, go, spatial="box")
+    _report_box(f"box_C{C}_S{S}", g, go)
 
 
 @pytest.mark.parametrize("C,h,w", [(1, 37, 29), (2, 33, 31), (3, 41, 27), (4, 29, 35)])

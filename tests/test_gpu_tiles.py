@@ -1,16 +1,20 @@
 """Oracle parity of the convolution kernels at the tile geometry of the large
 workloads (Algorithm 1, Section III).
 
-Each block of the convolution kernels streams its output tile in chunks of
-rows through an LDS ring; small images get one chunk per tile, large ones up
-to eight, so the ring wraps only there.  These tests force the chunk counts
-of the large workloads (nkf_set_conv_chunks) on images the oracle handles in
-full, and compare sampled pixels of the full-size workloads, in their own
-launch configuration, with the oracle evaluated pixel by pixel.
+Each block of the Gaussian-window kernels (forward and backward) streams its
+output tile in chunks of rows through an LDS ring; small images get one
+chunk per tile, large ones up to eight, so the ring wraps only there.  These
+tests force the chunk counts of the large workloads (nkf_set_conv_chunks) on
+images the oracle handles in full, and compare sampled pixels of the
+full-size workloads, in their own launch configuration, with the oracle
+evaluated pixel by pixel.  The box-window kernel has fixed tiles of 56 (or
+48) rows and is checked here on images with partial tiles in both
+directions.
 
 Bars as in test_gpu_parity.py: 1e-4 on the 0-255 scale (1e-4 / 255 on the
 [0, 1] hyperspectral scale) on every pixel whose first-order FP32 storage
-bound is below it; the rest within that bound.
+bound is below it and the rest within that bound; the box window (FP64
+throughout) 1e-4 on every pixel.
 """
 import contextlib
 
@@ -65,6 +69,15 @@ def _grade(name, g, go, bound, tol):
         assert np.all(err[~well] <= EPS_STORE * bound[~well]), name
 
 
+def _grade_box(name, g, go, tol):
+    """Box window: FP64 from the embedding planes to the output, so 1e-4 on
+    every entry."""
+    err = np.abs(g - go)
+    i = np.unravel_index(np.argmax(err), err.shape)
+    print(f"[{name}] max|dg|={err.max():.3e} at {i} over {err.size} entries", flush=True)
+    assert err.max() <= tol, name
+
+
 def _filter(f, p, c32, sigma_s, sigma_r, S, nch, **kw):
     nkf = _nkf()
     Q, al, F, reff = nkf.landmark_factor(c32.astype(np.float64), sigma_r)
@@ -80,32 +93,29 @@ def _filter(f, p, c32, sigma_s, sigma_r, S, nch, **kw):
     return g
 
 
-@pytest.mark.parametrize("nch", [2, 4, 8])
-def test_box_patch_guide_multichunk(nch):
-    """The colour NLM kernel (21 x 21 box, 7 x 7 x 3 patches) with the ring
-    wrapping: 4 chunks per tile is the 1024^2 workload's geometry; 300 rows
-    leave a partial last tile for every chunk count."""
+def test_box_patch_guide_tiles():
+    """The colour NLM kernel (21 x 21 box, 7 x 7 x 3 patches): 300 x 72 pixels
+    leave partial tiles in both directions; the FP32 form keeps the planes in
+    FP64."""
     f, prm = synth.workload("color_nlm_1024", 300, 72)
     pg = exact.patch_guide(f.astype(np.float64), prm["patch_radius"])
     c32 = _landmarks(pg.reshape(-1, pg.shape[2]), 32, prm["landmark_seed"], 4)
-    g = _filter(f, None, c32, 1.0, prm["sigma_r"], prm["S"], nch, spatial="box", guide="patch",
+    g = _filter(f, None, c32, 1.0, prm["sigma_r"], prm["S"], 0, spatial="box", guide="patch",
                 patch_radius=prm["patch_radius"])
     go = nystrom.nystrom_filter(f.astype(np.float64), pg, c32.astype(np.float64), 1.0, prm["sigma_r"],
                                 prm["S"], "box")
-    B = nystrom.storage_error_bound(f, pg, c32.astype(np.float64), 1.0, prm["sigma_r"], prm["S"], "box")
-    _grade(f"box_patch_nch{nch}", g, go, B, TOL_255)
+    _grade_box("box_patch", g, go, TOL_255)
 
 
-@pytest.mark.parametrize("C,nch", [(3, 8), (1, 3)])
-def test_box_self_guide_multichunk(C, nch):
+@pytest.mark.parametrize("C", [3, 1])
+def test_box_self_guide_tiles(C):
     f, _ = synth.workload("color_blf_256", 270, 45, seed=31)
     f = np.ascontiguousarray(f[:, :, :C])
     c32 = _landmarks(f.reshape(-1, C).astype(np.float64), 12, 3, 5)
-    g = _filter(f, None, c32, 1.0, 30.0, 7, nch, spatial="box", guide="self")
+    g = _filter(f, None, c32, 1.0, 30.0, 7, 0, spatial="box", guide="self")
     go = nystrom.nystrom_filter(f.astype(np.float64), f.astype(np.float64), c32.astype(np.float64), 1.0,
                                 30.0, 7, "box")
-    B = nystrom.storage_error_bound(f, f, c32.astype(np.float64), 1.0, 30.0, 7, "box")
-    _grade(f"box_C{C}_nch{nch}", g, go, B, TOL_255)
+    _grade_box(f"box_C{C}", g, go, TOL_255)
 
 
 @pytest.mark.parametrize("nch", [3, 8])
@@ -184,8 +194,11 @@ def test_backward_multichunk(nch):
 
 def _sampled_coords(H, W, n, seed):
     rng = np.random.default_rng(seed)
+    # corners, Gaussian-kernel chunk and tile edges (32-row chunks, 32-column
+    # tiles), box-kernel tile edges (48 or 56 rows, 44 columns at S = 10)
     edges = [[0, 0], [H - 1, W - 1], [0, W - 1], [H - 1, 0], [127, 31], [128, 32], [255, 33],
-             [256, 64], [127, 500 % W], [128, 95], [383, 63], [384, 64], [511, 127], [512, 128]]
+             [256, 64], [127, 500 % W], [128, 95], [383, 63], [384, 64], [511, 127], [512, 128],
+             [47, 43], [48, 44], [55, 87], [56, 88], [95, 131], [96, 132], [111, 43], [112, 44]]
     edges = [[min(y, H - 1), min(x, W - 1)] for y, x in edges]
     return np.concatenate([rng.integers(0, [H, W], (n, 2)), np.array(edges)])
 
@@ -208,8 +221,7 @@ def test_full_size_nlm_1024_sampled():
     pg = exact.patch_guide(f.astype(np.float64), prm["patch_radius"])
     args = (f.astype(np.float64), pg, c32.astype(np.float64), 1.0, prm["sigma_r"], prm["S"], coords)
     go, _ = nystrom.nystrom_filter_at(*args, spatial="box")
-    B = nystrom.storage_error_bound_at(*args, spatial="box")
-    _grade("nlm1024_sampled", g[coords[:, 0], coords[:, 1]], go, B, TOL_255)
+    _grade_box("nlm1024_sampled", g[coords[:, 0], coords[:, 1]], go, TOL_255)
     assert np.isfinite(g).all()
 
 
