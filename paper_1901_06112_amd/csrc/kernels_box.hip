@@ -12,7 +12,7 @@
 // here: every stage is FP64, so the uncentred numerator costs no accuracy and
 // g = zeta / eta directly.
 //
-// A block owns an output tile of TW = 64 - 2S columns by 56 rows (40 or 48
+// A block owns an output tile of TW = 64 - 2S columns by 56 rows (32 to 48
 // for the larger radii); the 64 columns of the tile plus S on each side are the threads'
 // columns.  For each plane k:
 //   vertical pass    thread (column, plane p, half of the rows) walks down its
@@ -47,7 +47,7 @@ constexpr int kXW = 64;         // tile width including the 2S halo columns
 // windows would not leave registers for 56 (a register spill puts scratch
 // loads on the counter the plane prefetch relies on).
 constexpr int tile_rows(int S, bool u_fp64) {
-  return u_fp64 ? (S <= 8 ? 56 : S <= 13 ? 48 : 40) : (S <= 11 ? 56 : S <= 13 ? 48 : 40);
+  return u_fp64 ? (S <= 8 ? 56 : S <= 10 ? 48 : S <= 12 ? 40 : 32) : (S <= 10 ? 56 : S <= 13 ? 48 : 40);
 }
 constexpr int kNP = 4;          // planes per k: E and up to three channels
 // LDS strides of the vertical sums vbuf[row][plane][column] in doubles.  An
@@ -105,6 +105,27 @@ __device__ __forceinline__ unsigned opaque_s(unsigned v) {
   return v;
 }
 
+// Value of lane J of each quad (four consecutive lanes), in every lane of the
+// quad: DPP quad_perm [J, J, J, J] on each 32-bit half.
+template <int J>
+__device__ __forceinline__ double quad_bcast(double v) {
+  constexpr int ctl = J * 0x55;
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, ctl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctl, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// quad_bcast for a lane index known after unrolling
+__device__ __forceinline__ double quad_bcast_at(double v, int j) {
+  switch (j & 3) {
+    case 0: return quad_bcast<0>(v);
+    case 1: return quad_bcast<1>(v);
+    case 2: return quad_bcast<2>(v);
+    default: return quad_bcast<3>(v);
+  }
+}
+
 // s_waitcnt vmcnt(0) (expcnt and lgkmcnt left free): the image values are in
 // registers before the first plane's loads are issued, so that at most one
 // plane's loads per thread (fewer than the 63 the counter tracks) are ever in
@@ -119,6 +140,7 @@ __global__ __launch_bounds__(kBT) void box_kernel(BoxArgs a) {
   constexpr int G = 2 * S + 1;           // window length
   constexpr int IRH = kTHH + 2 * S;      // input rows of one half of the vertical pass
   constexpr int RUN = TW / 2;            // output columns per horizontal-pass thread
+  static_assert(kTH % 8 == 0 && kTH <= 64, "horizontal pass: 8 rows per wave, 8 waves");
   __shared__ double vbuf[kTH * kRS];
   __shared__ double ubuf[kTH * kUS];
 
@@ -163,17 +185,28 @@ __global__ __launch_bounds__(kBT) void box_kernel(BoxArgs a) {
     freg[q] = vp == 0 ? 1.0f : (ok ? a.f[((int64_t)gy * W + gx) * C + (vp - 1)] : 0.0f);
   }
   wait_vm_all();
-  UT ureg[IRH];
-  {
-    const __amdgpu_buffer_rsrc_t r0 = plane_rsrc(k0);
+
+  // The four threads of a column (a quad of lanes, one per plane) split its
+  // rows: thread p loads rows p, p + 4, ..., M of them, and each row's value
+  // reaches the other three by a quad broadcast.  Two register sets
+  // alternate: the loads of plane k + 1 are issued at the start of plane k.
+  constexpr int M = (IRH + 3) / 4;
+  const unsigned voffp = voff0 + (unsigned)vp * rowbytes;
+  UT own[2][M];
+  auto load_plane = [&](UT (&dst)[M], int k) {
+    const __amdgpu_buffer_rsrc_t rk = plane_rsrc(k);
+    // the row stride is opaque per plane so that the M offsets are not hoisted
+    const unsigned rb4 = opaque_s(4u * rowbytes);
+    unsigned vo = voffp;
 #pragma unroll
-    for (int q = 0; q < IRH; ++q) {
-      ureg[q] = ld<UT>(r0, voff0 + (unsigned)q * rowbytes);
-      // issued in row order, as in the plane loop, so that the loop head
-      // waits for row 0's load alone
+    for (int m = 0; m < M; ++m) {
+      dst[m] = ld<UT>(rk, vo);
+      vo += rb4;
+      // issued in row order, so that each use waits for its own row alone
       __builtin_amdgcn_sched_barrier(0);
     }
-  }
+  };
+  load_plane(own[0], k0);
 
   // ---- horizontal-pass role: 8 rows x 4 planes x 2 column halves per wave --
   const int ho = (tid >> 6) * 8 + (tid & 7);
@@ -183,40 +216,29 @@ __global__ __launch_bounds__(kBT) void box_kernel(BoxArgs a) {
 #pragma unroll
   for (int j = 0; j < RUN; ++j) acc[j] = 0.0;
 
-  for (int k = k0; k < k1; ++k) {
-    // the next plane's loads (the last plane reloads itself: no branch in the loop)
-    const int kn = k + 1 < k1 ? k + 1 : k;
-    const __amdgpu_buffer_rsrc_t rn = plane_rsrc(kn);
-    // running offset of the next row to load; the row stride is opaque per
-    // plane so that the per-row offsets are not hoisted out of the loop
-    const unsigned rb = opaque_s(rowbytes);
-    unsigned vo = voff0;
+  // one plane: the vertical pass from `cur`, the next plane's loads into `nxt`,
+  // then the horizontal pass
+  auto plane = [&](UT (&cur)[M], UT (&nxt)[M], int k) {
+    // the next plane's loads (the last plane reloads itself: no branch)
+    load_plane(nxt, k + 1 < k1 ? k + 1 : k);
 #pragma unroll
     for (int q = 0; q < IRH; ++q) touch_v(freg[q]);
+    // u of the last G rows, a ring indexed by row mod G
+    double fifo[G];
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < IRH; ++q) {
-      s = fma((double)ureg[q], (double)freg[q], s);
-      if (q >= G) {
-        const int ql = q - G;  // the row leaving the window
-        s = fma(-(double)ureg[ql], (double)freg[ql], s);
-        ureg[ql] = ld<UT>(rn, vo);
-        vo += rb;
-      }
+      const double uq = quad_bcast_at((double)cur[q >> 2], q);
+      s = fma(uq, (double)freg[q], s);
+      if (q >= G) s = fma(-fifo[q % G], (double)freg[q - G], s);  // the row leaving the window
+      fifo[q % G] = uq;
       if (q >= 2 * S) {
         const int o = vh * kTHH + q - 2 * S;  // output row centred on input row q - S
         vbuf[o * kRS + vp * kPS + vc] = s;
         // the four plane threads of a column store the same value
-        ubuf[o * kUS + vc] = (double)ureg[q - S];
+        ubuf[o * kUS + vc] = fifo[(q - S) % G];
       }
-      // rows stay in program order, so each load is issued as soon as its
-      // register is free (the scheduler would otherwise bunch them at the end)
       __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int ql = IRH - G; ql < IRH; ++ql) {
-      ureg[ql] = ld<UT>(rn, vo);
-      vo += rb;
     }
     __syncthreads();
     if (hact) {
@@ -232,6 +254,11 @@ __global__ __launch_bounds__(kBT) void box_kernel(BoxArgs a) {
       }
     }
     __syncthreads();
+  };
+
+  for (int k = k0; k < k1; k += 2) {
+    plane(own[0], own[1], k);
+    if (k + 1 < k1) plane(own[1], own[0], k + 1);
   }
 
   // ---- epilogue -------------------------------------------------------------
