@@ -12,10 +12,17 @@ planes fused with the contraction and normalisation.  Inputs are resident in
 HBM before the timed region.
 
 Prints one JSON line; ``roofline`` describes the convolution + contraction
-kernel, timed with HIP events on the stream it runs on; ``cpu_baseline`` is
-the FP64 oracle on a bounded crop of the same image, with (``quality``) the
-PSNR of the GPU output against the exact brute-force filter on the centre
-256 x 256 pixels.  ``workloads`` holds the
+kernel, timed with HIP events on the stream it runs on (``launch_ms``), next
+to the rocprofv3 average of the committed profile of the same command
+(``launch_ms_rocprof``); ``cpu_baseline`` is the FP64 oracle on a bounded
+crop of the same image with all host cores (Lloyd iterations in one process,
+Algorithm 1 over row strips in a pool of worker processes), with the
+single-core figure beside it and (``quality``) the PSNR of the GPU output
+against the exact brute-force filter on the centre 256 x 256 pixels.  Each
+entry of ``workloads`` carries the roofline of its convolution stage (HBM for
+the box window, FP64-rate ALU for the Gaussian) and the MFMA fractions of
+its 16-bit stages; the differentiation batch carries the ALU fraction of its
+forward and forward + backward.  ``workloads`` holds the
 other configurations, each timed the same way (whole calls, inputs resident):
 the hyperspectral BLF (512 x 512 x 128, d = 128) in the plain FP32 form and
 the BF16 precision form, the colour NLM (1024 x 1024, 7 x 7 x 3 patches,
@@ -53,6 +60,32 @@ def conv_flops_per_pixel(r_eff, C, T):
     return 4 * P * T + r_eff * C + 2 * P + 2 * C
 
 
+def embed_flops_per_pixel(r_eff, r, D):
+    """Embedding u = F^T b: 3 flops per guide dimension and landmark for the
+    distances (difference, multiply, add), one exponential per landmark
+    (counted as one flop) and 2 r r_eff for the mix."""
+    return 3 * D * r + r + 2 * r * r_eff
+
+
+def fwd_flops_per_pixel(r_eff, r, D, C, T):
+    """Forward with given landmarks: embedding + convolutions + contraction."""
+    return embed_flops_per_pixel(r_eff, r, D) + conv_flops_per_pixel(r_eff, C, T)
+
+
+def bwd_flops_per_pixel(r_eff, r, D, C, T):
+    """Backward with the forward's output and eta given (as the autograd
+    function runs it), per pixel, with P = r_eff (C + 1) planes:
+    the embedding recomputed; du_dir: the P planes convolved again (4 P T) and
+    combined with (beta, a) (2 P); the sigma_s pass: P planes through the w1
+    and w1' row taps and the matching column taps (8 P T) and the products
+    (2 P); the adjoint: P planes (4 P T), du and df (4 P); the reduction: the
+    distances again (3 D r), db = F du (2 r r_eff), dp (3 D r), the sigma_r
+    terms (4 r) and R = sum b du_dir^T (2 r r_eff); (beta, a): 4 C."""
+    P = r_eff * (C + 1)
+    return (embed_flops_per_pixel(r_eff, r, D) + (4 * P * T + 2 * P) + (8 * P * T + 2 * P)
+            + (4 * P * T + 4 * P) + (6 * D * r + 4 * r + 4 * r * r_eff) + 4 * C)
+
+
 def conv_bytes_per_pixel(r_eff, C):
     """Compulsory HBM bytes of the stage per pixel: u read (r_eff floats),
     f read and g written (C floats each)."""
@@ -85,6 +118,23 @@ def _traffic():
         return None
 
 
+PROFILE_HEADLINE = os.path.join("profiles", "conv_color_blf_2048.md")
+
+
+def rocprof_launch_ms(kernel_prefix, path=PROFILE_HEADLINE):
+    """Average duration (ms) of the kernel whose name starts with kernel_prefix
+    in a committed rocprofv3 --stats summary (a markdown table with the
+    average in microseconds), or None."""
+    try:
+        for line in open(os.path.join(ROOT, path)):
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 3 and cells[0].strip("`").startswith(kernel_prefix):
+                return float(cells[2]) / 1e3
+    except (OSError, ValueError):
+        pass
+    return None
+
+
 def copy_calibration(nbytes, reps):
     """Device-to-device copies of a known size, for scaling the FETCH_SIZE and
     WRITE_SIZE counters: each copy reads and writes nbytes."""
@@ -95,6 +145,77 @@ def copy_calibration(nbytes, reps):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_workers():
+    """Worker processes for the all-cores oracle: the cores this process may
+    run on, at most 16 (a one-GPU share of the GPU hosts)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_strip(args):
+    """Algorithm 1 (FP64 oracle) on rows [y0, y1) of the image: the strip plus
+    an S-row halo on each side, so that every window of the kept rows sees the
+    same pixels as in the whole image (zero extension only at the image edge)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import nystrom
+    fc, c, y0, y1, sigma_s, sigma_r, S = args
+    a, b = max(0, y0 - S), min(fc.shape[0], y1 + S)
+    with threadpool_limits(1):
+        g = nystrom.nystrom_filter(fc[a:b], fc[a:b], c, sigma_s, sigma_r, S)
+    return y0, np.ascontiguousarray(g[y0 - a:y0 - a + (y1 - y0)])
+
+
+def cpu_baseline_parallel(crop=1024, workers=None):
+    """The FP64 oracle on the crop x crop centre crop with all host cores: the
+    Lloyd iterations in one process (NumPy, BLAS threads = all cores), then
+    Algorithm 1 over horizontal strips in a pool of worker processes (the
+    strips' outputs equal the whole-image output exactly).  Run before the GPU
+    is initialised (the pool is forked)."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    from oracle import kmeans, seeding
+    from paper_1901_06112_amd import synth
+
+    workers = workers or cpu_workers()
+    f, prm = synth.workload(WORKLOAD)
+    y0 = (f.shape[0] - crop) // 2
+    fc = np.ascontiguousarray(f[y0:y0 + crop, y0:y0 + crop]).astype(np.float64)
+    nstrip = 4 * workers
+    bounds = [(crop * i // nstrip, crop * (i + 1) // nstrip) for i in range(nstrip)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        t0 = time.perf_counter()
+        P = fc.reshape(-1, 3)
+        c0 = P[seeding.distinct_indices(P.shape[0], prm["r"], prm["landmark_seed"])]
+        c, _, _ = kmeans.lloyd(P, c0, prm["iters"])
+        t1 = time.perf_counter()
+        parts = pool.map(_oracle_strip, [(fc, c, a, b, prm["sigma_s"], prm["sigma_r"], prm["S"])
+                                         for a, b in bounds])
+        t2 = time.perf_counter()
+    assert sum(p[1].shape[0] for p in parts) == crop
+    return {"value": crop * crop / (t2 - t0) / 1e6, "cores": workers, "seconds": round(t2 - t0, 2),
+            "kmeans_s": round(t1 - t0, 2), "filter_s": round(t2 - t1, 2),
+            "sample": f"{crop}x{crop} centre crop: {prm['iters']} Lloyd iterations in one process, then "
+                      f"Algorithm 1 in FP64 over {nstrip} row strips (S-row halos) on {workers} worker processes"}
 
 
 def cpu_baseline(crop=1024, gpu_out=None, gpu_landmarks=None, qcrop=256):
@@ -122,8 +243,9 @@ def cpu_baseline(crop=1024, gpu_out=None, gpu_landmarks=None, qcrop=256):
         nystrom.nystrom_filter(fc, fc, c, prm["sigma_s"], prm["sigma_r"], prm["S"])
         dt = time.perf_counter() - t0
     res = {"value": crop * crop / dt / 1e6, "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+           "cpu_model": cpu_model(),
            "sample": f"{crop}x{crop} centre crop of the 2048x2048 image, full oracle path "
-                     f"(seeding, {prm['iters']} Lloyd iterations, Algorithm 1 in FP64), {dt:.1f} s"}
+                     f"(seeding, {prm['iters']} Lloyd iterations, Algorithm 1 in FP64), one core, {dt:.1f} s"}
     if gpu_out is not None:
         m, q = prm["S"], qcrop
         yq = (f.shape[0] - q) // 2
@@ -200,6 +322,23 @@ def leg_precision(name, steps, warmup):
                                     steps, warmup, ft)
         ent = {"ms_per_call": round(ms, 3), "Mpixel_s": round(N / ms / 1e3, 2), "r_eff": r_eff,
                "stages_ms": st}
+        conv_s = st["conv"] * 1e-3
+        if kw.get("spatial") == "box":
+            # box conv: HBM-bound; compulsory bytes = the embedding planes (FP64
+            # in the plain form, FP32 in the 16-bit form), f read, g written
+            ub = 8 if prec == "fp32" else 4
+            nbytes = N * (r_eff * ub + 8 * C)
+            ent["conv_roofline"] = {"kernel": "box_kernel", "bound": "hbm", "unit": "GB/s",
+                                    "achieved": round(nbytes / conv_s / 1e9, 1), "peak": PEAK_HBM_GBS,
+                                    "frac": round(nbytes / conv_s / 1e9 / PEAK_HBM_GBS, 4),
+                                    "algorithmic_bytes_per_launch": nbytes}
+        else:
+            T = 2 * prm["S"] + 1
+            fl = conv_flops_per_pixel(r_eff, C, T) * N
+            ent["conv_roofline"] = {"kernel": "conv_kernel", "bound": "alu", "unit": "TFLOP/s",
+                                    "achieved": round(fl / conv_s / 1e12, 2), "peak": PEAK_FP64_TFLOPS,
+                                    "frac": round(fl / conv_s / 1e12 / PEAK_FP64_TFLOPS, 4),
+                                    "algorithmic_flops_per_launch": fl}
         if prec != "fp32":
             km = prm["iters"] * N * 2.0 * D * prm["r"] / (st["kmeans"] * 1e-3) / 1e12
             em = N * (2.0 * D * prm["r"] + 2.0 * prm["r"] * r_eff) / (st["embed"] * 1e-3) / 1e12
@@ -241,8 +380,14 @@ def leg_pca_nlm(steps, warmup):
             g = nkf.patch_pca(ft, **pk)
             return nkf.filter(ft, g, precision=prec, return_r_eff=True, **kw)
         ms, st, (g, r_eff) = _timed(call, steps, warmup, ft)
+        nbytes = N * (r_eff * (8 if prec == "fp32" else 4) + 8 * C)
+        conv_s = st["conv"] * 1e-3
         res[prec] = ({"ms_per_call": round(ms, 3), "Mpixel_s": round(N / ms / 1e3, 2), "r_eff": r_eff,
-                      "stages_ms": st}, g)
+                      "stages_ms": st,
+                      "conv_roofline": {"kernel": "box_kernel", "bound": "hbm", "unit": "GB/s",
+                                        "achieved": round(nbytes / conv_s / 1e9, 1), "peak": PEAK_HBM_GBS,
+                                        "frac": round(nbytes / conv_s / 1e9 / PEAK_HBM_GBS, 4),
+                                        "algorithmic_bytes_per_launch": nbytes}}, g)
     out.update({p: e for p, (e, _) in res.items()})
     # each form runs its own k-means, which in 25 dimensions may settle on other
     # landmarks; the arithmetic of the two forms is compared with shared ones
@@ -290,9 +435,19 @@ def leg_diff(steps, warmup):
 
     ms_f, _, _ = _timed(fwd, steps, warmup)
     ms_b, _, _ = _timed(fwdbwd, steps, warmup)
+    T = 2 * prm["S"] + 1
+    fl_f = sum(fwd_flops_per_pixel(im[5], prm["r"], 3, 3, T) * im[0].shape[0] * im[0].shape[1] for im in imgs)
+    fl_fb = fl_f + sum(bwd_flops_per_pixel(im[5], prm["r"], 3, 3, T) * im[0].shape[0] * im[0].shape[1]
+                       for im in imgs)
     return {"images": [list(s) for s in sizes], "pixels": npx, "r": prm["r"], "S": prm["S"],
             "fwd_ms": round(ms_f, 3), "fwd_Mpixel_s": round(npx / ms_f / 1e3, 2),
-            "fwd_bwd_ms": round(ms_b, 3), "fwd_bwd_Mpixel_s": round(npx / ms_b / 1e3, 2)}
+            "fwd_bwd_ms": round(ms_b, 3), "fwd_bwd_Mpixel_s": round(npx / ms_b / 1e3, 2),
+            "roofline": {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS,
+                         "fwd_achieved": round(fl_f / (ms_f * 1e-3) / 1e12, 2),
+                         "fwd_frac": round(fl_f / (ms_f * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+                         "fwd_bwd_achieved": round(fl_fb / (ms_b * 1e-3) / 1e12, 2),
+                         "fwd_bwd_frac": round(fl_fb / (ms_b * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+                         "algorithmic_flops": {"fwd": fl_f, "fwd_bwd": fl_fb}}}
 
 
 LEGS = {
@@ -322,6 +477,13 @@ def main():
         sys.exit(2)
 
     import numpy as np
+
+    # the all-cores oracle runs first: its worker pool is forked before the GPU
+    # is initialised
+    par = None
+    if not (a.no_cpu_baseline or a.copy_calibration or a.leg):
+        par = cpu_baseline_parallel(a.cpu_crop)
+
     import torch
 
     from paper_1901_06112_amd import nkf, synth
@@ -367,6 +529,7 @@ def main():
     flops = conv_flops_per_pixel(r_eff, C, T) * N
     achieved = flops / (conv_launch_ms * 1e-3) / 1e12
     traffic = _traffic()
+    conv_rocprof_ms = rocprof_launch_ms("void nkf::conv::conv_kernel<15, 4, true, 32, 0, 512, false>")
     line = {
         "metric": "Mpixel/s Nystrom BLF forward (k-means + factor + embedding + r(C+1) convolutions + "
                   "contraction), FP32",
@@ -391,6 +554,13 @@ def main():
                                    "accumulate in FP64",
                      "frac_of_fp32_vector_peak": round(achieved / PEAK_FP32_TFLOPS, 4),
                      "traffic": traffic, "launch_ms": round(conv_launch_ms, 4),
+                     "launch_ms_rocprof": conv_rocprof_ms,
+                     "frac_rocprof": (round(flops / (conv_rocprof_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)
+                                      if conv_rocprof_ms else None),
+                     "sources": {"launch_ms": "HIP events around each launch on the library's stream, "
+                                              "averaged over the timed steps of this run",
+                                 "launch_ms_rocprof": f"{PROFILE_HEADLINE}: rocprofv3 --kernel-trace --stats "
+                                                      "average of the same command (committed run)"},
                      "algorithmic_flops_per_launch": flops,
                      "algorithmic_hbm_GBs": round(conv_bytes_per_pixel(r_eff, C) * N / (conv_launch_ms * 1e-3) / 1e9, 1)},
         "stages_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in st.items() if v[1] > 0},
@@ -399,8 +569,16 @@ def main():
         line["workloads"] = {k: fn(a.leg_steps, 1) for k, fn in LEGS.items()}
     if not a.no_cpu_baseline:
         cen = nkf.kmeans(ft, r=prm["r"], iters=prm["iters"], seed=prm["landmark_seed"])
-        line["cpu_baseline"] = cpu_baseline(a.cpu_crop, out.cpu().numpy().astype(np.float64),
-                                            cen.cpu().numpy().astype(np.float64))
+        one = cpu_baseline(a.cpu_crop, out.cpu().numpy().astype(np.float64),
+                           cen.cpu().numpy().astype(np.float64))
+        line["cpu_baseline"] = {"value": round(par["value"], 4), "unit": "Mpixel/s", "cores": par["cores"],
+                                "kind": "oracle", "cpu_model": one["cpu_model"],
+                                "host_cpus": os.cpu_count(), "sample": par["sample"],
+                                "seconds": par["seconds"], "kmeans_s": par["kmeans_s"],
+                                "filter_s": par["filter_s"],
+                                "single_core": {"value": round(one["value"], 4), "cores": 1,
+                                                "sample": one["sample"]},
+                                "quality": one["quality"]}
     print(json.dumps(line), flush=True)
 
 

@@ -245,6 +245,34 @@ nkf_status nkf_enable_timing(nkf_ctx *ctx, int enable);
  * count_host[NKF_STAGE_COUNT] since the last reset; reset != 0 clears them. */
 nkf_status nkf_stage_times(nkf_ctx *ctx, double *ms_host, int *count_host, int reset);
 
+/* Statistics of the last forward call on a context (nkf_filter or
+ * nkf_filter_landmarks; not the allocation-free call nor the backward's
+ * recompute), for diagnosing the cases the paper leaves open: the number of
+ * kept eigenpairs of A and its conditioning (Section III: A may be
+ * ill-conditioned; eigenvalues at or below tau * alpha_max are dropped), and
+ * the pixels whose eta_hat was <= 0 or not finite, where the output is f.
+ * Off by default; with it on, each forward call adds one small reduction over
+ * eta_hat (and keeps its own eta_hat copy when eta_out is NULL).  Setting the
+ * environment variable NKF_LOG (non-empty, not "0") when a context is created
+ * turns it on and prints the record of every forward call to stderr (each
+ * call then waits for its stream). */
+typedef struct {
+  int valid;               /* 1 when a forward call has been recorded since the last enable */
+  int r, r_eff;            /* landmarks and kept eigenpairs                                     */
+  double alpha_max;        /* largest eigenvalue of A (NAN: the caller supplied F)              */
+  double alpha_min_kept;   /* smallest kept eigenvalue (NAN as above)                           */
+  double cond_kept;        /* alpha_max / alpha_min_kept                                         */
+  long long pixels;        /* H * W                                                              */
+  long long guarded;       /* pixels with eta_hat <= 0 or not finite (output = f)               */
+  double min_eta;          /* smallest positive finite eta_hat (NAN if none)                    */
+} nkf_stats;
+/* enable != 0 turns the statistics on (allocates an 8-byte device buffer
+ * once), 0 turns them off; either clears the record. */
+nkf_status nkf_enable_stats(nkf_ctx *ctx, int enable);
+/* Copies the record of the last forward call to *out, waiting for the stream
+ * for the eta_hat part.  out->valid == 0 when none has been recorded. */
+nkf_status nkf_get_stats(nkf_ctx *ctx, nkf_stats *out);
+
 /* Host-only: the r distinct pixel indices (draw order) that initialise
  * k-means for (N, r, seed): partial Fisher-Yates over [0, N) driven by
  * SplitMix64.  idx_host [r].  Exposed so the draw can be checked. */

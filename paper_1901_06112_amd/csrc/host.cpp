@@ -2,6 +2,7 @@
 // include/nkf.h, argument validation, the device workspace, the k-means
 // seeding draw, the FP64 landmark factor and the stream-ordered launch
 // sequence of Algorithm 1.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
@@ -45,6 +46,11 @@ struct nkf_ctx {
   hipEvent_t pinned_free = nullptr;  // after the last queued copy through `pinned`
   // the last PCA sample draw (it depends on N and the seed only)
   int conv_chunks = 0;  // nkf_set_conv_chunks
+  // statistics of the last forward call (nkf_enable_stats, NKF_LOG)
+  bool stats = false;
+  bool log = false;          // NKF_LOG set: print them after each forward call
+  unsigned *dstat = nullptr; // device [2]: guarded-pixel count, min eta_hat code
+  nkf_stats last{};
   int num_cu = 0;       // compute units of the device
   int64_t pca_draw_N = -1;
   uint64_t pca_draw_seed = 0;
@@ -52,6 +58,36 @@ struct nkf_ctx {
 };
 
 namespace {
+
+// roctx ranges (rocprofv3 --marker-trace) around every stage, when the roctx
+// library can be loaded; otherwise the ranges are no-ops.
+struct Roctx {
+  int (*push)(const char *) = nullptr;
+  int (*pop)() = nullptr;
+  Roctx() {
+    void *h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL);
+    if (!h) h = dlopen("librocprofiler-sdk-roctx.so", RTLD_NOW | RTLD_LOCAL);
+    if (!h) return;
+    push = reinterpret_cast<int (*)(const char *)>(dlsym(h, "roctxRangePushA"));
+    pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+    if (!push || !pop) push = nullptr, pop = nullptr;
+  }
+};
+const Roctx &roctx() {
+  static const Roctx r;
+  return r;
+}
+struct Range {
+  bool on;
+  explicit Range(const char *name) : on(roctx().push != nullptr) {
+    if (on) roctx().push(name);
+  }
+  ~Range() {
+    if (on) roctx().pop();
+  }
+};
+const char *const kStageRange[NKF_STAGE_COUNT] = {"nkf:seed", "nkf:kmeans", "nkf:factor",
+                                                  "nkf:embed", "nkf:conv", "nkf:backward"};
 
 hipEvent_t take_event(nkf_ctx *ctx) {
   if (!ctx->event_pool.empty()) {
@@ -68,8 +104,9 @@ hipEvent_t take_event(nkf_ctx *ctx) {
 struct StageTimer {
   nkf_ctx *ctx;
   int stage;
+  Range range;
   hipEvent_t a = nullptr;
-  StageTimer(nkf_ctx *c, int s) : ctx(c), stage(s) {
+  StageTimer(nkf_ctx *c, int s) : ctx(c), stage(s), range(kStageRange[s]) {
     if (ctx->timing && (a = take_event(ctx))) (void)hipEventRecord(a, ctx->stream);
   }
   ~StageTimer() {
@@ -84,8 +121,9 @@ struct StageTimer {
 struct HostTimer {
   nkf_ctx *ctx;
   int stage;
+  Range range;
   std::chrono::steady_clock::time_point t0;
-  HostTimer(nkf_ctx *c, int s) : ctx(c), stage(s), t0(std::chrono::steady_clock::now()) {}
+  HostTimer(nkf_ctx *c, int s) : ctx(c), stage(s), range(kStageRange[s]), t0(std::chrono::steady_clock::now()) {}
   ~HostTimer() {
     if (!ctx || !ctx->timing) return;
     ctx->host_ms[stage] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -422,9 +460,11 @@ struct FwdBufs {
   double *mpart; // partial sums of the centring offsets
   void *lm;      // prepared 16-bit landmarks
   double *ct64;  // transposed FP64 landmarks of the FP32 embedding
+  float *eta_stat;  // eta_hat for the statistics when the caller passes no eta_out
 };
 
-void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r, bool u64, int num_cu) {
+void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r, bool u64, int num_cu,
+               bool stats = false) {
   b.f0 = cv.take<float>(rs.C);
   b.mm = cv.take<unsigned>(center_scratch_words(rs.C));
   b.u = u64 ? nullptr : cv.take<float>((size_t)r_eff * rs.N);
@@ -437,6 +477,7 @@ void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r, bool
   b.mpart = cv.take<double>(guide_mean_scratch_doubles(rs.g));
   b.lm = cv.take<unsigned char>(mfma_landmark_scratch_bytes(rs.g, r));
   b.ct64 = cv.take<double>(embed_scratch_doubles(rs.g, r));
+  b.eta_stat = cv.take<float>(stats ? rs.N : 1);
 }
 
 // The landmark-independent part of the forward: the centring offsets f0 and,
@@ -448,8 +489,11 @@ nkf_status run_pre(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, cons
 }
 
 // pre_done: run_pre has been enqueued already
+// stats_ok: a forward entry point whose statistics are recorded (not the
+// backward's recompute, nor the allocation-free call)
 nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, const float *c, const double *F,
-                   int r_eff, float *out, float *eta_out, const FwdBufs &b, bool conv = true, bool pre_done = false) {
+                   int r_eff, float *out, float *eta_out, const FwdBufs &b, bool conv = true, bool pre_done = false,
+                   bool stats_ok = false) {
   {
     StageTimer tm(ctx, NKF_STAGE_EMBED);
     if (!pre_done) {
@@ -464,6 +508,9 @@ nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, cons
     }
   }
   if (!conv) return NKF_OK;
+  // eta_hat for the statistics: the caller's, else the library's copy
+  const bool want_stats = ctx->stats && ctx->dstat && stats_ok;
+  if (want_stats && !eta_out) eta_out = b.eta_stat;
   if (box_path(rs)) {
     BoxProblem bx{};
     bx.H = rs.H;
@@ -478,8 +525,11 @@ nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, cons
     bx.eta_out = eta_out;
     bx.part = b.box_part;
     bx.num_cu = ctx->num_cu;
-    StageTimer tm(ctx, NKF_STAGE_CONV);
-    HIP_TRY(ctx, launch_box(bx, ctx->stream));
+    {
+      StageTimer tm(ctx, NKF_STAGE_CONV);
+      HIP_TRY(ctx, launch_box(bx, ctx->stream));
+    }
+    if (want_stats) HIP_TRY(ctx, launch_eta_stats(eta_out, rs.N, ctx->dstat, ctx->stream));
     return NKF_OK;
   }
   ConvProblem pb{};
@@ -498,8 +548,11 @@ nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, cons
   pb.eta_buf = b.eta_buf;
   pb.f_planar = b.f_planar;
   pb.force_nch = ctx->conv_chunks;
-  StageTimer tm(ctx, NKF_STAGE_CONV);
-  HIP_TRY(ctx, launch_conv_contract(pb, ctx->stream));
+  {
+    StageTimer tm(ctx, NKF_STAGE_CONV);
+    HIP_TRY(ctx, launch_conv_contract(pb, ctx->stream));
+  }
+  if (want_stats) HIP_TRY(ctx, launch_eta_stats(eta_out, rs.N, ctx->dstat, ctx->stream));
   return NKF_OK;
 }
 
@@ -550,6 +603,38 @@ nkf_status run_seed(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, flo
   return NKF_OK;
 }
 
+// Host part of the statistics of one forward call (the eta_hat part is
+// reduced on the device and read by nkf_get_stats).
+void record_stats(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, int r_eff, double alpha_max,
+                  double alpha_min_kept) {
+  if (!ctx->stats) return;
+  nkf_stats &t = ctx->last;
+  t = nkf_stats{};
+  t.valid = 1;
+  t.pixels = rs.N;
+  t.r = prm->r;
+  t.r_eff = r_eff;
+  t.alpha_max = alpha_max;
+  t.alpha_min_kept = alpha_min_kept;
+  t.cond_kept = alpha_max / alpha_min_kept;
+  t.guarded = -1;
+  t.min_eta = NAN;
+}
+
+nkf_status log_stats(nkf_ctx *ctx, const char *call, const Resolved &rs, const nkf_params *prm) {
+  if (!ctx->log) return NKF_OK;
+  nkf_stats t;
+  const nkf_status st = nkf_get_stats(ctx, &t);
+  if (st != NKF_OK) return st;
+  fprintf(stderr,
+          "nkf: %s %dx%dx%d D=%d S=%d %s %s r=%d r_eff=%d cond(A_kept)=%.3g alpha_max=%.6g "
+          "guarded=%lld min_eta=%.6g\n",
+          call, rs.H, rs.W, rs.C, rs.D, rs.S, rs.box ? "box" : "gaussian",
+          prm->prec == NKF_PREC_FP32 ? "fp32" : prm->prec == NKF_PREC_BF16 ? "bf16" : "fp16", t.r, t.r_eff,
+          t.cond_kept, t.alpha_max, t.guarded, t.min_eta);
+  return NKF_OK;
+}
+
 }  // namespace
 
 // =============================================================================
@@ -590,6 +675,12 @@ nkf_status nkf_create(nkf_ctx **out, void *hip_stream) {
   if (hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
     (void)hipGetLastError();
     c->num_cu = 0;
+  }
+  // NKF_LOG (non-empty, not "0"): statistics of every forward call on stderr
+  const char *lg = getenv("NKF_LOG");
+  if (lg && *lg && strcmp(lg, "0") != 0) {
+    c->log = true;
+    if (nkf_enable_stats(c, 1) != NKF_OK) c->log = false;
   }
   *out = c;
   return NKF_OK;
@@ -653,12 +744,40 @@ nkf_status nkf_destroy(nkf_ctx *ctx) {
   if (ctx->copy_done) (void)hipEventDestroy(ctx->copy_done);
   if (ctx->pinned_free) (void)hipEventDestroy(ctx->pinned_free);
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->dstat) (void)hipFree(ctx->dstat);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
   return st;
 }
 
 const char *nkf_last_error(const nkf_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+nkf_status nkf_enable_stats(nkf_ctx *ctx, int enable) {
+  if (!ctx) return fail(nullptr, NKF_ERR_INVALID_ARG, "ctx is NULL");
+  if (enable && !ctx->dstat) {
+    void *p = nullptr;
+    if (hipMalloc(&p, 2 * sizeof(unsigned)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, NKF_ERR_OUT_OF_MEMORY, "hipMalloc of the statistics buffer failed");
+    }
+    ctx->dstat = static_cast<unsigned *>(p);
+  }
+  ctx->stats = enable != 0;
+  ctx->last = nkf_stats{};
+  return NKF_OK;
+}
+
+nkf_status nkf_get_stats(nkf_ctx *ctx, nkf_stats *out) {
+  if (!ctx || !out) return fail(ctx, NKF_ERR_INVALID_ARG, "ctx and out are required");
+  *out = ctx->last;
+  if (!ctx->last.valid || !ctx->dstat) return NKF_OK;
+  unsigned h[2] = {0u, 0u};
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  HIP_TRY(ctx, hipMemcpy(h, ctx->dstat, sizeof h, hipMemcpyDeviceToHost));
+  out->guarded = (long long)h[0];
+  out->min_eta = eta_stats_min(h[1]);
+  return NKF_OK;
+}
 
 nkf_status nkf_set_conv_chunks(nkf_ctx *ctx, int nch) {
   if (!ctx) return fail(nullptr, NKF_ERR_INVALID_ARG, "ctx is NULL");
@@ -838,11 +957,14 @@ nkf_status nkf_filter_landmarks(nkf_ctx *ctx, int H, int W, int C, const float *
   Carve dry{nullptr};
   FwdBufs fb;
   const bool u64 = fwd_u64(rs, prm->prec);
-  carve_fwd(dry, rs, r_eff, fb, kMaxLandmarks, u64, ctx->num_cu);
+  carve_fwd(dry, rs, r_eff, fb, kMaxLandmarks, u64, ctx->num_cu, ctx->stats);
   if ((st = ensure_workspace(ctx, dry.off)) != NKF_OK) return st;
   Carve cv{ctx->ws};
-  carve_fwd(cv, rs, r_eff, fb, kMaxLandmarks, u64, ctx->num_cu);
-  return run_fwd(ctx, rs, prm, centroids, F, r_eff, out, eta_out, fb);
+  carve_fwd(cv, rs, r_eff, fb, kMaxLandmarks, u64, ctx->num_cu, ctx->stats);
+  // the factor was formed by the caller: no eigenvalues to report
+  record_stats(ctx, rs, prm, r_eff, NAN, NAN);
+  if ((st = run_fwd(ctx, rs, prm, centroids, F, r_eff, out, eta_out, fb, true, false, true)) != NKF_OK) return st;
+  return log_stats(ctx, "filter_landmarks", rs, prm);
 }
 
 nkf_status nkf_filter_landmarks_noalloc(nkf_ctx *ctx, int H, int W, int C, const float *f, int D,
@@ -888,7 +1010,7 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
     c = cv.take<float>((size_t)r * rs.D);
     idx = cv.take<int64_t>(r);
     Fd = cv.take<double>((size_t)r * r);
-    carve_fwd(cv, rs, r, fb, kMaxLandmarks, fwd_u64(rs, prm->prec), ctx->num_cu);
+    carve_fwd(cv, rs, r, fb, kMaxLandmarks, fwd_u64(rs, prm->prec), ctx->num_cu, ctx->stats);
   };
   KmBufs kb;
   FwdBufs fb;
@@ -921,10 +1043,11 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
     std::vector<double> cd((size_t)r * rs.D);
     for (size_t i = 0; i < cd.size(); ++i) cd[i] = c_host[i];
     double *F_host = reinterpret_cast<double *>(ctx->pinned + ((sizeof(float) * r * rs.D + 255) & ~(size_t)255));
-    std::vector<double> Fr((size_t)r * r);
-    if ((st = factor(ctx, r, rs.D, cd.data(), prm->sigma_r, prm->eig_rel_tol, nullptr, nullptr, Fr.data(),
+    std::vector<double> Fr((size_t)r * r), al(r);
+    if ((st = factor(ctx, r, rs.D, cd.data(), prm->sigma_r, prm->eig_rel_tol, nullptr, al.data(), Fr.data(),
                      &r_eff)) != NKF_OK)
       return st;
+    record_stats(ctx, rs, prm, r_eff, al[r - 1], al[r - r_eff]);
     // pack F [r, r_eff]
     for (int i = 0; i < r; ++i)
       for (int j = 0; j < r_eff; ++j) F_host[i * r_eff + j] = Fr[i * r + j];
@@ -932,7 +1055,8 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
     if ((st = pinned_release(ctx)) != NKF_OK) return st;
   }
   if (r_eff_out) *r_eff_out = r_eff;
-  return run_fwd(ctx, rs, prm, c, Fd, r_eff, out, eta_out, fb, true, true);
+  if ((st = run_fwd(ctx, rs, prm, c, Fd, r_eff, out, eta_out, fb, true, true, true)) != NKF_OK) return st;
+  return log_stats(ctx, "filter", rs, prm);
 }
 
 nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, const float *p,

@@ -10,6 +10,7 @@
 // and kept in FP64, and the r x r_eff mix accumulates in FP64, so the stored
 // u_k carries a single FP32 rounding even where F^T b cancels.
 #include <hip/hip_runtime.h>
+#include <string.h>
 #include <float.h>
 #include <math.h>
 
@@ -197,6 +198,12 @@ __device__ __forceinline__ unsigned ord_encode(float v) {
 }
 __device__ __forceinline__ float ord_decode(unsigned k) {
   return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+static float ord_decode_host(unsigned k) {
+  const unsigned b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+  float v;
+  memcpy(&v, &b, sizeof v);
+  return v;
 }
 
 // The C <= 4 path keeps kMmReps copies of the (min, max) words, each copy
@@ -388,6 +395,48 @@ hipError_t launch_center(const float *f, int64_t N, int C, double center, float 
 }
 
 size_t center_scratch_words(int C) { return C <= 4 ? (size_t)kMmReps * kMmSlot : 2 * (size_t)C; }
+
+// eta_hat statistics: st[0] = pixels that took the eta_hat <= 0 / non-finite
+// guard, st[1] = ord_encode(min eta_hat over the other pixels).
+__global__ void eta_stats_init_kernel(unsigned *st) {
+  if (threadIdx.x == 0) {
+    st[0] = 0u;
+    st[1] = 0xffffffffu;
+  }
+}
+
+__global__ __launch_bounds__(256) void eta_stats_kernel(const float *__restrict__ eta, int64_t N, unsigned *st) {
+  unsigned cnt = 0u, mn = 0xffffffffu;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += (int64_t)gridDim.x * blockDim.x) {
+    const float e = eta[x];
+    if (e > 0.0f && isfinite(e))
+      mn = min(mn, ord_encode(e));
+    else
+      ++cnt;
+  }
+#pragma unroll
+  for (int m = kWave / 2; m >= 1; m >>= 1) {
+    cnt += (unsigned)__shfl_xor((int)cnt, m, kWave);
+    mn = min(mn, (unsigned)__shfl_xor((int)mn, m, kWave));
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (cnt) atomicAdd(&st[0], cnt);
+    atomicMin(&st[1], mn);
+  }
+}
+
+hipError_t launch_eta_stats(const float *eta, int64_t N, unsigned *st, hipStream_t s) {
+  hipLaunchKernelGGL(eta_stats_init_kernel, dim3(1), dim3(64), 0, s, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int64_t blocks = (N + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(eta_stats_kernel, dim3((unsigned)blocks), dim3(256), 0, s, eta, N, st);
+  return hipGetLastError();
+}
+
+double eta_stats_min(unsigned code) { return code == 0xffffffffu ? NAN : (double)ord_decode_host(code); }
 
 size_t embed_scratch_doubles(const Guide &g, int r) {
   const bool small = g.D <= 4 && g.kind != GUIDE_PATCH;

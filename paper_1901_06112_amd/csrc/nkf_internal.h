@@ -71,6 +71,11 @@ inline bool use_mfma_distance(const Guide &g, int prec) { return prec != 0 && g.
 size_t center_scratch_words(int C);
 hipError_t launch_center(const float *f, int64_t N, int C, double center, float *f0,
                          unsigned *scratch /*[2C]*/, hipStream_t s);
+// eta_hat statistics into st[2] (device): the count of pixels that took the
+// eta_hat <= 0 / non-finite guard, and the order-preserving code of the
+// smallest positive eta_hat (decoded by eta_stats_min; NAN if none).
+hipError_t launch_eta_stats(const float *eta, int64_t N, unsigned *st, hipStream_t s);
+double eta_stats_min(unsigned code);
 // u[k][x] = sum_j F[j][k] exp(-|p(x) - c_j|^2 / (2 sigma_r^2)), planar [r_eff][N] float32.
 // ct64 is scratch of embed_scratch_doubles(g, r) doubles (transposed FP64 landmarks).
 size_t embed_scratch_doubles(const Guide &g, int r);

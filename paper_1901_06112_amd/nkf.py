@@ -29,7 +29,7 @@ EXPORTS = [
     "nkf_last_error", "nkf_set_workspace_limit", "nkf_workspace_bytes", "nkf_filter", "nkf_kmeans",
     "nkf_kmeans_iterate", "nkf_landmark_factor", "nkf_filter_landmarks", "nkf_filter_backward",
     "nkf_seed_indices", "nkf_spatial_taps", "nkf_enable_timing", "nkf_stage_times", "nkf_patch_pca",
-    "nkf_set_conv_chunks", "nkf_filter_landmarks_noalloc",
+    "nkf_set_conv_chunks", "nkf_filter_landmarks_noalloc", "nkf_enable_stats", "nkf_get_stats",
 ]
 STAGES = ["seed", "kmeans", "factor", "embed", "conv", "backward"]
 
@@ -46,6 +46,14 @@ class Params(ct.Structure):
         ("spatial", ct.c_int), ("guide", ct.c_int), ("patch_radius", ct.c_int), ("prec", ct.c_int),
         ("kmeans_iters", ct.c_int), ("seed", ct.c_uint64), ("eig_rel_tol", ct.c_double),
         ("center", ct.c_double),
+    ]
+
+
+class Stats(ct.Structure):
+    _fields_ = [
+        ("valid", ct.c_int), ("r", ct.c_int), ("r_eff", ct.c_int), ("alpha_max", ct.c_double),
+        ("alpha_min_kept", ct.c_double), ("cond_kept", ct.c_double), ("pixels", ct.c_longlong),
+        ("guarded", ct.c_longlong), ("min_eta", ct.c_double),
     ]
 
 
@@ -86,6 +94,8 @@ def load_library(path=LIB_PATH):
             "nkf_enable_timing": (I, [P, I]),
             "nkf_stage_times": (I, [P, P, P, I]),
             "nkf_set_conv_chunks": (I, [P, I]),
+            "nkf_enable_stats": (I, [P, I]),
+            "nkf_get_stats": (I, [P, ct.POINTER(Stats)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -337,6 +347,25 @@ def set_conv_chunks(t, nch):
     the current stream (0: automatic); see nkf_set_conv_chunks."""
     ctx = _cur_ctx(t)
     _check(load_library().nkf_set_conv_chunks(ctx, int(nch)), ctx)
+
+
+def enable_stats(t, enable=True):
+    """Record the statistics of each forward call (r_eff, cond(A), the pixels
+    that took the eta_hat <= 0 guard, min eta_hat) for the context of ``t``'s
+    device and the current stream."""
+    ctx = _cur_ctx(t)
+    _check(load_library().nkf_enable_stats(ctx, 1 if enable else 0), ctx)
+
+
+def get_stats(t):
+    """The record of the last forward call (a dict; waits for the stream), or
+    None if none was recorded."""
+    ctx = _cur_ctx(t)
+    st = Stats()
+    _check(load_library().nkf_get_stats(ctx, ct.byref(st)), ctx)
+    if not st.valid:
+        return None
+    return {k: getattr(st, k) for k, _ in Stats._fields_ if k != "valid"}
 
 
 def stage_times(t, reset=True):
