@@ -27,7 +27,9 @@
 // wave adds its pixels' centred guide vectors to the block's per-cluster FP32
 // sums in LDS (lanes over dimensions, so the atomics of one instruction hit
 // distinct words), written out once per block as FP64 partials.
-// Embedding: b = exp(-d^2 / (2 sigma_r^2)) into an LDS tile, then
+// Embedding: the products as 16-bit hi + lo pairs (three MFMA passes, about
+// twice the bits of the k-means products, whose decisions only need the
+// nearest landmark), b = exp(-d^2 / (2 sigma_r^2)) into an LDS tile, then
 // u^T = F^T b^T on v_mfma_f32_16x16x4_f32, each wave keeping its rows of F^T
 // in registers for the whole launch.
 #include <hip/hip_runtime.h>
@@ -86,6 +88,7 @@ struct MArgs {
   int tiles_x;       // patch guides: tiles per image row
   int ntiles;
   const void *ctg;   // [RP][DS] 16-bit centred landmarks on the permuted axis
+  const void *ctg_lo;  // [RP][DS] their rounding remainders, also 16-bit (embedding)
   const float *cn2g; // [RP] their FP32 squared norms (FLT_MAX for padding)
   // k-means
   int *labels;       // nullable
@@ -181,11 +184,13 @@ __device__ __forceinline__ void build_tables(const MArgs &a, int *tab_off, int *
     }
 }
 
-// Centred 16-bit landmarks on the permuted axis and their FP32 squared norms
-// (padded landmarks get FLT_MAX so that they never win an argmin), once per
-// launch: one wave per landmark row.
+// Centred 16-bit landmarks on the permuted axis, the 16-bit rounding of what
+// the first rounding left (hi + lo carries about twice the bits), and their
+// FP32 squared norms (padded landmarks get FLT_MAX so that they never win an
+// argmin), once per launch: one wave per landmark row.
 template <int PREC>
-__global__ __launch_bounds__(64) void prep_landmarks_kernel(MArgs a, typename Half<PREC>::T *ctg, float *cn2g) {
+__global__ __launch_bounds__(64) void prep_landmarks_kernel(MArgs a, typename Half<PREC>::T *ctg,
+                                                            typename Half<PREC>::T *ctg_lo, float *cn2g) {
   using T = typename Half<PREC>::T;
   const int k = blockIdx.x, lane = threadIdx.x, D = a.g.D;
   float s = 0.0f;
@@ -197,28 +202,40 @@ __global__ __launch_bounds__(64) void prep_landmarks_kernel(MArgs a, typename Ha
       v = a.c[k * D + d] - mu_of(a, d);
     }
     s = fmaf(v, v, s);
-    ctg[k * a.DS + dd] = (T)v;
+    const T hv = (T)v;
+    ctg[k * a.DS + dd] = hv;
+    ctg_lo[k * a.DS + dd] = (T)(v - (float)hv);
   }
   s = wave_sum(s);
   if (lane == 0) cn2g[k] = k < a.r ? s : FLT_MAX;
 }
 
 // copy the prepared landmarks into LDS (16-byte vectors)
-__device__ __forceinline__ void load_landmarks(const MArgs &a, void *ct, float *cn2, int BT) {
+__device__ __forceinline__ void load_landmarks(const MArgs &a, void *ct, float *cn2, int BT,
+                                               void *ct_lo = nullptr) {
   const int n16 = a.RP * a.DS * 2 / 16;  // RP * DS halves, DS a multiple of 8
   const uint4 *src = reinterpret_cast<const uint4 *>(a.ctg);
   uint4 *dst = reinterpret_cast<uint4 *>(ct);
   for (int e = threadIdx.x; e < n16; e += BT) dst[e] = src[e];
+  if (ct_lo) {
+    const uint4 *sl = reinterpret_cast<const uint4 *>(a.ctg_lo);
+    uint4 *dl = reinterpret_cast<uint4 *>(ct_lo);
+    for (int e = threadIdx.x; e < n16; e += BT) dl[e] = sl[e];
+  }
   for (int k = threadIdx.x; k < a.RP; k += BT) cn2[k] = a.cn2g[k];
 }
 
 // acc[t][i] = p~(pixel 16w + 4 rq + i) . c~(landmark 16t + col) for this
 // wave's 16 pixels and all RP landmarks; with NORMS, s2 = |p~|^2 (FP32, from
-// the unrounded values) of pixel 16w + (lane & 15).
-template <int PREC, int NT, bool NORMS>
+// the unrounded values) of pixel 16w + (lane & 15).  With SPLIT (ct_lo holds
+// the landmarks' 16-bit remainders) each operand is a 16-bit pair hi + lo and
+// the product takes hi.hi + lo.hi + hi.lo: three MFMA passes whose result
+// carries about twice the bits of one (lo.lo is below their rounding).
+template <int PREC, int NT, bool NORMS, bool SPLIT = false>
 __device__ __forceinline__ void tile_products(const MArgs &a, const float *raw, const int *tab_off,
                                               const int *tab_nv, const typename Half<PREC>::T *ct,
-                                              floatx4 (&acc)[NT], float &s2) {
+                                              floatx4 (&acc)[NT], float &s2,
+                                              const typename Half<PREC>::T *ct_lo = nullptr) {
   using T = typename Half<PREC>::T;
   using V = typename Half<PREC>::V;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -242,18 +259,28 @@ __device__ __forceinline__ void tile_products(const MArgs &a, const float *raw, 
 #pragma unroll
       for (int j = 0; j < 8; ++j) x[j] = src[j];
     }
-    V av;
+    V av, avl;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const float v = j < nv ? x[j] : 0.0f;
       if constexpr (NORMS) s2 = fmaf(v, v, s2);
       av[j] = (T)v;
+      if constexpr (SPLIT) avl[j] = (T)(v - (float)av[j]);
     }
     V bv[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) bv[t] = *reinterpret_cast<const V *>(&ct[(16 * t + row) * a.DS + 32 * s + 8 * kq]);
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = Half<PREC>::mma(av, bv[t], acc[t]);
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = Half<PREC>::mma(avl, bv[t], acc[t]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        bv[t] = *reinterpret_cast<const V *>(&ct_lo[(16 * t + row) * a.DS + 32 * s + 8 * kq]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = Half<PREC>::mma(av, bv[t], acc[t]);
+    }
   }
   if constexpr (NORMS) {
     s2 += __shfl_xor(s2, 16, 64);
@@ -502,7 +529,8 @@ __global__ __launch_bounds__(BT) void embed_mfma_kernel(MArgs a) {
   constexpr bool FREG = KS * MAXT2 <= 64 && NT <= 8;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   T *ct = reinterpret_cast<T *>(smem_raw);                                    // [RP][DS]
-  float *raw = reinterpret_cast<float *>(ct + (size_t)a.RP * a.DS);           // [raw_floats + 8]
+  T *ct_lo = ct + (size_t)a.RP * a.DS;                                        // [RP][DS]
+  float *raw = reinterpret_cast<float *>(ct_lo + (size_t)a.RP * a.DS);        // [raw_floats + 8]
   float *bs = raw + a.raw_floats + 8;                                         // [TP][RP + 4]
   float *cn2 = bs + TP * (a.RP + 4);                                          // [RP]
   int *tab_off = reinterpret_cast<int *>(cn2 + a.RP);                         // [kMaxChunks]
@@ -513,7 +541,7 @@ __global__ __launch_bounds__(BT) void embed_mfma_kernel(MArgs a) {
   // col) and the mix reads (rows col, columns 4 s + rq) hit distinct banks
   const int BS = a.RP + 4;
 
-  load_landmarks(a, ct, cn2, BT);
+  load_landmarks(a, ct, cn2, BT, ct_lo);
   build_tables(a, tab_off, tab_nv, nullptr, BT);
   // mix operand A = F^T: A[k'][j] = F[j][k']; lane (col, rq) takes
   // A[16 t2 + col][4 s + rq] for the wave's tiles t2 = w + NW m
@@ -535,7 +563,7 @@ __global__ __launch_bounds__(BT) void embed_mfma_kernel(MArgs a) {
     __syncthreads();
     floatx4 acc[NT];
     float s2;
-    tile_products<PREC, NT, true>(a, raw, tab_off, tab_nv, ct, acc, s2);
+    tile_products<PREC, NT, true, true>(a, raw, tab_off, tab_nv, ct, acc, s2, ct_lo);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int pxl = 16 * w + 4 * rq + i;
@@ -711,7 +739,7 @@ int plan_embed(const Guide &g, int r, size_t *lds) {
   for (int BT : {512, 256}) {
     const MArgs a = make_args(g, nullptr, r, nullptr, 16 * BT / 64);
     if (a.Dp / 8 > kMaxChunks) return 0;
-    const size_t l = embed_lds(a, 16 * BT / 64, ct_bytes<PREC>(a));
+    const size_t l = embed_lds(a, 16 * BT / 64, 2 * ct_bytes<PREC>(a));
     if (l <= kLdsMax) {
       *lds = l;
       return BT;
@@ -743,15 +771,17 @@ hipError_t launch_lloyd_nt(const MArgs &a, const LloydPlan &pl, hipStream_t s, i
 }
 
 // The prepared landmarks live in the caller's scratch: [RP][DS] 16-bit values,
-// then [RP] floats.
+// [RP][DS] 16-bit remainders, then [RP] floats.
 template <int PREC>
 hipError_t prep_landmarks(MArgs &a, void *scratch, hipStream_t s) {
   using T = typename Half<PREC>::T;
   T *ctg = reinterpret_cast<T *>(scratch);
-  float *cn2g = reinterpret_cast<float *>(ctg + (size_t)a.RP * a.DS);
+  T *ctg_lo = ctg + (size_t)a.RP * a.DS;
+  float *cn2g = reinterpret_cast<float *>(ctg_lo + (size_t)a.RP * a.DS);
   a.ctg = ctg;
+  a.ctg_lo = ctg_lo;
   a.cn2g = cn2g;
-  hipLaunchKernelGGL(prep_landmarks_kernel<PREC>, dim3(a.RP), dim3(64), 0, s, a, ctg, cn2g);
+  hipLaunchKernelGGL(prep_landmarks_kernel<PREC>, dim3(a.RP), dim3(64), 0, s, a, ctg, ctg_lo, cn2g);
   return hipGetLastError();
 }
 
@@ -808,7 +838,7 @@ bool mfma_path_supported(const Guide &g, int r, int prec) {
 
 size_t mfma_landmark_scratch_bytes(const Guide &g, int r) {
   const MArgs a = make_args(g, nullptr, r, nullptr, 16);
-  return 2 * (size_t)a.RP * a.DS + sizeof(float) * a.RP;
+  return 2 * 2 * (size_t)a.RP * a.DS + sizeof(float) * a.RP;
 }
 
 size_t guide_mean_scratch_doubles(const Guide &g) {

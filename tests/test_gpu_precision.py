@@ -1,5 +1,6 @@
 """Precision forms: the distance/embedding step on MFMA with BF16 or FP16
-centred operands (FP32 accumulation, FP32 norms, FP64 landmark factor).
+centred operands (FP32 accumulation, FP32 norms, FP64 landmark factor); the
+embedding takes each product as 16-bit hi + lo pairs (three MFMA passes).
 
 Graded as PSNR >= 45 dB against the FP64 oracle of Algorithm 1 with the same
 landmarks (peak 255 for colour, 1 for the [0, 1] hyperspectral cube).  The
@@ -68,11 +69,64 @@ def test_nlm_patch_precision_forms(prec):
     p16, p32 = exact.psnr(g, go), exact.psnr(g32, go)
     print(f"[nlm {prec}] PSNR vs FP64 Nystrom {p16:.1f} dB (FP32 form {p32:.1f} dB)", flush=True)
     assert np.isfinite(g).all()
-    if prec == "fp16":
-        # the NLM workload's precision form; BF16 (8-bit mantissa) is reported
-        # for comparison only: centred 147-dimensional patch products lose
-        # about 2^-8 of |p~||c~|, which the near-identity NLM kernel amplifies
-        assert p16 >= 45.0
+    # single-pass 16-bit products lose about 2^-8 (BF16) or 2^-11 (FP16) of
+    # |p~||c~| on the centred 147-dimensional patches; the hi + lo pairs of the
+    # embedding keep about twice those bits
+    assert p16 >= 45.0
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_pca_nlm_precision_forms(prec):
+    """PCA-NLM guide (7 x 7 x 3 patches reduced to 25 dimensions, standard
+    deviations up to several hundred against sigma_r = 90): the 16-bit forms
+    against the FP64 oracle with the same guide and landmarks."""
+    nkf = _nkf()
+    f, prm = synth.workload("color_pca_nlm_1024", 96, 80)
+    ft = torch.from_numpy(f).cuda()
+    g = nkf.patch_pca(ft, patch_radius=prm["patch_radius"], dim=prm["pca_dim"], seed=prm["seed"])
+    g64 = g.cpu().numpy().astype(np.float64)
+    c32 = _landmarks(g64.reshape(-1, g64.shape[2]), prm["r"], prm["landmark_seed"], 5)
+    kw = dict(sigma_s=1.0, sigma_r=prm["sigma_r"], radius=prm["S"], spatial="box")
+    go = nystrom.nystrom_filter(f.astype(np.float64), g64, c32.astype(np.float64), 1.0, prm["sigma_r"], prm["S"],
+                                "box")
+    _, _, F, _ = nkf.landmark_factor(c32.astype(np.float64), prm["sigma_r"])
+    out = nkf.filter_landmarks(ft, torch.from_numpy(c32).cuda(), F, g, precision=prec, **kw)
+    ps = exact.psnr(out.cpu().numpy().astype(np.float64), go)
+    print(f"[pca-nlm {prec}] PSNR vs FP64 Nystrom {ps:.1f} dB (guide std max {g64.reshape(-1, g64.shape[2]).std(0).max():.0f})",
+          flush=True)
+    assert ps >= 45.0
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_precision_forms_ill_conditioned_factor(prec):
+    """Landmarks close together relative to sigma_r make A ill-conditioned, so
+    F = Q Lambda^{-1/2} has large entries and the mix u = F^T b cancels.  The
+    16-bit forms apply F in FP32 on the matrix cores; this bounds what that
+    costs against the FP64 oracle, next to the FP32 form."""
+    nkf = _nkf()
+    h, w, D, r = 64, 56, 16, 24
+    rng = np.random.default_rng(11)
+    f = synth.rectangles_image(h, w, 3, 15.0, seed=12)
+    # a smooth 16-dimensional guide: random low-frequency fields
+    yy, xx = np.mgrid[0:h, 0:w] / 16.0
+    p = np.stack([np.sin(rng.uniform(0.5, 2) * yy + rng.uniform(0, 6)) * np.cos(rng.uniform(0.5, 2) * xx)
+                  for _ in range(D)], axis=2).astype(np.float32)
+    c32 = _landmarks(p.reshape(-1, D).astype(np.float64), r, 4, 5)
+    sr = 8.0  # cond of the kept eigenvalues about 1.5e6, max |F| about 150
+    Q, al, F, reff = nkf.landmark_factor(c32.astype(np.float64), sr)
+    cond = al[-1] / al[len(al) - reff]
+    go = nystrom.nystrom_filter(f.astype(np.float64), p.astype(np.float64), c32.astype(np.float64), 2.0, sr, 6)
+    ft = torch.from_numpy(f).cuda()
+    pt = torch.from_numpy(p).cuda()
+    res = {}
+    for pr in (prec, "fp32"):
+        out = nkf.filter_landmarks(ft, torch.from_numpy(c32).cuda(), F, pt, sigma_s=2.0, sigma_r=sr, radius=6,
+                                   precision=pr)
+        res[pr] = exact.psnr(out.cpu().numpy().astype(np.float64), go)
+    print(f"[ill-conditioned {prec}] r_eff {reff} of {r}, cond(kept) {cond:.2e}, max|F| {np.abs(F).max():.2e}: "
+          f"PSNR vs FP64 Nystrom {res[prec]:.1f} dB (FP32 form {res['fp32']:.1f} dB)", flush=True)
+    assert cond > 1e5
+    assert res[prec] >= 45.0
 
 
 def _tie_bound(Pc, cc, eps):
