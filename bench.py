@@ -395,8 +395,16 @@ def leg_pca_nlm(steps, warmup):
     cen = nkf.kmeans(ft, g, r=prm["r"], iters=prm["iters"], seed=prm["landmark_seed"])
     Q, al, F, r_eff = nkf.landmark_factor(cen.cpu().numpy().astype(np.float64), prm["sigma_r"])
     fl = {prec: nkf.filter_landmarks(ft, cen, F, g, sigma_s=1.0, sigma_r=prm["sigma_r"], radius=prm["S"],
-                                     spatial="box", precision=prec) for prec in ("fp32", "fp16")}
-    out["psnr_fp16_vs_fp32_same_landmarks_dB"] = round(_psnr(fl["fp16"], fl["fp32"], 255.0), 2)
+                                     spatial="box", precision=prec, return_eta=True) for prec in ("fp32", "fp16")}
+    # supported pixels: eta_hat keeps >= 1e-3 of the exact filter's least mass
+    # there (the pixel's own term, w(0) = 1 for the box); elsewhere no
+    # landmark is near the pixel's guide value and 1 / eta_hat amplifies
+    # any rounding, the FP64 result's included
+    sup = fl["fp32"][1] >= 1e-3
+    out["psnr_fp16_vs_fp32_same_landmarks_dB"] = round(_psnr(fl["fp16"][0], fl["fp32"][0], 255.0), 2)
+    out["psnr_fp16_vs_fp32_same_landmarks_supported_dB"] = round(
+        _psnr(fl["fp16"][0][sup], fl["fp32"][0][sup], 255.0), 2)
+    out["unsupported_pixels"] = int((~sup).sum().item())
     out["psnr_fp16_vs_fp32_own_landmarks_dB"] = round(_psnr(res["fp16"][1], res["fp32"][1], 255.0), 2)
     return out
 

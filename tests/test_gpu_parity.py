@@ -30,6 +30,11 @@ def _landmarks(P, r, seed, iters):
     return c.astype(np.float32)
 
 
+def _sample_landmarks(P, r, seed, iters, n=32768):
+    """Oracle k-means on n pixels drawn by the seeding draw (large images)."""
+    return _landmarks(P[seeding.distinct_indices(P.shape[0], n, seed + 100)], r, seed, iters)
+
+
 def _run_case(f, p, c32, sigma_s, sigma_r, S, spatial="gaussian", guide="explicit", patch_radius=3,
               center=None):
     nkf = _nkf()
@@ -235,8 +240,8 @@ def test_full_size_color_blf_2048_sampled():
     nkf = _nkf()
     f, prm = synth.workload("color_blf_2048")
     ft = torch.from_numpy(f).cuda()
-    c = nkf.kmeans(ft, r=prm["r"], iters=prm["iters"], seed=prm["landmark_seed"])
-    c32 = c.cpu().numpy()
+    c32 = _sample_landmarks(f.reshape(-1, 3).astype(np.float64), prm["r"], prm["landmark_seed"], prm["iters"])
+    c = torch.from_numpy(c32).cuda()
     Q, al, F, reff = nkf.landmark_factor(c32.astype(np.float64), prm["sigma_r"])
     g, eta = nkf.filter_landmarks(ft, c, F, sigma_s=prm["sigma_s"], sigma_r=prm["sigma_r"],
                                   radius=prm["S"], return_eta=True)

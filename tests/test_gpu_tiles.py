@@ -53,6 +53,11 @@ def _landmarks(P, r, seed, iters):
     return c.astype(np.float32)
 
 
+def _sample_landmarks(P, r, seed, iters, n=16384):
+    """Oracle k-means on n pixels drawn by the seeding draw (large images)."""
+    return _landmarks(P[seeding.distinct_indices(P.shape[0], n, seed + 100)], r, seed, iters)
+
+
 def _grade(name, g, go, bound, tol):
     """g, go, bound: [..., C].  1e-4-type bar where the bound allows it."""
     err = np.abs(g - go)
@@ -211,14 +216,14 @@ def test_full_size_nlm_1024_sampled():
     f, prm = synth.workload("color_nlm_1024")
     ft = torch.from_numpy(f).cuda()
     kw = dict(guide="patch", patch_radius=prm["patch_radius"])
-    c = nkf.kmeans(ft, r=prm["r"], iters=3, seed=prm["landmark_seed"], **kw)
-    c32 = c.cpu().numpy()
+    pg = exact.patch_guide(f.astype(np.float64), prm["patch_radius"])
+    c32 = _sample_landmarks(pg.reshape(-1, pg.shape[2]), prm["r"], prm["landmark_seed"], 3)
+    c = torch.from_numpy(c32).cuda()
     Q, al, F, reff = nkf.landmark_factor(c32.astype(np.float64), prm["sigma_r"])
     g = nkf.filter_landmarks(ft, c, F, sigma_s=1.0, sigma_r=prm["sigma_r"], radius=prm["S"], spatial="box", **kw)
     g = g.cpu().numpy().astype(np.float64)
     H, W = f.shape[:2]
     coords = _sampled_coords(H, W, 30, 1)
-    pg = exact.patch_guide(f.astype(np.float64), prm["patch_radius"])
     args = (f.astype(np.float64), pg, c32.astype(np.float64), 1.0, prm["sigma_r"], prm["S"], coords)
     go, _ = nystrom.nystrom_filter_at(*args, spatial="box")
     _grade_box("nlm1024_sampled", g[coords[:, 0], coords[:, 1]], go, TOL_255)
@@ -232,8 +237,8 @@ def test_full_size_hyperspectral_512_sampled():
     nkf = _nkf()
     f, prm = synth.workload("hyperspectral_512x128")
     ft = torch.from_numpy(f).cuda()
-    c = nkf.kmeans(ft, r=prm["r"], iters=3, seed=prm["landmark_seed"])
-    c32 = c.cpu().numpy()
+    c32 = _sample_landmarks(f.reshape(-1, f.shape[2]).astype(np.float64), prm["r"], prm["landmark_seed"], 3)
+    c = torch.from_numpy(c32).cuda()
     Q, al, F, reff = nkf.landmark_factor(c32.astype(np.float64), prm["sigma_r"])
     g = nkf.filter_landmarks(ft, c, F, sigma_s=prm["sigma_s"], sigma_r=prm["sigma_r"], radius=prm["S"])
     g = g.cpu().numpy().astype(np.float64)
