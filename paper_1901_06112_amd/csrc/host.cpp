@@ -461,23 +461,32 @@ struct FwdBufs {
   void *lm;      // prepared 16-bit landmarks
   double *ct64;  // transposed FP64 landmarks of the FP32 embedding
   float *eta_stat;  // eta_hat for the statistics when the caller passes no eta_out
+  void *wk;         // operands of the windowed MFMA form (16-bit forms, C > 3), else null
 };
 
+// The 16-bit forms on more than three channels evaluate the windows on MFMA
+// (kernels_wk.hip) instead of convolving r_eff (C + 1) planes; wk_r bounds
+// r_eff (the landmark count), 0 when the windowed form is not used.
+int fwd_wk_r(const Resolved &rs, const nkf_params *prm, int r) {
+  return wk_supported(rs.C, r, rs.S, prm->prec) ? r : 0;
+}
+
 void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r, bool u64, int num_cu,
-               bool stats = false) {
+               bool stats = false, int wk_r = 0) {
   b.f0 = cv.take<float>(rs.C);
   b.mm = cv.take<unsigned>(center_scratch_words(rs.C));
   b.u = u64 ? nullptr : cv.take<float>((size_t)r_eff * rs.N);
   b.u64 = u64 ? cv.take<double>((size_t)r_eff * rs.N) : nullptr;
   b.box_part = cv.take<double>(box_part_doubles(rs, r_eff, num_cu, u64));
-  b.eta_buf = cv.take<float>(rs.C > 3 ? rs.N : 1);
-  b.f_planar = cv.take<float>(rs.C > 3 ? (size_t)rs.C * rs.N : 1);
+  b.eta_buf = cv.take<float>(rs.C > 3 && !wk_r ? rs.N : 1);
+  b.f_planar = cv.take<float>(rs.C > 3 && !wk_r ? (size_t)rs.C * rs.N : 1);
   b.mu = cv.take<float>(rs.D);
   b.F32 = cv.take<float>((size_t)r * r_eff);
   b.mpart = cv.take<double>(guide_mean_scratch_doubles(rs.g));
   b.lm = cv.take<unsigned char>(mfma_landmark_scratch_bytes(rs.g, r));
   b.ct64 = cv.take<double>(embed_scratch_doubles(rs.g, r));
   b.eta_stat = cv.take<float>(stats ? rs.N : 1);
+  b.wk = wk_r ? static_cast<void *>(cv.take<unsigned char>(wk_scratch_bytes(rs.H, rs.W, rs.C, wk_r))) : nullptr;
 }
 
 // The landmark-independent part of the forward: the centring offsets f0 and,
@@ -528,6 +537,28 @@ nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, cons
     {
       StageTimer tm(ctx, NKF_STAGE_CONV);
       HIP_TRY(ctx, launch_box(bx, ctx->stream));
+    }
+    if (want_stats) HIP_TRY(ctx, launch_eta_stats(eta_out, rs.N, ctx->dstat, ctx->stream));
+    return NKF_OK;
+  }
+  if (b.wk) {
+    WkProblem wp{};
+    wp.H = rs.H;
+    wp.W = rs.W;
+    wp.C = rs.C;
+    wp.S = rs.S;
+    wp.r_eff = r_eff;
+    wp.prec = prm->prec;
+    wp.f = rs.g.f;
+    wp.f0 = b.f0;
+    wp.u = b.u;
+    wp.taps = rs.taps;
+    wp.out = out;
+    wp.eta_out = eta_out;
+    wp.scratch = b.wk;
+    {
+      StageTimer tm(ctx, NKF_STAGE_CONV);
+      HIP_TRY(ctx, launch_wk(wp, ctx->stream));
     }
     if (want_stats) HIP_TRY(ctx, launch_eta_stats(eta_out, rs.N, ctx->dstat, ctx->stream));
     return NKF_OK;
@@ -957,10 +988,11 @@ nkf_status nkf_filter_landmarks(nkf_ctx *ctx, int H, int W, int C, const float *
   Carve dry{nullptr};
   FwdBufs fb;
   const bool u64 = fwd_u64(rs, prm->prec);
-  carve_fwd(dry, rs, r_eff, fb, kMaxLandmarks, u64, ctx->num_cu, ctx->stats);
+  const int wk_r = fwd_wk_r(rs, prm, r_eff);
+  carve_fwd(dry, rs, r_eff, fb, kMaxLandmarks, u64, ctx->num_cu, ctx->stats, wk_r);
   if ((st = ensure_workspace(ctx, dry.off)) != NKF_OK) return st;
   Carve cv{ctx->ws};
-  carve_fwd(cv, rs, r_eff, fb, kMaxLandmarks, u64, ctx->num_cu, ctx->stats);
+  carve_fwd(cv, rs, r_eff, fb, kMaxLandmarks, u64, ctx->num_cu, ctx->stats, wk_r);
   // the factor was formed by the caller: no eigenvalues to report
   record_stats(ctx, rs, prm, r_eff, NAN, NAN);
   if ((st = run_fwd(ctx, rs, prm, centroids, F, r_eff, out, eta_out, fb, true, false, true)) != NKF_OK) return st;
@@ -978,7 +1010,8 @@ nkf_status nkf_filter_landmarks_noalloc(nkf_ctx *ctx, int H, int W, int C, const
   Carve dry{nullptr};
   FwdBufs fb;
   const bool u64 = fwd_u64(rs, prm->prec);
-  carve_fwd(dry, rs, r_eff, fb, prm->r, u64, ctx->num_cu);
+  const int wk_r = fwd_wk_r(rs, prm, r_eff);
+  carve_fwd(dry, rs, r_eff, fb, prm->r, u64, ctx->num_cu, false, wk_r);
   if (dry.off > static_scratch_bytes())
     return fail(ctx, NKF_ERR_OUT_OF_MEMORY,
                 "this problem needs %zu bytes of scratch; the static scratch holds %zu (use nkf_filter_landmarks)",
@@ -988,7 +1021,7 @@ nkf_status nkf_filter_landmarks_noalloc(nkf_ctx *ctx, int H, int W, int C, const
   if (e != hipSuccess)
     return fail(ctx, NKF_ERR_HIP, "static scratch of device %d unavailable: %s", ctx->device, hipGetErrorString(e));
   Carve cv{static_cast<char *>(base)};
-  carve_fwd(cv, rs, r_eff, fb, prm->r, u64, ctx->num_cu);
+  carve_fwd(cv, rs, r_eff, fb, prm->r, u64, ctx->num_cu, false, wk_r);
   // no stage events either: the call enqueues kernels only
   const bool timing = ctx->timing;
   ctx->timing = false;
@@ -1010,7 +1043,7 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
     c = cv.take<float>((size_t)r * rs.D);
     idx = cv.take<int64_t>(r);
     Fd = cv.take<double>((size_t)r * r);
-    carve_fwd(cv, rs, r, fb, kMaxLandmarks, fwd_u64(rs, prm->prec), ctx->num_cu, ctx->stats);
+    carve_fwd(cv, rs, r, fb, kMaxLandmarks, fwd_u64(rs, prm->prec), ctx->num_cu, ctx->stats, fwd_wk_r(rs, prm, r));
   };
   KmBufs kb;
   FwdBufs fb;

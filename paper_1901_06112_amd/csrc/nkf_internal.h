@@ -117,6 +117,25 @@ int box_splits(int H, int W, int S, int r_eff, int num_cu, int u_fp64);
 size_t box_partials_doubles(int H, int W, int S, int r_eff, int num_cu, int u_fp64);
 hipError_t launch_box(const BoxProblem &pb, hipStream_t s);
 
+// ---- kernels_wk.hip ---------------------------------------------------------
+// Windowed Nystrom-kernel evaluation on MFMA for many channels (16-bit forms):
+// K_hat = U_keys U_queries^T per window, then zeta = (w K_hat)^T (f - f0).
+constexpr int kWkMaxRank = 64;
+struct WkProblem {
+  int H, W, C, S, r_eff, prec;  // prec 1 = BF16, 2 = FP16
+  const float *f;     // [H, W, C]
+  const float *f0;    // [C] centring offsets
+  const float *u;     // [r_eff][N] FP32 planes
+  Taps taps;
+  float *out;         // [H, W, C]
+  float *eta_out;     // nullable [N]
+  void *scratch;      // wk_scratch_bytes(H, W, C, r_eff or more)
+};
+// Whether the windowed form serves C channels, up to r landmarks, radius S.
+bool wk_supported(int C, int r, int S, int prec);
+size_t wk_scratch_bytes(int H, int W, int C, int r);
+hipError_t launch_wk(const WkProblem &pb, hipStream_t s);
+
 // ---- kernels_bwd.hip --------------------------------------------------------
 // Backward passes (C <= 3).  mode 1: du_dir planes; 2: sigma_s partial sums
 // (one double per block, with row taps wr and column taps wc); 3: adjoint
