@@ -51,6 +51,31 @@ PEAK_HBM_GBS = 8000.0
 PEAK_MFMA16_TFLOPS = 2500.0       # MI355X dense BF16 / FP16 matrix peak
 
 
+def wk_flops_per_pixel(r_eff, C, T):
+    """Algorithmic flops per pixel of the windowed form (the 16-bit forms on
+    C > 3): for each of the T^2 window pixels y, K_hat(x, y) = u(x).u(y)
+    (2 r_eff), the weight (1) and the weighted sums of f~(y) and of 1 for
+    eta_hat (2 (C + 1))."""
+    return T * T * (2 * r_eff + 1 + 2 * (C + 1))
+
+
+def wk_mfma_flops_issued(H, W, C, r_eff, S):
+    """Matrix-core flops the windowed kernel issues per launch: 8-row by
+    32-column query tiles of 8 waves, two 16-query units per wave; a wave
+    works on the 2S + 5 key rows that reach one of its units: three 16-key
+    tiles x r_eff / 32 steps (rounded up to 32 or 64) x three split passes x
+    two units on GEMM1, and 2 x two units per 16 channels on GEMM2; each
+    16x16x32 MFMA is 16384 flops.  Includes the tile halo, the padding and
+    the zero half of the last key pair: the work the kernel actually
+    issues, next to the algorithmic work."""
+    rs = 1 if r_eff <= 32 else 2
+    ct = (C + 15) // 16
+    chunks = (ct + 7) // 8
+    per_row = chunks * (3 * rs * 3 * 2) + ct * 2 * 2
+    blocks = ((W + 31) // 32) * ((H + 7) // 8)
+    return blocks * 8 * (2 * S + 5) * per_row * 16384
+
+
 def conv_flops_per_pixel(r_eff, C, T):
     """Algorithmic flops of the convolution + contraction stage per pixel:
     P = r_eff (C+1) planes, two separable T-tap passes (2 flops per tap),
@@ -332,6 +357,20 @@ def leg_precision(name, steps, warmup):
                                     "achieved": round(nbytes / conv_s / 1e9, 1), "peak": PEAK_HBM_GBS,
                                     "frac": round(nbytes / conv_s / 1e9 / PEAK_HBM_GBS, 4),
                                     "algorithmic_bytes_per_launch": nbytes}
+        elif prec != "fp32" and C > 3 and r_eff <= 64:
+            # the windowed form on the matrix cores (stage time includes its
+            # two operand-preparation kernels)
+            T = 2 * prm["S"] + 1
+            fl = wk_flops_per_pixel(r_eff, C, T) * N
+            issued = wk_mfma_flops_issued(H, W, C, r_eff, prm["S"])
+            ent["conv_roofline"] = {"kernel": "wk_kernel (windowed K_hat on MFMA)", "bound": "mfma",
+                                    "unit": "TFLOP/s", "achieved": round(fl / conv_s / 1e12, 2),
+                                    "peak": PEAK_MFMA16_TFLOPS,
+                                    "frac": round(fl / conv_s / 1e12 / PEAK_MFMA16_TFLOPS, 4),
+                                    "algorithmic_flops_per_launch": fl,
+                                    "issued_mfma_flops_per_launch": issued,
+                                    "issued_frac": round(issued / conv_s / 1e12 / PEAK_MFMA16_TFLOPS, 4),
+                                    "fir_flops_replaced": conv_flops_per_pixel(r_eff, C, T) * N}
         else:
             T = 2 * prm["S"] + 1
             fl = conv_flops_per_pixel(r_eff, C, T) * N

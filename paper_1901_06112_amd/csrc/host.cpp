@@ -489,11 +489,23 @@ void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r, bool
   b.wk = wk_r ? static_cast<void *>(cv.take<unsigned char>(wk_scratch_bytes(rs.H, rs.W, rs.C, wk_r))) : nullptr;
 }
 
-// The landmark-independent part of the forward: the centring offsets f0 and,
-// for the 16-bit distance path, the guide mean.
+// The landmark-independent part of the forward: the centring offsets f0,
+// for the 16-bit distance path the guide mean, and for the windowed form its
+// centred 16-bit image.
 nkf_status run_pre(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, const FwdBufs &b) {
   HIP_TRY(ctx, launch_center(rs.g.f, rs.N, rs.C, prm->center, b.f0, b.mm, ctx->stream));
   if (use_mfma_distance(rs.g, prm->prec)) HIP_TRY(ctx, launch_guide_mean(rs.g, b.mu, b.mpart, ctx->stream));
+  if (b.wk) {
+    WkProblem wp{};
+    wp.H = rs.H;
+    wp.W = rs.W;
+    wp.C = rs.C;
+    wp.prec = prm->prec;
+    wp.f = rs.g.f;
+    wp.f0 = b.f0;
+    wp.scratch = b.wk;
+    HIP_TRY(ctx, launch_wk_prep_f(wp, ctx->stream));
+  }
   return NKF_OK;
 }
 

@@ -94,48 +94,81 @@ struct WkStage {
 };
 
 // ---- preparation: zero-padded 16-bit operands -------------------------------
+// Both kernels walk the H x WP storage slots (slot = y WP + storage column) in
+// groups of 64 and transpose through LDS, so that the reads (planes of u,
+// pixels of f) and the writes (pixel-major u, channel planes of f) are
+// contiguous runs.
+
+constexpr int kPrepPx = 64;
 
 template <typename T>
 __global__ __launch_bounds__(256) void wk_prep_u_kernel(const float *__restrict__ u, int64_t N, int r_eff, int H,
                                                         int W, int WP, int RP, T *__restrict__ uh,
                                                         T *__restrict__ ul) {
-  const int KC = RP / 8;
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (int64_t)H * KC * WP) return;
-  const int sc = (int)(t % WP);
-  const int64_t rest = t / WP;
-  const int kc = (int)(rest % KC), y = (int)(rest / KC);
-  const int x = sc - kColOff;
-  typename WkOp<T>::V8 hi, lo;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int k = 8 * kc + i;
-    const float v = (x >= 0 && x < W && k < r_eff) ? u[(int64_t)k * N + (int64_t)y * W + x] : 0.0f;
-    hi[i] = (T)v;
-    lo[i] = (T)(v - (float)hi[i]);
+  __shared__ float tile[64][kPrepPx + 1];  // [plane][slot]
+  const int64_t nslots = (int64_t)H * WP;
+  const int64_t s0 = (int64_t)blockIdx.x * kPrepPx;
+  const int tid = threadIdx.x;
+  // read: plane k, 64 consecutive slots (pixels of one image row or two)
+  for (int e = tid; e < RP * kPrepPx; e += 256) {
+    const int k = e / kPrepPx, px = e % kPrepPx;
+    const int64_t sl = s0 + px;
+    float v = 0.0f;
+    if (sl < nslots && k < r_eff) {
+      const int y = (int)(sl / WP), x = (int)(sl % WP) - kColOff;
+      if (x >= 0 && x < W) v = u[(int64_t)k * N + (int64_t)y * W + x];
+    }
+    tile[k][px] = v;
   }
-  const int64_t o = ((int64_t)y * WP + sc) * RP + 8 * kc;
-  *reinterpret_cast<typename WkOp<T>::V8 *>(uh + o) = hi;
-  *reinterpret_cast<typename WkOp<T>::V8 *>(ul + o) = lo;
+  __syncthreads();
+  // write: 8 planes of one slot per thread-step, consecutive threads along the
+  // slot's RP values, then the next slot
+  const int KC = RP / 8;
+  for (int e = tid; e < KC * kPrepPx; e += 256) {
+    const int px = e / KC, kc = e % KC;
+    const int64_t sl = s0 + px;
+    if (sl >= nslots) continue;
+    typename WkOp<T>::V8 hi, lo;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const float v = tile[8 * kc + i][px];
+      hi[i] = (T)v;
+      lo[i] = (T)(v - (float)hi[i]);
+    }
+    *reinterpret_cast<typename WkOp<T>::V8 *>(uh + sl * RP + 8 * kc) = hi;
+    *reinterpret_cast<typename WkOp<T>::V8 *>(ul + sl * RP + 8 * kc) = lo;
+  }
 }
 
+// grid: (slot groups, channel groups of 128)
 template <typename T>
 __global__ __launch_bounds__(256) void wk_prep_f_kernel(const float *__restrict__ f, const float *__restrict__ f0,
                                                         int C, int CP, int H, int W, int WP, T *__restrict__ ft) {
-  const int QW = WP / 8;
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (int64_t)H * QW * CP) return;
-  const int c = (int)(t % CP);
-  const int64_t rest = t / CP;
-  const int q = (int)(rest % QW), y = (int)(rest / QW);
-  const float c0 = c < C ? f0[c] : 0.0f;
-  typename WkOp<T>::V8 v;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int x = 8 * q + i - kColOff;
-    v[i] = (T)((c < C && x >= 0 && x < W) ? f[((int64_t)y * W + x) * C + c] - c0 : 0.0f);
+  __shared__ T tile[kCB][kPrepPx + 8];  // [channel][slot]
+  const int64_t nslots = (int64_t)H * WP;
+  const int64_t s0 = (int64_t)blockIdx.x * kPrepPx;
+  const int cb = blockIdx.y * kCB, nc = min(kCB, CP - cb);
+  const int tid = threadIdx.x;
+  // read: the slots' pixels, channels cb .. cb + nc - 1 (contiguous per pixel)
+  for (int e = tid; e < nc * kPrepPx; e += 256) {
+    const int px = e / nc, c = e % nc;
+    const int64_t sl = s0 + px;
+    float v = 0.0f;
+    if (sl < nslots && cb + c < C) {
+      const int y = (int)(sl / WP), x = (int)(sl % WP) - kColOff;
+      if (x >= 0 && x < W) v = f[((int64_t)y * W + x) * C + cb + c] - f0[cb + c];
+    }
+    tile[c][px] = (T)v;
   }
-  *reinterpret_cast<typename WkOp<T>::V8 *>(ft + ((int64_t)c * H + y) * WP + 8 * q) = v;
+  __syncthreads();
+  // write: 8 slots of one channel per thread-step
+  for (int e = tid; e < nc * (kPrepPx / 8); e += 256) {
+    const int c = e / (kPrepPx / 8), q = e % (kPrepPx / 8);
+    const int64_t sl = s0 + 8 * q;
+    if (sl >= nslots) continue;  // nslots is a multiple of 8 (WP is)
+    *reinterpret_cast<typename WkOp<T>::V8 *>(ft + (int64_t)(cb + c) * nslots + sl) =
+        *reinterpret_cast<const typename WkOp<T>::V8 *>(&tile[c][8 * q]);
+  }
 }
 
 // ---- the windowed kernel ----------------------------------------------------
@@ -357,19 +390,15 @@ template <typename T>
 hipError_t launch_wk_t(const WkProblem &pb, hipStream_t s) {
   const int WP = wk_wp(pb.W), RP = 32 * wk_rs(pb.r_eff), CP = (pb.C + 15) / 16 * 16;
   const int64_t N = (int64_t)pb.H * pb.W;
-  T *uh = static_cast<T *>(pb.scratch);
+  // scratch: the centred image first (prepared by launch_wk_prep_f, which
+  // needs no landmarks), then the embedding hi and lo
+  T *ft = static_cast<T *>(pb.scratch);
+  T *uh = ft + (size_t)CP * pb.H * WP;
   T *ul = uh + (size_t)pb.H * WP * RP;
-  T *ft = ul + (size_t)pb.H * WP * RP;
-  {
-    const int64_t n = (int64_t)pb.H * (RP / 8) * WP;
-    hipLaunchKernelGGL(wk_prep_u_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pb.u, N, pb.r_eff,
-                       pb.H, pb.W, WP, RP, uh, ul);
-  }
-  {
-    const int64_t n = (int64_t)pb.H * (WP / 8) * CP;
-    hipLaunchKernelGGL(wk_prep_f_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pb.f, pb.f0, pb.C,
-                       CP, pb.H, pb.W, WP, ft);
-  }
+  const unsigned groups = (unsigned)(((int64_t)pb.H * WP + kPrepPx - 1) / kPrepPx);
+  hipLaunchKernelGGL(wk_prep_u_kernel<T>, dim3(groups), dim3(256), 0, s, pb.u, N, pb.r_eff, pb.H, pb.W, WP, RP,
+                     uh, ul);
+
   WkArgs a{};
   a.H = pb.H;
   a.W = pb.W;
@@ -394,7 +423,20 @@ hipError_t launch_wk_t(const WkProblem &pb, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_wk_prep_f_t(const WkProblem &pb, hipStream_t s) {
+  const int WP = wk_wp(pb.W), CP = (pb.C + 15) / 16 * 16;
+  const unsigned groups = (unsigned)(((int64_t)pb.H * WP + kPrepPx - 1) / kPrepPx);
+  hipLaunchKernelGGL(wk_prep_f_kernel<T>, dim3(groups, (unsigned)((CP + kCB - 1) / kCB)), dim3(256), 0, s, pb.f,
+                     pb.f0, pb.C, CP, pb.H, pb.W, WP, static_cast<T *>(pb.scratch));
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_wk_prep_f(const WkProblem &pb, hipStream_t s) {
+  return pb.prec == 1 ? launch_wk_prep_f_t<__bf16>(pb, s) : launch_wk_prep_f_t<_Float16>(pb, s);
+}
 
 bool wk_supported(int C, int r, int S, int prec) {
   return prec != 0 && C >= 4 && r <= kWkMaxRank && S <= kMaxRadius;

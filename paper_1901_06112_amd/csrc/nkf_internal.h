@@ -131,6 +131,9 @@ struct WkProblem {
   float *eta_out;     // nullable [N]
   void *scratch;      // wk_scratch_bytes(H, W, C, r_eff or more)
 };
+// The centred 16-bit image the windowed kernel reads (landmark-independent:
+// enqueue it before the landmark factor); launch_wk expects it in scratch.
+hipError_t launch_wk_prep_f(const WkProblem &pb, hipStream_t s);
 // Whether the windowed form serves C channels, up to r landmarks, radius S.
 bool wk_supported(int C, int r, int S, int prec);
 size_t wk_scratch_bytes(int H, int W, int C, int r);
