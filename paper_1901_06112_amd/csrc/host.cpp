@@ -11,6 +11,7 @@
 
 #include <chrono>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/nkf.h"
@@ -492,9 +493,17 @@ void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r, bool
 // The landmark-independent part of the forward: the centring offsets f0,
 // for the 16-bit distance path the guide mean, and for the windowed form its
 // centred 16-bit image.
-nkf_status run_pre(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, const FwdBufs &b) {
+// mu_ready: the guide mean the k-means of this call already formed (copied
+// instead of recomputed), or null.
+nkf_status run_pre(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, const FwdBufs &b,
+                   const float *mu_ready = nullptr) {
   HIP_TRY(ctx, launch_center(rs.g.f, rs.N, rs.C, prm->center, b.f0, b.mm, ctx->stream));
-  if (use_mfma_distance(rs.g, prm->prec)) HIP_TRY(ctx, launch_guide_mean(rs.g, b.mu, b.mpart, ctx->stream));
+  if (use_mfma_distance(rs.g, prm->prec)) {
+    if (mu_ready)
+      HIP_TRY(ctx, hipMemcpyAsync(b.mu, mu_ready, sizeof(float) * rs.D, hipMemcpyDeviceToDevice, ctx->stream));
+    else
+      HIP_TRY(ctx, launch_guide_mean(rs.g, b.mu, b.mpart, ctx->stream));
+  }
   if (b.wk) {
     WkProblem wp{};
     wp.H = rs.H;
@@ -608,7 +617,8 @@ struct KmBufs {
 };
 
 void carve_km(Carve &cv, const Resolved &rs, int r, KmBufs &b) {
-  b.sums = cv.take<double>(kmeans_partials_doubles(r, rs.D));
+  // the partial sums double as the scratch of the guide mean
+  b.sums = cv.take<double>(std::max(kmeans_partials_doubles(r, rs.D), guide_mean_scratch_doubles(rs.g)));
   b.lab_scratch = cv.take<int>(rs.N);
   b.mu = cv.take<float>(rs.D);
   b.lm = cv.take<unsigned char>(mfma_landmark_scratch_bytes(rs.g, r));
@@ -1080,7 +1090,8 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
     if (!ctx->copy_done) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->copy_done, hipEventDisableTiming));
     HIP_TRY(ctx, hipEventRecord(ctx->copy_done, ctx->stream));
     // landmark-independent work runs on the device while the host factors A
-    if ((st = run_pre(ctx, rs, prm, fb)) != NKF_OK) return st;
+    const bool mean_ready = prm->kmeans_iters > 0 && use_mfma_distance(rs.g, prm->prec);
+    if ((st = run_pre(ctx, rs, prm, fb, mean_ready ? kb.mu : nullptr)) != NKF_OK) return st;
     HIP_TRY(ctx, hipEventSynchronize(ctx->copy_done));
     // the factor stage is the host's work once the landmarks have arrived, so
     // timing it needs no extra synchronisation

@@ -51,7 +51,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 constexpr int kMaxChunks = 64;   // 8-element chunks of the permuted axis (Dp <= 512)
 constexpr int kMaxDc = 4;        // dimensions per lane in the accumulation (D <= 256)
 constexpr int kMaxBlocks = 256;  // k-means partial slots
-constexpr int kMeanBlocks = 256;
+constexpr int kMeanBlocks = 1024;
 constexpr int kEmbedBlocks = 512;
 constexpr size_t kLdsMax = 160 * 1024;
 
@@ -84,7 +84,8 @@ struct MArgs {
   // Dp = NR * RLP rounded up to 32; DS = Dp + 8 (landmark row stride, halves)
   int NR, RL, RLP, Dp, DS;
   // raw tile: value (pixel i, run q, element e) at q * rowstride + i * pxstride + e
-  int rowstride, pxstride, raw_floats;
+  int rowstride, pxstride, raw_floats;  // raw_floats includes muf floats for the offsets
+  int muf;
   int tiles_x;       // patch guides: tiles per image row
   int ntiles;
   const void *ctg;   // [RP][DS] 16-bit centred landmarks on the permuted axis
@@ -128,9 +129,12 @@ __device__ __forceinline__ TileInfo tile_info(const MArgs &a, int t) {
   return ti;
 }
 
-// Centred FP32 guide data of one tile into raw.
+// Centred FP32 guide data of one tile into raw; mus is the block's LDS copy
+// of the centring offsets.  For explicit and self guides every thread issues
+// its loads in batches of eight (float4 where D % 4 == 0) before storing any,
+// so a tile costs about one memory latency instead of one per element.
 template <int TP, int BT>
-__device__ __forceinline__ void stage_raw(const MArgs &a, const TileInfo &ti, float *raw) {
+__device__ __forceinline__ void stage_raw(const MArgs &a, const TileInfo &ti, float *raw, const float *mus) {
   const Guide &g = a.g;
   const int tid = threadIdx.x;
   if (g.kind == GUIDE_PATCH) {
@@ -143,7 +147,7 @@ __device__ __forceinline__ void stage_raw(const MArgs &a, const TileInfo &ti, fl
       float *dst = raw + q * a.rowstride + j * C;
       if (xs < g.W + g.pr) {  // columns past the padded image edge are never read
         const float *src = g.f + ((int64_t)yy * g.W + sym_index(xs, g.W)) * C;
-        for (int ch = 0; ch < C; ++ch) dst[ch] = src[ch] - a.mu[ch];
+        for (int ch = 0; ch < C; ++ch) dst[ch] = src[ch] - mus[ch];
       } else {
         for (int ch = 0; ch < C; ++ch) dst[ch] = 0.0f;
       }
@@ -151,19 +155,78 @@ __device__ __forceinline__ void stage_raw(const MArgs &a, const TileInfo &ti, fl
   } else {
     const int D = g.D;
     const float *src = (g.kind == GUIDE_EXPLICIT ? g.p : g.f) + ti.x0 * D;
-    // element e = i D + d of the tile, walked with incremental (i, d)
-    int i = tid / D, d = tid - (tid / D) * D;
-    const int di = BT / D, dd = BT - (BT / D) * D;
-    for (int e = tid; e < TP * D; e += BT) {
-      raw[i * a.pxstride + d] = i < ti.nvalid ? src[e] - a.mu[d] : 0.0f;
-      i += di;
-      d += dd;
-      if (d >= D) {
-        d -= D;
-        ++i;
+    const int ntot = TP * D, nval = ti.nvalid * D;
+    if ((D & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+      // float4 groups (never across pixels: D % 4 == 0), walked with
+      // incremental (pixel, dimension) indices
+      constexpr int NB = 8, STEP = 4 * BT;
+      const int di = STEP / D, dd = STEP - di * D;
+      int i = (4 * tid) / D, d = 4 * tid - i * D;
+      for (int b = 4 * tid; b < ntot; b += NB * STEP) {
+        float4 v[NB];
+        int pi[NB], pd[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const int e = b + k * STEP;
+          pi[k] = i;
+          pd[k] = d;
+          v[k] = e < nval ? *reinterpret_cast<const float4 *>(src + e) : make_float4(0.f, 0.f, 0.f, 0.f);
+          i += di;
+          d += dd;
+          if (d >= D) {
+            d -= D;
+            ++i;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const int e = b + k * STEP;
+          if (e >= ntot) break;
+          float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (e < nval) {
+            const float *m = mus + pd[k];
+            o = make_float4(v[k].x - m[0], v[k].y - m[1], v[k].z - m[2], v[k].w - m[3]);
+          }
+          *reinterpret_cast<float4 *>(raw + pi[k] * a.pxstride + pd[k]) = o;
+        }
+      }
+    } else {
+      // element e = i D + d of the tile, walked with incremental (i, d)
+      constexpr int NB = 8;
+      const int di = BT / D, dd = BT - (BT / D) * D;
+      int i = tid / D, d = tid - (tid / D) * D;
+      for (int b = tid; b < ntot; b += NB * BT) {
+        float v[NB];
+        int pi[NB], pd[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const int e = b + k * BT;
+          pi[k] = i;
+          pd[k] = d;
+          v[k] = e < nval ? src[e] : 0.0f;
+          i += di;
+          d += dd;
+          if (d >= D) {
+            d -= D;
+            ++i;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const int e = b + k * BT;
+          if (e >= ntot) break;
+          raw[pi[k] * a.pxstride + pd[k]] = e < nval ? v[k] - mus[pd[k]] : 0.0f;
+        }
       }
     }
   }
+}
+
+// The block's copy of the centring offsets sits at the end of the raw area.
+__device__ __forceinline__ float *raw_mu(const MArgs &a, float *raw) { return raw + a.raw_floats - a.muf; }
+__device__ __forceinline__ void load_mu(const MArgs &a, float *mus, int BT) {
+  const int M = a.g.kind == GUIDE_PATCH ? a.g.C : a.g.D;
+  for (int e = threadIdx.x; e < M; e += BT) mus[e] = a.mu[e];
 }
 
 // Chunk table of the permuted axis (raw offset without the pixel term, and
@@ -372,6 +435,7 @@ __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
 
   load_landmarks(a, ct, cn2, BT);
   build_tables(a, tab_off, tab_nv, dmap, BT);
+  load_mu(a, raw_mu(a, raw), BT);
   for (int e = tid; e < TP; e += BT) labs[e] = -1;
   if constexpr (MDT > 0) {
     for (int e = tid; e < a.RP * OHS; e += BT) oh[e] = (T)0.0f;
@@ -406,7 +470,7 @@ __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileInfo ti = tile_info<TP>(a, t);
     __syncthreads();
-    stage_raw<TP, BT>(a, ti, raw);
+    stage_raw<TP, BT>(a, ti, raw, raw_mu(a, raw));
     __syncthreads();
     {
       floatx4 acc[NT];
@@ -543,6 +607,7 @@ __global__ __launch_bounds__(BT) void embed_mfma_kernel(MArgs a) {
 
   load_landmarks(a, ct, cn2, BT, ct_lo);
   build_tables(a, tab_off, tab_nv, nullptr, BT);
+  load_mu(a, raw_mu(a, raw), BT);
   // mix operand A = F^T: A[k'][j] = F[j][k']; lane (col, rq) takes
   // A[16 t2 + col][4 s + rq] for the wave's tiles t2 = w + NW m
   auto fval = [&](int m, int s) {
@@ -559,7 +624,7 @@ __global__ __launch_bounds__(BT) void embed_mfma_kernel(MArgs a) {
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileInfo ti = tile_info<TP>(a, t);
     __syncthreads();
-    stage_raw<TP, BT>(a, ti, raw);
+    stage_raw<TP, BT>(a, ti, raw, raw_mu(a, raw));
     __syncthreads();
     floatx4 acc[NT];
     float s2;
@@ -610,6 +675,9 @@ __global__ __launch_bounds__(BT) void embed_mfma_kernel(MArgs a) {
 // m < C: a patch dimension takes its channel's mean).  Block b sums a
 // contiguous pixel range in FP64 with lanes (m, ln); the block partials are
 // then added in block order, so the result is deterministic.
+// Guide mean: per-block FP64 partial sums over a contiguous pixel range (eight
+// independent accumulators per thread keep eight loads in flight), then one
+// block per dimension sums the partials in a fixed order.
 __global__ __launch_bounds__(256) void mean_partial_kernel(Guide g, int64_t N, int M, double *part) {
   __shared__ double red[256];
   const int tid = threadIdx.x;
@@ -619,10 +687,19 @@ __global__ __launch_bounds__(256) void mean_partial_kernel(Guide g, int64_t N, i
   const int stride = g.kind == GUIDE_EXPLICIT ? g.D : g.C;
   const int64_t per = (N + gridDim.x - 1) / gridDim.x;
   const int64_t x0 = per * blockIdx.x, x1 = x0 + per < N ? x0 + per : N;
-  double s = 0.0;
-  if (ln < lanes)
-    for (int64_t x = x0 + ln; x < x1; x += lanes) s += src[x * stride + m];
-  red[tid] = s;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (ln < lanes) {
+    int64_t x = x0 + ln;
+    for (; x + 7 * lanes < x1; x += 8 * lanes) {
+      float v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = src[(x + q * lanes) * stride + m];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] += v[q];
+    }
+    for (; x < x1; x += lanes) acc[0] += src[x * stride + m];
+  }
+  red[tid] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   __syncthreads();
   if (tid < M) {
     double t = 0.0;
@@ -631,12 +708,19 @@ __global__ __launch_bounds__(256) void mean_partial_kernel(Guide g, int64_t N, i
   }
 }
 
-__global__ void mean_final_kernel(const double *part, int nb, int M, int64_t N, float *mu) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= M) return;
+// grid: M blocks of 256 threads
+__global__ __launch_bounds__(256) void mean_final_kernel(const double *part, int nb, int M, int64_t N, float *mu) {
+  __shared__ double red[256];
+  const int m = blockIdx.x, tid = threadIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[(size_t)b * M + m];
-  mu[m] = (float)(s / (double)N);
+  for (int b = tid; b < nb; b += 256) s += part[(size_t)b * M + m];
+  red[tid] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) mu[m] = (float)(red[0] / (double)N);
 }
 
 __global__ void f64_to_f32_kernel(const double *src, float *dst, int n) {
@@ -659,7 +743,8 @@ MArgs make_args(const Guide &g, const float *c, int r, const float *mu, int TP) 
     a.RL = PW * g.C;
     a.pxstride = g.C;
     a.rowstride = (TP + 2 * g.pr) * g.C;
-    a.raw_floats = PW * a.rowstride;
+    a.muf = (g.C + 3) / 4 * 4;
+    a.raw_floats = PW * a.rowstride + a.muf;
     a.tiles_x = (g.W + TP - 1) / TP;
     a.ntiles = (int)((int64_t)g.H * a.tiles_x);
   } else {
@@ -669,7 +754,8 @@ MArgs make_args(const Guide &g, const float *c, int r, const float *mu, int TP) 
     // fall on distinct groups of four banks
     a.pxstride = (g.D + 63) / 64 * 64 + 4;
     a.rowstride = 0;
-    a.raw_floats = TP * a.pxstride;
+    a.muf = (g.D + 3) / 4 * 4;
+    a.raw_floats = TP * a.pxstride + a.muf;
     a.tiles_x = 0;
     a.ntiles = (int)((a.N + TP - 1) / TP);
   }
@@ -851,7 +937,7 @@ hipError_t launch_guide_mean(const Guide &g, float *mu, double *scratch, hipStre
   hipLaunchKernelGGL(mean_partial_kernel, dim3(kMeanBlocks), dim3(256), 0, s, g, N, M, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(mean_final_kernel, dim3((M + 255) / 256), dim3(256), 0, s, scratch, kMeanBlocks, M, N, mu);
+  hipLaunchKernelGGL(mean_final_kernel, dim3(M), dim3(256), 0, s, scratch, kMeanBlocks, M, N, mu);
   return hipGetLastError();
 }
 
