@@ -65,7 +65,7 @@ def _compile(src):
     if gxx:
         # AVX2 + FMA (every x86-64 host of an MI355X has them): the eigensolver's
         # rotation loops run four doubles per instruction
-        cmd = [gxx, "-O3", "-std=c++17", "-fPIC", "-Wall", "-mavx2", "-mfma", "-c", path, "-o", obj]
+        cmd = [gxx, "-O3", "-std=c++17", "-fPIC", "-Wall", "-mavx2", "-mfma", "-pthread", "-c", path, "-o", obj]
     else:
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmd = [hipcc()] + COMMON + lang + ["-c", path, "-o", obj]
@@ -87,7 +87,7 @@ def build(jobs=None, verbose=False):
                 print(f"[{src}]\n{err}", file=sys.stderr)
     objs = [o for o, _ in res]
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
+    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-pthread", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

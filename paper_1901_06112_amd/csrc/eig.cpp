@@ -2,16 +2,18 @@
 //
 // Method (Golub & Van Loan, "Matrix Computations", Sections 8.3.1-8.3.3):
 // Householder reduction A = Q T Q^T to tridiagonal form (updating the lower
-// triangle only), then implicit symmetric QR steps with the Wilkinson shift
-// on the unreduced blocks of T (kept as its diagonal and off-diagonal),
-// accumulating every reflection and rotation into Q.  Cost O(n^3) with a small
-// constant, n <= 256.
+// triangle only, the reflectors kept), then implicit symmetric QR steps with
+// the Wilkinson shift on the unreduced blocks of T (kept as its diagonal and
+// off-diagonal), the rotations recorded; the eigenvectors are the reflections
+// and rotations applied to the identity, by column blocks on up to 8 threads
+// (the columns are independent).  Cost O(n^3) with a small constant, n <= 256.
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
 
 #include <algorithm>
 #include <cmath>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -25,9 +27,19 @@ inline double sgn(double x) { return x < 0.0 ? -1.0 : 1.0; }
 
 namespace {
 
+// Threads for the eigenvector stage: from n = 96 on, up to 8, one column
+// block of at least 16 columns each (below, thread start-up costs more than
+// the work).
+int vec_threads(int n) {
+  if (n < 96) return 1;
+  const unsigned hc = std::thread::hardware_concurrency();
+  int t = std::min(8, n / 16);
+  if (hc > 0) t = std::min(t, (int)hc);
+  return std::max(1, t);
+}
+
 int sym_eig_impl(int n, const double *A, double *w, double *V) {
-  std::vector<double> T(A, A + (size_t)n * n), Q((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) Q[i * n + i] = 1.0;
+  std::vector<double> T(A, A + (size_t)n * n);
   // symmetrise (guards against a caller's round-off asymmetry)
   for (int i = 0; i < n; ++i)
     for (int j = i + 1; j < n; ++j) {
@@ -36,9 +48,13 @@ int sym_eig_impl(int n, const double *A, double *w, double *V) {
     }
 
   // ---- Householder tridiagonalisation (lower triangle) ---------------------
-  std::vector<double> v(n), p(n), q(n);
+  // reflector k acts on entries k+1 .. n-1: H_k = I - beta_k v v^T, v kept in
+  // R[k][0 .. n-k-2]; Q = H_0 H_1 ... H_{n-3} is not formed here
+  std::vector<double> R((size_t)n * n, 0.0), betas(n, 0.0);
+  std::vector<double> p(n), q(n);
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;  // length of x = T[k+1:, k]
+    double *v = &R[(size_t)k * n];
     double sigma = 0.0;
     for (int i = 1; i < m; ++i) sigma += T[(k + 1 + i) * n + k] * T[(k + 1 + i) * n + k];
     const double x0 = T[(k + 1) * n + k];
@@ -47,8 +63,8 @@ int sym_eig_impl(int n, const double *A, double *w, double *V) {
     // v = x + sign(x0) |x| e1, beta = 2 / v^T v; H x = -sign(x0) |x| e1
     v[0] = x0 + sgn(x0) * mu;
     for (int i = 1; i < m; ++i) v[i] = T[(k + 1 + i) * n + k];
-    double vtv = v[0] * v[0] + sigma;
-    const double beta = 2.0 / vtv;
+    const double beta = 2.0 / (v[0] * v[0] + sigma);
+    betas[k] = beta;
     // p = beta * T' v on the trailing block T' = T[k+1:, k+1:], of which only
     // the lower triangle is kept (rows j <= i and their transposes)
     for (int i = 0; i < m; ++i) p[i] = 0.0;
@@ -74,26 +90,23 @@ int sym_eig_impl(int n, const double *A, double *w, double *V) {
     }
     T[(k + 1) * n + k] = -sgn(x0) * mu;
     for (int i = 1; i < m; ++i) T[(k + 1 + i) * n + k] = 0.0;
-    // Q <- Q H on columns k+1..n-1
-    for (int i = 0; i < n; ++i) {
-      double acc = 0.0;
-      const double *row = &Q[i * n + (k + 1)];
-      for (int j = 0; j < m; ++j) acc += row[j] * v[j];
-      acc *= beta;
-      double *roww = &Q[i * n + (k + 1)];
-      for (int j = 0; j < m; ++j) roww[j] -= acc * v[j];
-    }
   }
-// ---- implicit symmetric QR with Wilkinson shift on the band -------------
-  // d: diagonal, e[i]: entry (i+1, i); the eigenvector estimates are the rows
-  // of Z = Q^T, so that a rotation in the (k, k+1) plane updates two
-  // contiguous rows.
-  std::vector<double> d(n), e(n, 0.0), Z((size_t)n * n);
+
+  // ---- implicit symmetric QR with Wilkinson shift on the band -------------
+  // d: diagonal, e[i]: entry (i+1, i).  The rotations act on (d, e) here and
+  // are recorded; the eigenvector estimates, the rows of Z = G ... G Q^T, are
+  // formed below.
+  std::vector<double> d(n), e(n, 0.0);
   for (int i = 0; i < n; ++i) {
     d[i] = T[i * n + i];
     if (i + 1 < n) e[i] = T[(i + 1) * n + i];
-    for (int j = 0; j < n; ++j) Z[(size_t)i * n + j] = Q[(size_t)j * n + i];
   }
+  struct Rot {
+    int k;
+    double c, s;
+  };
+  std::vector<Rot> rots;
+  rots.reserve((size_t)2 * n * n);
   const double eps = 2.220446049250313e-16;
   int hi = n - 1;
   int iter = 0;
@@ -133,19 +146,57 @@ int sym_eig_impl(int n, const double *A, double *w, double *V) {
         bulge = s * e[k + 1];  // new entry (k, k+2)
         e[k + 1] *= c;
       }
-      // Q <- Q G^T, i.e. rows k, k+1 of Z
-      double *zk = &Z[(size_t)k * n], *zk1 = &Z[(size_t)(k + 1) * n];
-      for (int i = 0; i < n; ++i) {
-        const double a = zk[i], bb = zk1[i];
-        zk[i] = c * a + s * bb;
-        zk1[i] = -s * a + c * bb;
-      }
+      rots.push_back(Rot{k, c, s});
       if (k + 1 < hi) {
         x = e[k];
         z = bulge;
       }
     }
   }
+
+  // ---- eigenvectors: Z = G_last ... G_1 H_{n-3} ... H_0 I ------------------
+  // The columns of Z are independent, so each thread takes a block of them
+  // (row-major n x JB in its own buffer, in L1/L2 throughout), applies the
+  // reflectors in order and then the recorded rotations.
+  std::vector<double> Z((size_t)n * n);
+  auto vec_block = [&](int j0, int j1) {
+    const int JB = j1 - j0;
+    std::vector<double> B((size_t)n * JB, 0.0), acc(JB);
+    for (int j = 0; j < JB; ++j) B[(size_t)(j0 + j) * JB + j] = 1.0;
+    for (int k = 0; k + 2 < n; ++k) {
+      const double beta = betas[k];
+      if (beta == 0.0) continue;
+      const int m = n - k - 1;
+      const double *v = &R[(size_t)k * n];
+      for (int j = 0; j < JB; ++j) acc[j] = 0.0;
+      for (int i = 0; i < m; ++i) {
+        const double *row = &B[(size_t)(k + 1 + i) * JB];
+        const double vi = v[i];
+        for (int j = 0; j < JB; ++j) acc[j] += vi * row[j];
+      }
+      for (int j = 0; j < JB; ++j) acc[j] *= beta;
+      for (int i = 0; i < m; ++i) {
+        double *row = &B[(size_t)(k + 1 + i) * JB];
+        const double vi = v[i];
+        for (int j = 0; j < JB; ++j) row[j] -= vi * acc[j];
+      }
+    }
+    for (const Rot &g : rots) {
+      double *zk = &B[(size_t)g.k * JB], *zk1 = &B[(size_t)(g.k + 1) * JB];
+      for (int j = 0; j < JB; ++j) {
+        const double a = zk[j], bb = zk1[j];
+        zk[j] = g.c * a + g.s * bb;
+        zk1[j] = -g.s * a + g.c * bb;
+      }
+    }
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < JB; ++j) Z[(size_t)i * n + j0 + j] = B[(size_t)i * JB + j];
+  };
+  const int nt = vec_threads(n);
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(vec_block, t * n / nt, (t + 1) * n / nt);
+  vec_block(0, n / nt);
+  for (auto &th : pool) th.join();
 
   // ---- sort ascending -------------------------------------------------------
   std::vector<int> ord(n);
