@@ -380,9 +380,12 @@ nkf_status validate(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, co
 }
 
 // ---- host FP64 landmark factor ----------------------------------------------
+nkf_status factor_from_gram(nkf_ctx *ctx, int r, std::vector<double> &A, double tau, double *Q, double *alpha,
+                            double *F, int *r_eff);
+
 nkf_status factor(nkf_ctx *ctx, int r, int D, const double *c, double sigma_r, double tau, double *Q,
                   double *alpha, double *F, int *r_eff) {
-  std::vector<double> A((size_t)r * r), Qv((size_t)r * r), al(r);
+  std::vector<double> A((size_t)r * r);
   const double inv = isinf(sigma_r) ? 0.0 : 1.0 / (2.0 * sigma_r * sigma_r);
   for (int i = 0; i < r; ++i) {
     A[i * r + i] = 1.0;
@@ -403,6 +406,13 @@ nkf_status factor(nkf_ctx *ctx, int r, int D, const double *c, double sigma_r, d
       A[i * r + j] = A[j * r + i] = exp(-d2 * inv);
     }
   }
+  return factor_from_gram(ctx, r, A, tau, Q, alpha, F, r_eff);
+}
+
+// The eigendecomposition of A (Eq. (eigA)) and F = Q_keep diag(alpha_keep^{-1/2}).
+nkf_status factor_from_gram(nkf_ctx *ctx, int r, std::vector<double> &A, double tau, double *Q, double *alpha,
+                            double *F, int *r_eff) {
+  std::vector<double> Qv((size_t)r * r), al(r);
   if (sym_eig(r, A.data(), al.data(), Qv.data()) != 0)
     return fail(ctx, NKF_ERR_NUMERICAL, "eigendecomposition of A did not converge");
   const double amax = al[r - 1];
@@ -1060,33 +1070,36 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
   if (!out) return fail(ctx, NKF_ERR_INVALID_ARG, "out is NULL");
   const int r = prm->r;
   // workspace: k-means buffers and landmark state first, forward buffers sized for r_eff = r
-  auto carve_all = [&](Carve &cv, KmBufs &kb, float *&c, int64_t *&idx, double *&Fd, FwdBufs &fb) {
+  auto carve_all = [&](Carve &cv, KmBufs &kb, float *&c, int64_t *&idx, double *&Fd, double *&Ad, FwdBufs &fb) {
     carve_km(cv, rs, r, kb);
     c = cv.take<float>((size_t)r * rs.D);
     idx = cv.take<int64_t>(r);
     Fd = cv.take<double>((size_t)r * r);
+    Ad = cv.take<double>((size_t)r * r);
     carve_fwd(cv, rs, r, fb, kMaxLandmarks, fwd_u64(rs, prm->prec), ctx->num_cu, ctx->stats, fwd_wk_r(rs, prm, r));
   };
   KmBufs kb;
   FwdBufs fb;
   float *c;
   int64_t *idx;
-  double *Fd;
+  double *Fd, *Ad;
   Carve dry{nullptr};
-  carve_all(dry, kb, c, idx, Fd, fb);
+  carve_all(dry, kb, c, idx, Fd, Ad, fb);
   if ((st = ensure_workspace(ctx, dry.off)) != NKF_OK) return st;
   const size_t host_bytes = sizeof(double) * ((size_t)r * rs.D + 3 * (size_t)r * r + r) + sizeof(float) * r * rs.D;
   if ((st = ensure_pinned(ctx, 64 * 1024 + host_bytes)) != NKF_OK) return st;
   Carve cv{ctx->ws};
-  carve_all(cv, kb, c, idx, Fd, fb);
+  carve_all(cv, kb, c, idx, Fd, Ad, fb);
 
   if ((st = run_seed(ctx, rs, prm, c, idx)) != NKF_OK) return st;
   if ((st = run_lloyd(ctx, rs, r, c, prm->kmeans_iters, nullptr, kb, prm->prec)) != NKF_OK) return st;
-  // the one host round trip: landmarks to the host for the FP64 factor
+  // the one host round trip: the landmark Gram matrix A (formed on the
+  // device in FP64) to the host for the FP64 eigendecomposition
   int r_eff = 0;
   {
-    float *c_host = reinterpret_cast<float *>(ctx->pinned);
-    HIP_TRY(ctx, hipMemcpyAsync(c_host, c, sizeof(float) * r * rs.D, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, launch_landmark_gram(c, r, rs.D, prm->sigma_r, Ad, ctx->stream));
+    double *A_host = reinterpret_cast<double *>(ctx->pinned);
+    HIP_TRY(ctx, hipMemcpyAsync(A_host, Ad, sizeof(double) * r * r, hipMemcpyDeviceToHost, ctx->stream));
     if (!ctx->copy_done) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->copy_done, hipEventDisableTiming));
     HIP_TRY(ctx, hipEventRecord(ctx->copy_done, ctx->stream));
     // landmark-independent work runs on the device while the host factors A
@@ -1096,12 +1109,10 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
     // the factor stage is the host's work once the landmarks have arrived, so
     // timing it needs no extra synchronisation
     HostTimer ht(ctx, NKF_STAGE_FACTOR);
-    std::vector<double> cd((size_t)r * rs.D);
-    for (size_t i = 0; i < cd.size(); ++i) cd[i] = c_host[i];
-    double *F_host = reinterpret_cast<double *>(ctx->pinned + ((sizeof(float) * r * rs.D + 255) & ~(size_t)255));
+    std::vector<double> A(A_host, A_host + (size_t)r * r);
+    double *F_host = reinterpret_cast<double *>(ctx->pinned + ((sizeof(double) * r * r + 255) & ~(size_t)255));
     std::vector<double> Fr((size_t)r * r), al(r);
-    if ((st = factor(ctx, r, rs.D, cd.data(), prm->sigma_r, prm->eig_rel_tol, nullptr, al.data(), Fr.data(),
-                     &r_eff)) != NKF_OK)
+    if ((st = factor_from_gram(ctx, r, A, prm->eig_rel_tol, nullptr, al.data(), Fr.data(), &r_eff)) != NKF_OK)
       return st;
     record_stats(ctx, rs, prm, r_eff, al[r - 1], al[r - r_eff]);
     // pack F [r, r_eff]

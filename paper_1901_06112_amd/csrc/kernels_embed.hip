@@ -398,6 +398,41 @@ size_t center_scratch_words(int C) { return C <= 4 ? (size_t)kMmReps * kMmSlot :
 
 // eta_hat statistics: st[0] = pixels that took the eta_hat <= 0 / non-finite
 // guard, st[1] = ord_encode(min eta_hat over the other pixels).
+// Landmark Gram matrix A[i][j] = k(c_i, c_j) (Eq. (defA)) in FP64 on the
+// device, so that only A crosses to the host for the eigendecomposition:
+// one thread per entry (i, j), squared distance from the FP32 landmarks in
+// four partial sums over d mod 4 added in a fixed order.
+__global__ __launch_bounds__(256) void gram_kernel(const float *__restrict__ c, int r, int D, double inv2s2,
+                                                   double *__restrict__ A) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= r * r) return;
+  const int i = e / r, j = e - (e / r) * r;
+  if (i == j) {
+    A[e] = 1.0;
+    return;
+  }
+  const float *ci = c + (size_t)i * D, *cj = c + (size_t)j * D;
+  double d4[4] = {0.0, 0.0, 0.0, 0.0};
+  int k = 0;
+  for (; k + 4 <= D; k += 4)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double t = (double)ci[k + q] - (double)cj[k + q];
+      d4[q] = fma(t, t, d4[q]);
+    }
+  for (; k < D; ++k) {
+    const double t = (double)ci[k] - (double)cj[k];
+    d4[0] = fma(t, t, d4[0]);
+  }
+  A[e] = exp_neg64(((d4[0] + d4[1]) + (d4[2] + d4[3])) * inv2s2);
+}
+
+hipError_t launch_landmark_gram(const float *c, int r, int D, double sigma_r, double *A, hipStream_t s) {
+  const double inv = isinf(sigma_r) ? 0.0 : 1.0 / (2.0 * sigma_r * sigma_r);
+  hipLaunchKernelGGL(gram_kernel, dim3((r * r + 255) / 256), dim3(256), 0, s, c, r, D, inv, A);
+  return hipGetLastError();
+}
+
 __global__ void eta_stats_init_kernel(unsigned *st) {
   if (threadIdx.x == 0) {
     st[0] = 0u;

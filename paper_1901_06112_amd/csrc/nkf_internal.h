@@ -75,6 +75,8 @@ hipError_t launch_center(const float *f, int64_t N, int C, double center, float 
 // eta_hat <= 0 / non-finite guard, and the order-preserving code of the
 // smallest positive eta_hat (decoded by eta_stats_min; NAN if none).
 hipError_t launch_eta_stats(const float *eta, int64_t N, unsigned *st, hipStream_t s);
+// A [r][r] FP64 = exp(-|c_i - c_j|^2 / (2 sigma_r^2)) from FP32 landmarks c [r][D].
+hipError_t launch_landmark_gram(const float *c, int r, int D, double sigma_r, double *A, hipStream_t s);
 double eta_stats_min(unsigned code);
 // u[k][x] = sum_j F[j][k] exp(-|p(x) - c_j|^2 / (2 sigma_r^2)), planar [r_eff][N] float32.
 // ct64 is scratch of embed_scratch_doubles(g, r) doubles (transposed FP64 landmarks).
