@@ -222,6 +222,49 @@ __device__ __forceinline__ void stage_raw(const MArgs &a, const TileInfo &ti, fl
   }
 }
 
+// Register prefetch of an explicit / self guide tile in one batch of float4
+// groups (D % 4 == 0, 16-byte aligned rows, TP D <= 32 BT): the k-means loop
+// issues the loads of its next tile before processing the current one, so
+// they are in flight during its products and sums.
+template <int TP, int BT>
+struct TilePrefetch {
+  float4 v[8];
+  static __host__ __device__ __forceinline__ bool usable(const MArgs &a) {
+    const float *base = a.g.kind == GUIDE_EXPLICIT ? a.g.p : a.g.f;
+    return a.g.kind != GUIDE_PATCH && (a.g.D & 3) == 0 && (reinterpret_cast<uintptr_t>(base) & 15) == 0 &&
+           TP * a.g.D <= 32 * BT;
+  }
+  __device__ __forceinline__ void load(const MArgs &a, const TileInfo &ti) {
+    const int D = a.g.D;
+    const float *src = (a.g.kind == GUIDE_EXPLICIT ? a.g.p : a.g.f) + ti.x0 * D;
+    const int nval = ti.nvalid * D;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = 4 * (int)threadIdx.x + k * 4 * BT;
+      v[k] = e < nval ? *reinterpret_cast<const float4 *>(src + e) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  __device__ __forceinline__ void store(const MArgs &a, const TileInfo &ti, float *raw, const float *mus) const {
+    const int D = a.g.D, nval = ti.nvalid * D, ntot = TP * D;
+    const int di = 4 * BT / D, dd = 4 * BT - di * D;
+    int i = (4 * (int)threadIdx.x) / D, d = 4 * (int)threadIdx.x - i * D;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = 4 * (int)threadIdx.x + k * 4 * BT;
+      if (e >= ntot) break;
+      float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < nval) o = make_float4(v[k].x - mus[d], v[k].y - mus[d + 1], v[k].z - mus[d + 2], v[k].w - mus[d + 3]);
+      *reinterpret_cast<float4 *>(raw + i * a.pxstride + d) = o;
+      i += di;
+      d += dd;
+      if (d >= D) {
+        d -= D;
+        ++i;
+      }
+    }
+  }
+};
+
 // The block's copy of the centring offsets sits at the end of the raw area.
 __device__ __forceinline__ float *raw_mu(const MArgs &a, float *raw) { return raw + a.raw_floats - a.muf; }
 __device__ __forceinline__ void load_mu(const MArgs &a, float *mus, int BT) {
@@ -410,7 +453,7 @@ struct Split<2> {
 // by the waves for the whole launch: wave w owns the dimension tiles
 // w + NW m (m < MDT) for all NT cluster tiles; dimension D carries the count
 // (value 1 for every pixel).
-template <int PREC, int NT, int BT, int MDT>
+template <int PREC, int NT, int BT, int MDT, bool PF>
 __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
   using T = typename Half<PREC>::T;
   using V = typename Half<PREC>::V;
@@ -467,11 +510,19 @@ __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
 #pragma unroll
     for (int t = 0; t < NT; ++t) sacc_r[m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+  // PF: the host found TilePrefetch usable for this guide
+  constexpr bool pf = PF;
+  TilePrefetch<TP, BT> pre;
+  if (pf && (int)blockIdx.x < a.ntiles) pre.load(a, tile_info<TP>(a, blockIdx.x));
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileInfo ti = tile_info<TP>(a, t);
     __syncthreads();
-    stage_raw<TP, BT>(a, ti, raw, raw_mu(a, raw));
+    if (pf)
+      pre.store(a, ti, raw, raw_mu(a, raw));
+    else
+      stage_raw<TP, BT>(a, ti, raw, raw_mu(a, raw));
     __syncthreads();
+    if (pf && t + (int)gridDim.x < a.ntiles) pre.load(a, tile_info<TP>(a, t + gridDim.x));
     {
       floatx4 acc[NT];
       float s2;
@@ -834,15 +885,24 @@ int plan_embed(const Guide &g, int r, size_t *lds) {
   return 0;
 }
 
-template <int PREC, int NT, int BT, int MDT>
-hipError_t launch_lloyd_k(const MArgs &a, size_t lds, hipStream_t s, int *nblocks) {
-  hipError_t e = set_lds(lloyd_mfma_kernel<PREC, NT, BT, MDT>, lds);
+template <int PREC, int NT, int BT, int MDT, bool PF>
+hipError_t launch_lloyd_kp(const MArgs &a, size_t lds, hipStream_t s, int *nblocks) {
+  hipError_t e = set_lds(lloyd_mfma_kernel<PREC, NT, BT, MDT, PF>, lds);
   if (e != hipSuccess) return e;
   int nb = a.ntiles < kMaxBlocks ? a.ntiles : kMaxBlocks;
   if (nb < 1) nb = 1;
   *nblocks = nb;
-  hipLaunchKernelGGL((lloyd_mfma_kernel<PREC, NT, BT, MDT>), dim3(nb), dim3(BT), lds, s, a);
+  hipLaunchKernelGGL((lloyd_mfma_kernel<PREC, NT, BT, MDT, PF>), dim3(nb), dim3(BT), lds, s, a);
   return hipGetLastError();
+}
+
+// The tile prefetch (registers) only for the 8-wave GEMM-sum kernels of wide
+// explicit / self guides; patch guides stage their tiles directly.
+template <int PREC, int NT, int BT, int MDT>
+hipError_t launch_lloyd_k(const MArgs &a, size_t lds, hipStream_t s, int *nblocks) {
+  if constexpr (BT == 512 && (MDT == 1 ? NT <= 8 : MDT == 2 && NT <= 4))  // these fit 256 VGPRs
+    if (TilePrefetch<16 * BT / 64, BT>::usable(a)) return launch_lloyd_kp<PREC, NT, BT, MDT, true>(a, lds, s, nblocks);
+  return launch_lloyd_kp<PREC, NT, BT, MDT, false>(a, lds, s, nblocks);
 }
 
 template <int PREC, int NT>
