@@ -265,6 +265,47 @@ struct TilePrefetch {
   }
 };
 
+// The same for patch guides with C <= 4 whose tile window (2pr+1 rows of
+// TP + 2pr columns) has at most 2 BT columns: each thread holds the centred
+// C values of up to two (patch row, column) pairs (zeros past the padded
+// image edge, as stage_raw writes them).
+template <int TP, int BT>
+struct PatchPrefetch {
+  float v[2][4];
+  static __host__ __device__ __forceinline__ bool usable(const MArgs &a) {
+    return a.g.kind == GUIDE_PATCH && a.g.C <= 4 && (2 * a.g.pr + 1) * (TP + 2 * a.g.pr) <= 2 * BT;
+  }
+  __device__ __forceinline__ void load(const MArgs &a, const TileInfo &ti, const float *mus) {
+    const Guide &g = a.g;
+    const int C = g.C, TPR = TP + 2 * g.pr, npair = (2 * g.pr + 1) * TPR;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int idx = (int)threadIdx.x + k * BT;
+      const int q = idx / TPR, j = idx - q * TPR;
+      const int xs = ti.col0 + j - g.pr;
+      const bool ok = idx < npair && xs < g.W + g.pr;  // columns past the padded edge are never read
+      const float *src =
+          g.f + ((int64_t)sym_index(ok ? ti.y + q - g.pr : 0, g.H) * g.W + sym_index(ok ? xs : 0, g.W)) * C;
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) v[k][ch] = ok && ch < C ? src[ch] - mus[ch] : 0.0f;
+    }
+  }
+  __device__ __forceinline__ void store(const MArgs &a, float *raw) const {
+    const Guide &g = a.g;
+    const int C = g.C, TPR = TP + 2 * g.pr, npair = (2 * g.pr + 1) * TPR;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int idx = (int)threadIdx.x + k * BT;
+      if (idx >= npair) break;
+      const int q = idx / TPR, j = idx - q * TPR;
+      float *dst = raw + q * a.rowstride + j * C;
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch)
+        if (ch < C) dst[ch] = v[k][ch];
+    }
+  }
+};
+
 // The block's copy of the centring offsets sits at the end of the raw area.
 __device__ __forceinline__ float *raw_mu(const MArgs &a, float *raw) { return raw + a.raw_floats - a.muf; }
 __device__ __forceinline__ void load_mu(const MArgs &a, float *mus, int BT) {
@@ -453,7 +494,7 @@ struct Split<2> {
 // by the waves for the whole launch: wave w owns the dimension tiles
 // w + NW m (m < MDT) for all NT cluster tiles; dimension D carries the count
 // (value 1 for every pixel).
-template <int PREC, int NT, int BT, int MDT, bool PF>
+template <int PREC, int NT, int BT, int MDT, int PF>
 __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
   using T = typename Half<PREC>::T;
   using V = typename Half<PREC>::V;
@@ -510,19 +551,29 @@ __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
 #pragma unroll
     for (int t = 0; t < NT; ++t) sacc_r[m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  // PF: the host found TilePrefetch usable for this guide
-  constexpr bool pf = PF;
+  // PF (chosen by the host): 1 = TilePrefetch, 2 = PatchPrefetch, 0 = none;
+  // the offsets in LDS are complete after the barrier at the loop head
   TilePrefetch<TP, BT> pre;
-  if (pf && (int)blockIdx.x < a.ntiles) pre.load(a, tile_info<TP>(a, blockIdx.x));
+  PatchPrefetch<TP, BT> ppre;
+  if constexpr (PF == 2) __syncthreads();
+  if ((int)blockIdx.x < a.ntiles) {
+    if constexpr (PF == 1) pre.load(a, tile_info<TP>(a, blockIdx.x));
+    if constexpr (PF == 2) ppre.load(a, tile_info<TP>(a, blockIdx.x), raw_mu(a, raw));
+  }
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileInfo ti = tile_info<TP>(a, t);
     __syncthreads();
-    if (pf)
+    if constexpr (PF == 1)
       pre.store(a, ti, raw, raw_mu(a, raw));
+    else if constexpr (PF == 2)
+      ppre.store(a, raw);
     else
       stage_raw<TP, BT>(a, ti, raw, raw_mu(a, raw));
     __syncthreads();
-    if (pf && t + (int)gridDim.x < a.ntiles) pre.load(a, tile_info<TP>(a, t + gridDim.x));
+    if (t + (int)gridDim.x < a.ntiles) {
+      if constexpr (PF == 1) pre.load(a, tile_info<TP>(a, t + gridDim.x));
+      if constexpr (PF == 2) ppre.load(a, tile_info<TP>(a, t + gridDim.x), raw_mu(a, raw));
+    }
     {
       floatx4 acc[NT];
       float s2;
@@ -565,10 +616,13 @@ __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
 #pragma unroll
         for (int m = 0; m < MDT; ++m) {
           if (w + NW * m >= ndt) break;
+          // v = raw value (dimension column), 1 (count column) or 0 (padding)
+          const bool dim = doff[m] >= 0;
+          const float va = doff[m] == -2 ? 1.0f : 0.0f;
+          const float *src = raw + px0 * a.pxstride + (dim ? doff[m] : 0);
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
-            const float x = raw[(px0 + j) * a.pxstride + (doff[m] >= 0 ? doff[m] : 0)];
-            const float v = doff[m] >= 0 ? x : (doff[m] == -2 ? 1.0f : 0.0f);
+            const float v = dim ? src[j * a.pxstride] : va;
             T pp[NPART];
             Split<PREC>::parts(v, pp);
 #pragma unroll
@@ -885,7 +939,7 @@ int plan_embed(const Guide &g, int r, size_t *lds) {
   return 0;
 }
 
-template <int PREC, int NT, int BT, int MDT, bool PF>
+template <int PREC, int NT, int BT, int MDT, int PF>
 hipError_t launch_lloyd_kp(const MArgs &a, size_t lds, hipStream_t s, int *nblocks) {
   hipError_t e = set_lds(lloyd_mfma_kernel<PREC, NT, BT, MDT, PF>, lds);
   if (e != hipSuccess) return e;
@@ -900,9 +954,12 @@ hipError_t launch_lloyd_kp(const MArgs &a, size_t lds, hipStream_t s, int *nbloc
 // explicit / self guides; patch guides stage their tiles directly.
 template <int PREC, int NT, int BT, int MDT>
 hipError_t launch_lloyd_k(const MArgs &a, size_t lds, hipStream_t s, int *nblocks) {
+  constexpr int TP = 16 * BT / 64;
   if constexpr (BT == 512 && (MDT == 1 ? NT <= 8 : MDT == 2 && NT <= 4))  // these fit 256 VGPRs
-    if (TilePrefetch<16 * BT / 64, BT>::usable(a)) return launch_lloyd_kp<PREC, NT, BT, MDT, true>(a, lds, s, nblocks);
-  return launch_lloyd_kp<PREC, NT, BT, MDT, false>(a, lds, s, nblocks);
+    if (TilePrefetch<TP, BT>::usable(a)) return launch_lloyd_kp<PREC, NT, BT, MDT, 1>(a, lds, s, nblocks);
+  if constexpr (BT == 512 && MDT > 0 && NT <= 8)
+    if (PatchPrefetch<TP, BT>::usable(a)) return launch_lloyd_kp<PREC, NT, BT, MDT, 2>(a, lds, s, nblocks);
+  return launch_lloyd_kp<PREC, NT, BT, MDT, 0>(a, lds, s, nblocks);
 }
 
 template <int PREC, int NT>
