@@ -602,27 +602,48 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
   }
 }
 
+// Compute units of the current device (cached per device).
+inline int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int n = 0;
+    cus[dev] = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0 ? n : 256;
+  }
+  return cus[dev];
+}
+
 // Tile geometry and launch of one kernel instantiation.
 template <int S, int NP, bool HAS_E, int RC, int MODE, int BT = kBlock, bool BOX = false>
-hipError_t launch_one(ConvArgs a, hipStream_t s, int ch_per_block, int nchunks_c, int min_blocks = 512,
-                      int *nblocks_out = nullptr) {
+hipError_t launch_one(ConvArgs a, hipStream_t s, int ch_per_block, int nchunks_c, int *nblocks_out = nullptr) {
   using K = Cfg<S, NP, HAS_E, RC, MODE, BT, BOX>;
   a.ch_per_block = ch_per_block;
   a.tiles_x = (a.W + kTW - 1) / kTW;
-  // largest chunk count (<= NCH_MAX) that still gives >= min_blocks blocks;
-  // 512-thread blocks hold a whole CU's LDS, so one block per CU fills the chip
-  if (BT == 512 && min_blocks > 256) min_blocks = 256;
-  int nch = K::NCH_MAX;
   auto blocks = [&](int n) {
     const int th = n * RC;
     return (int64_t)a.tiles_x * ((a.H + th - 1) / th) * nchunks_c;
   };
-  if (a.force_nch > 0)
-    nch = a.force_nch < K::NCH_MAX ? a.force_nch : K::NCH_MAX;
-  else
-    while (nch > 1 && blocks(nch) < min_blocks) --nch;
   // do not use more chunks than the image needs
   const int need = (a.H + RC - 1) / RC;
+  int nch = 1;
+  if (a.force_nch > 0) {
+    nch = a.force_nch < K::NCH_MAX ? a.force_nch : K::NCH_MAX;
+  } else {
+    // a block streams nch + LAG input chunks for its nch output chunks, and
+    // blocks run in rounds of one per CU (512 threads: a whole CU's LDS) or
+    // two (256 threads): take the chunk count of the fewest chunk-steps,
+    // rounds x (nch + LAG), the larger one on ties
+    const int64_t slots = (int64_t)device_cus() * (BT == 512 ? 1 : 2);
+    int64_t best = -1;
+    for (int n = 1; n <= K::NCH_MAX && n <= need; ++n) {
+      const int64_t cost = (blocks(n) + slots - 1) / slots * (n + K::LAG);
+      if (best < 0 || cost <= best) {
+        best = cost;
+        nch = n;
+      }
+    }
+  }
   if (nch > need) nch = need;
   a.nch = nch;
   a.tiles_y = (a.H + nch * RC - 1) / (nch * RC);

@@ -185,9 +185,9 @@ hipError_t launch_mode(ConvArgs a, int S, hipStream_t s, int *nblocks) {
 #define NKF_CASE(SV)                                                               \
   case SV:                                                                         \
     if constexpr (MODE == MODE_SIGS && SV > 10)                                    \
-      return launch_one<SV, 4, true, 16, MODE, 512>(a, s, 3, 1, 512, nblocks);      \
+      return launch_one<SV, 4, true, 16, MODE, 512>(a, s, 3, 1, nblocks);      \
     else                                                                           \
-      return launch_one<SV, 4, true, 32, MODE, 512>(a, s, 3, 1, 512, nblocks);
+      return launch_one<SV, 4, true, 32, MODE, 512>(a, s, 3, 1, nblocks);
     NKF_CASE(0) NKF_CASE(1) NKF_CASE(2) NKF_CASE(3) NKF_CASE(4) NKF_CASE(5) NKF_CASE(6) NKF_CASE(7)
     NKF_CASE(8) NKF_CASE(9) NKF_CASE(10) NKF_CASE(11) NKF_CASE(12) NKF_CASE(13) NKF_CASE(14)
     NKF_CASE(15) NKF_CASE(16)
