@@ -89,17 +89,30 @@ __global__ __launch_bounds__(kRBlock) void reduce_kernel(Guide g, int64_t N, con
   for (int q = 0; q < 4; ++q) racc[q] = double4_t{0.0, 0.0, 0.0, 0.0};
   double sr_acc = 0.0;
   for (int64_t base = (int64_t)blockIdx.x * kRTile; base < N; base += (int64_t)gridDim.x * kRTile) {
-    __syncthreads();
-    for (int e = tid; e < D * kRTile; e += kRBlock) {
-      const int d = e / kRTile, q = e - d * kRTile;
-      const int64_t x = base + q;
-      pt[e] = x < N ? guide_elem(g, x, d) : 0.0f;
-    }
-    for (int e = tid; e < r_eff * kRTile; e += kRBlock) {
-      const int k = e / kRTile, q = e - k * kRTile;
-      const int64_t x = base + q;
-      dus[e] = x < N ? du[(int64_t)k * N + x] : 0.0f;
-      duds[k * kRS + q] = x < N ? dud[(int64_t)k * N + x] : 0.0f;
+    // stage the tile: thread (px, kg) takes planes k = kg + 4 q of its pixel;
+    // every load is issued before the first LDS store, so a tile costs one
+    // memory latency
+    {
+      const int64_t x = base + px;
+      const bool xin = x < N;
+      float vdu[kRMaxJ], vdud[kRMaxJ];
+#pragma unroll
+      for (int q = 0; q < kRMaxJ; ++q) {
+        const int k = kg + 4 * q;
+        const bool ok = xin && k < r_eff;
+        vdu[q] = ok ? du[(int64_t)k * N + x] : 0.0f;
+        vdud[q] = ok ? dud[(int64_t)k * N + x] : 0.0f;
+      }
+      __syncthreads();
+      for (int d = kg; d < D; d += 4) pt[d * kRTile + px] = xin ? guide_elem(g, x, d) : 0.0f;
+#pragma unroll
+      for (int q = 0; q < kRMaxJ; ++q) {
+        const int k = kg + 4 * q;
+        if (k < r_eff) {
+          dus[k * kRTile + px] = vdu[q];
+          duds[k * kRS + px] = vdud[q];
+        }
+      }
     }
     __syncthreads();
     const bool valid = base + px < N;
