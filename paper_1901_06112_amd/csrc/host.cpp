@@ -473,6 +473,7 @@ struct FwdBufs {
   double *ct64;  // transposed FP64 landmarks of the FP32 embedding
   float *eta_stat;  // eta_hat for the statistics when the caller passes no eta_out
   void *wk;         // operands of the windowed MFMA form (16-bit forms, C > 3), else null
+  float *bsplit;    // cross-kernel tiles of the split 16-bit embedding (nkf_filter), else null
 };
 
 // The 16-bit forms on more than three channels evaluate the windows on MFMA
@@ -483,7 +484,7 @@ int fwd_wk_r(const Resolved &rs, const nkf_params *prm, int r) {
 }
 
 void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r, bool u64, int num_cu,
-               bool stats = false, int wk_r = 0) {
+               bool stats = false, int wk_r = 0, int split_prec = 0) {
   b.f0 = cv.take<float>(rs.C);
   b.mm = cv.take<unsigned>(center_scratch_words(rs.C));
   b.u = u64 ? nullptr : cv.take<float>((size_t)r_eff * rs.N);
@@ -498,6 +499,7 @@ void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r, bool
   b.ct64 = cv.take<double>(embed_scratch_doubles(rs.g, r));
   b.eta_stat = cv.take<float>(stats ? rs.N : 1);
   b.wk = wk_r ? static_cast<void *>(cv.take<unsigned char>(wk_scratch_bytes(rs.H, rs.W, rs.C, wk_r))) : nullptr;
+  b.bsplit = split_prec ? cv.take<float>(embed_split_floats(rs.g, r_eff, split_prec)) : nullptr;
 }
 
 // The landmark-independent part of the forward: the centring offsets f0,
@@ -531,16 +533,20 @@ nkf_status run_pre(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, cons
 // pre_done: run_pre has been enqueued already
 // stats_ok: a forward entry point whose statistics are recorded (not the
 // backward's recompute, nor the allocation-free call)
+// embed_b_done: the cross-kernel tiles of the split 16-bit embedding are in
+// b.bsplit already (enqueued before the landmark factor), only the mix is left
 nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, const float *c, const double *F,
                    int r_eff, float *out, float *eta_out, const FwdBufs &b, bool conv = true, bool pre_done = false,
-                   bool stats_ok = false) {
+                   bool stats_ok = false, bool embed_b_done = false) {
   {
     StageTimer tm(ctx, NKF_STAGE_EMBED);
     if (!pre_done) {
       nkf_status st = run_pre(ctx, rs, prm, b);
       if (st != NKF_OK) return st;
     }
-    if (use_mfma_distance(rs.g, prm->prec)) {
+    if (use_mfma_distance(rs.g, prm->prec) && embed_b_done && b.bsplit) {
+      HIP_TRY(ctx, launch_embed_mfma_mix(rs.g, prm->r, F, b.F32, r_eff, prm->prec, b.u, b.bsplit, ctx->stream));
+    } else if (use_mfma_distance(rs.g, prm->prec)) {
       HIP_TRY(ctx, launch_embed_mfma(rs.g, c, prm->r, b.mu, F, b.F32, r_eff, prm->sigma_r, prm->prec, b.u,
                                      b.lm, ctx->stream));
     } else {
@@ -1076,7 +1082,9 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
     idx = cv.take<int64_t>(r);
     Fd = cv.take<double>((size_t)r * r);
     Ad = cv.take<double>((size_t)r * r);
-    carve_fwd(cv, rs, r, fb, kMaxLandmarks, fwd_u64(rs, prm->prec), ctx->num_cu, ctx->stats, fwd_wk_r(rs, prm, r));
+    // the 16-bit embedding runs split: its cross-kernel part overlaps the host factor
+    carve_fwd(cv, rs, r, fb, kMaxLandmarks, fwd_u64(rs, prm->prec), ctx->num_cu, ctx->stats, fwd_wk_r(rs, prm, r),
+              use_mfma_distance(rs.g, prm->prec) ? prm->prec : 0);
   };
   KmBufs kb;
   FwdBufs fb;
@@ -1105,6 +1113,8 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
     // landmark-independent work runs on the device while the host factors A
     const bool mean_ready = prm->kmeans_iters > 0 && use_mfma_distance(rs.g, prm->prec);
     if ((st = run_pre(ctx, rs, prm, fb, mean_ready ? kb.mu : nullptr)) != NKF_OK) return st;
+    if (fb.bsplit)
+      HIP_TRY(ctx, launch_embed_mfma_b(rs.g, c, r, fb.mu, prm->sigma_r, prm->prec, fb.bsplit, fb.lm, ctx->stream));
     HIP_TRY(ctx, hipEventSynchronize(ctx->copy_done));
     // the factor stage is the host's work once the landmarks have arrived, so
     // timing it needs no extra synchronisation
@@ -1122,7 +1132,9 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
     if ((st = pinned_release(ctx)) != NKF_OK) return st;
   }
   if (r_eff_out) *r_eff_out = r_eff;
-  if ((st = run_fwd(ctx, rs, prm, c, Fd, r_eff, out, eta_out, fb, true, true, true)) != NKF_OK) return st;
+  if ((st = run_fwd(ctx, rs, prm, c, Fd, r_eff, out, eta_out, fb, true, true, true, fb.bsplit != nullptr)) !=
+      NKF_OK)
+    return st;
   return log_stats(ctx, "filter", rs, prm);
 }
 

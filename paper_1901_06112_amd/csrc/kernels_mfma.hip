@@ -100,6 +100,7 @@ struct MArgs {
   int r_eff, RE;     // RE = r_eff rounded up to 16
   float inv2s2;
   float *u;          // [r_eff][N]
+  float *bbuf;       // [ntiles][TP][RP] cross-kernel tiles of the split embedding
 };
 
 __device__ __forceinline__ float mu_of(const MArgs &a, int d) {
@@ -690,7 +691,10 @@ __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
 // ---- embedding --------------------------------------------------------------
 // MAXT2: output tiles (16 planes of u) per wave.  The wave's rows of F^T stay
 // in registers when they fit (FREG), else they are read from memory.
-template <int PREC, int NT, int BT, int MAXT2>
+// EM: 0 = the whole embedding; 1 = the cross-kernel tiles only, written to
+// bbuf (they need the landmarks but not F, so they can run while the host
+// decomposes A); 2 = the mix only, from the tiles in bbuf.
+template <int PREC, int NT, int BT, int MAXT2, int EM = 0>
 __global__ __launch_bounds__(BT) void embed_mfma_kernel(MArgs a) {
   using T = typename Half<PREC>::T;
   constexpr int NW = BT / 64, TP = 16 * NW;
@@ -700,7 +704,8 @@ __global__ __launch_bounds__(BT) void embed_mfma_kernel(MArgs a) {
   T *ct = reinterpret_cast<T *>(smem_raw);                                    // [RP][DS]
   T *ct_lo = ct + (size_t)a.RP * a.DS;                                        // [RP][DS]
   float *raw = reinterpret_cast<float *>(ct_lo + (size_t)a.RP * a.DS);        // [raw_floats + 8]
-  float *bs = raw + a.raw_floats + 8;                                         // [TP][RP + 4]
+  // [TP][RP + 4]; the mix-only form keeps nothing else in LDS
+  float *bs = EM == 2 ? reinterpret_cast<float *>(smem_raw) : raw + a.raw_floats + 8;
   float *cn2 = bs + TP * (a.RP + 4);                                          // [RP]
   int *tab_off = reinterpret_cast<int *>(cn2 + a.RP);                         // [kMaxChunks]
   int *tab_nv = tab_off + kMaxChunks;                                         // [kMaxChunks]
@@ -710,9 +715,11 @@ __global__ __launch_bounds__(BT) void embed_mfma_kernel(MArgs a) {
   // col) and the mix reads (rows col, columns 4 s + rq) hit distinct banks
   const int BS = a.RP + 4;
 
-  load_landmarks(a, ct, cn2, BT, ct_lo);
-  build_tables(a, tab_off, tab_nv, nullptr, BT);
-  load_mu(a, raw_mu(a, raw), BT);
+  if constexpr (EM != 2) {
+    load_landmarks(a, ct, cn2, BT, ct_lo);
+    build_tables(a, tab_off, tab_nv, nullptr, BT);
+    load_mu(a, raw_mu(a, raw), BT);
+  }
   // mix operand A = F^T: A[k'][j] = F[j][k']; lane (col, rq) takes
   // A[16 t2 + col][4 s + rq] for the wave's tiles t2 = w + NW m
   auto fval = [&](int m, int s) {
@@ -720,7 +727,7 @@ __global__ __launch_bounds__(BT) void embed_mfma_kernel(MArgs a) {
     return (kk < a.r_eff && j < a.r) ? a.F32[j * a.r_eff + kk] : 0.0f;
   };
   float fa[FREG ? MAXT2 : 1][FREG ? KS : 1];
-  if constexpr (FREG) {
+  if constexpr (FREG && EM != 1) {
 #pragma unroll
     for (int m = 0; m < MAXT2; ++m)
 #pragma unroll
@@ -728,24 +735,42 @@ __global__ __launch_bounds__(BT) void embed_mfma_kernel(MArgs a) {
   }
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileInfo ti = tile_info<TP>(a, t);
+    float4 *tile_b = reinterpret_cast<float4 *>(a.bbuf + (size_t)t * TP * a.RP);
     __syncthreads();
-    stage_raw<TP, BT>(a, ti, raw, raw_mu(a, raw));
-    __syncthreads();
-    floatx4 acc[NT];
-    float s2;
-    tile_products<PREC, NT, true, true>(a, raw, tab_off, tab_nv, ct, acc, s2, ct_lo);
+    if constexpr (EM == 2) {
+      for (int e = tid; e < TP * a.RP / 4; e += BT) {
+        const int px = 4 * e / a.RP, k = 4 * e - px * a.RP;
+        *reinterpret_cast<float4 *>(&bs[px * BS + k]) = tile_b[e];
+      }
+      __syncthreads();
+    } else {
+      stage_raw<TP, BT>(a, ti, raw, raw_mu(a, raw));
+      __syncthreads();
+      floatx4 acc[NT];
+      float s2;
+      tile_products<PREC, NT, true, true>(a, raw, tab_off, tab_nv, ct, acc, s2, ct_lo);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int pxl = 16 * w + 4 * rq + i;
-      const float n2 = __shfl(s2, 4 * rq + i, 64);  // lane 4 rq + i holds pixel 16w + 4 rq + i
+      for (int i = 0; i < 4; ++i) {
+        const int pxl = 16 * w + 4 * rq + i;
+        const float n2 = __shfl(s2, 4 * rq + i, 64);  // lane 4 rq + i holds pixel 16w + 4 rq + i
 #pragma unroll
-      for (int tt = 0; tt < NT; ++tt) {
-        const int k = 16 * tt + col;
-        const float d2 = fmaxf(n2 + cn2[k] - 2.0f * acc[tt][i], 0.0f);
-        bs[pxl * BS + k] = k < a.r ? exp2f(-d2 * a.inv2s2 * 1.4426950408889634f) : 0.0f;
+        for (int tt = 0; tt < NT; ++tt) {
+          const int k = 16 * tt + col;
+          const float d2 = fmaxf(n2 + cn2[k] - 2.0f * acc[tt][i], 0.0f);
+          bs[pxl * BS + k] = k < a.r ? exp2f(-d2 * a.inv2s2 * 1.4426950408889634f) : 0.0f;
+        }
+      }
+      __syncthreads();
+      if constexpr (EM == 1) {
+        // (bs is only 4-byte aligned here: scalar LDS reads)
+        for (int e = tid; e < TP * a.RP / 4; e += BT) {
+          const int px = 4 * e / a.RP, k = 4 * e - px * a.RP;
+          const float *src = &bs[px * BS + k];
+          tile_b[e] = make_float4(src[0], src[1], src[2], src[3]);
+        }
+        continue;
       }
     }
-    __syncthreads();
     // U[k'][px] = sum_j F[j][k'] b[px][j]: A = F^T, B = b^T (LDS)
 #pragma unroll
     for (int m = 0; m < MAXT2; ++m) {
@@ -777,12 +802,10 @@ __global__ __launch_bounds__(BT) void embed_mfma_kernel(MArgs a) {
 
 // ---- centring offsets -------------------------------------------------------
 // mu[m] = mean over the pixels of guide column m (m < D; for patch guides
-// m < C: a patch dimension takes its channel's mean).  Block b sums a
-// contiguous pixel range in FP64 with lanes (m, ln); the block partials are
-// then added in block order, so the result is deterministic.
-// Guide mean: per-block FP64 partial sums over a contiguous pixel range (eight
-// independent accumulators per thread keep eight loads in flight), then one
-// block per dimension sums the partials in a fixed order.
+// m < C: a patch dimension takes its channel's mean).  Per-block FP64 partial
+// sums over a contiguous pixel range (eight independent accumulators per
+// thread keep eight loads in flight), then one block per dimension sums the
+// partials in a fixed order, so the result is deterministic.
 __global__ __launch_bounds__(256) void mean_partial_kernel(Guide g, int64_t N, int M, double *part) {
   __shared__ double red[256];
   const int tid = threadIdx.x;
@@ -1004,17 +1027,22 @@ hipError_t launch_lloyd_p(const Guide &g, const float *c, int r, const float *mu
   return launch_lloyd_nt<PREC, 16>(a, pl, s, nblocks);
 }
 
-template <int PREC, int NT, int BT>
+template <int PREC, int NT, int BT, int EM>
 hipError_t launch_embed_nt(const MArgs &a, size_t lds, hipStream_t s) {
   constexpr int NW = BT / 64;
   const int per_wave = (a.RE / 16 + NW - 1) / NW;
   hipError_t e;
   int nb = a.ntiles < kEmbedBlocks ? a.ntiles : kEmbedBlocks;
   if (nb < 1) nb = 1;
+  if constexpr (EM == 1) {
+    if ((e = set_lds(embed_mfma_kernel<PREC, NT, BT, 1, 1>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL((embed_mfma_kernel<PREC, NT, BT, 1, 1>), dim3(nb), dim3(BT), lds, s, a);
+    return hipGetLastError();
+  }
 #define NKF_EMBED_CASE(M)                                                                         \
   if (per_wave <= M) {                                                                            \
-    if ((e = set_lds(embed_mfma_kernel<PREC, NT, BT, M>, lds)) != hipSuccess) return e;           \
-    hipLaunchKernelGGL((embed_mfma_kernel<PREC, NT, BT, M>), dim3(nb), dim3(BT), lds, s, a); \
+    if ((e = set_lds(embed_mfma_kernel<PREC, NT, BT, M, EM>, lds)) != hipSuccess) return e;       \
+    hipLaunchKernelGGL((embed_mfma_kernel<PREC, NT, BT, M, EM>), dim3(nb), dim3(BT), lds, s, a); \
     return hipGetLastError();                                                                     \
   }
   NKF_EMBED_CASE(1)
@@ -1024,11 +1052,11 @@ hipError_t launch_embed_nt(const MArgs &a, size_t lds, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-template <int PREC, int BT>
+template <int PREC, int BT, int EM = 0>
 hipError_t launch_embed_bt(const MArgs &a, size_t lds, hipStream_t s) {
-  if (a.RP == 64) return launch_embed_nt<PREC, 4, BT>(a, lds, s);
-  if (a.RP == 128) return launch_embed_nt<PREC, 8, BT>(a, lds, s);
-  return launch_embed_nt<PREC, 16, BT>(a, lds, s);
+  if (a.RP == 64) return launch_embed_nt<PREC, 4, BT, EM>(a, lds, s);
+  if (a.RP == 128) return launch_embed_nt<PREC, 8, BT, EM>(a, lds, s);
+  return launch_embed_nt<PREC, 16, BT, EM>(a, lds, s);
 }
 
 }  // namespace
@@ -1082,6 +1110,49 @@ hipError_t launch_embed_mfma(const Guide &g, const float *c, int r, const float 
   if (e != hipSuccess) return e;
   if (prec == 1) return BT == 512 ? launch_embed_bt<1, 512>(a, lds, s) : launch_embed_bt<1, 256>(a, lds, s);
   return BT == 512 ? launch_embed_bt<2, 512>(a, lds, s) : launch_embed_bt<2, 256>(a, lds, s);
+}
+
+size_t embed_split_floats(const Guide &g, int r, int prec) {
+  size_t lds = 0;
+  const int BT = prec == 1 ? plan_embed<1>(g, r, &lds) : plan_embed<2>(g, r, &lds);
+  if (BT == 0) return 0;
+  const MArgs a = make_args(g, nullptr, r, nullptr, 16 * BT / 64);
+  return (size_t)a.ntiles * (16 * BT / 64) * a.RP;
+}
+
+hipError_t launch_embed_mfma_b(const Guide &g, const float *c, int r, const float *mu, double sigma_r, int prec,
+                               float *bbuf, void *lm_scratch, hipStream_t s) {
+  size_t lds = 0;
+  const int BT = prec == 1 ? plan_embed<1>(g, r, &lds) : plan_embed<2>(g, r, &lds);
+  if (BT == 0) return hipErrorInvalidValue;
+  MArgs a = make_args(g, c, r, mu, 16 * BT / 64);
+  a.r_eff = 1;
+  a.RE = 16;
+  a.inv2s2 = isinf(sigma_r) ? 0.0f : (float)(1.0 / (2.0 * sigma_r * sigma_r));
+  a.bbuf = bbuf;
+  hipError_t e = prec == 1 ? prep_landmarks<1>(a, lm_scratch, s) : prep_landmarks<2>(a, lm_scratch, s);
+  if (e != hipSuccess) return e;
+  if (prec == 1) return BT == 512 ? launch_embed_bt<1, 512, 1>(a, lds, s) : launch_embed_bt<1, 256, 1>(a, lds, s);
+  return BT == 512 ? launch_embed_bt<2, 512, 1>(a, lds, s) : launch_embed_bt<2, 256, 1>(a, lds, s);
+}
+
+hipError_t launch_embed_mfma_mix(const Guide &g, int r, const double *F, float *F32, int r_eff, int prec, float *u,
+                                 const float *bbuf, hipStream_t s) {
+  hipLaunchKernelGGL(f64_to_f32_kernel, dim3((r * r_eff + 255) / 256), dim3(256), 0, s, F, F32, r * r_eff);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  size_t lds_full = 0;
+  const int BT = prec == 1 ? plan_embed<1>(g, r, &lds_full) : plan_embed<2>(g, r, &lds_full);
+  if (BT == 0) return hipErrorInvalidValue;
+  MArgs a = make_args(g, nullptr, r, nullptr, 16 * BT / 64);
+  a.F32 = F32;
+  a.r_eff = r_eff;
+  a.RE = (r_eff + 15) / 16 * 16;
+  a.u = u;
+  a.bbuf = const_cast<float *>(bbuf);
+  const size_t lds = sizeof(float) * (size_t)(16 * BT / 64) * (a.RP + 4);  // the b tile only
+  if (prec == 1) return BT == 512 ? launch_embed_bt<1, 512, 2>(a, lds, s) : launch_embed_bt<1, 256, 2>(a, lds, s);
+  return BT == 512 ? launch_embed_bt<2, 512, 2>(a, lds, s) : launch_embed_bt<2, 256, 2>(a, lds, s);
 }
 
 }  // namespace nkf

@@ -59,6 +59,14 @@ hipError_t launch_lloyd_mfma(const Guide &g, const float *c, int r, const float 
 hipError_t launch_embed_mfma(const Guide &g, const float *c, int r, const float *mu, const double *F,
                              float *F32, int r_eff, double sigma_r, int prec, float *u, void *lm_scratch,
                              hipStream_t s);
+// The 16-bit embedding in two launches: the cross-kernel tiles b (landmarks
+// only; they can run while the host decomposes A) into bbuf, then the mix
+// u = F^T b from them.  bbuf holds embed_split_floats(g, r, prec) floats.
+size_t embed_split_floats(const Guide &g, int r, int prec);
+hipError_t launch_embed_mfma_b(const Guide &g, const float *c, int r, const float *mu, double sigma_r, int prec,
+                               float *bbuf, void *lm_scratch, hipStream_t s);
+hipError_t launch_embed_mfma_mix(const Guide &g, int r, const double *F, float *F32, int r_eff, int prec, float *u,
+                                 const float *bbuf, hipStream_t s);
 // One Lloyd step whose assignment runs on MFMA (labels nullable).
 hipError_t launch_kmeans_step_mfma(const Guide &g, float *c, int r, const float *mu, int prec, double *partials,
                                    int *labels, void *lm_scratch, hipStream_t s);

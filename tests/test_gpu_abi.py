@@ -132,3 +132,36 @@ def test_one_shot_filter_psnr_vs_exact():
     Q, al, F, _ = nkf.landmark_factor(c_gpu.cpu().numpy().astype(np.float64), prm["sigma_r"])
     g2 = nkf.filter_landmarks(ft, c_gpu, F, sigma_s=prm["sigma_s"], sigma_r=prm["sigma_r"], radius=prm["S"])
     assert np.abs(g2.cpu().numpy() - g).max() <= 1e-3
+
+
+@pytest.mark.parametrize("prec,guide", [("fp16", "patch"), ("bf16", "patch"), ("bf16", "self")])
+def test_one_shot_16bit_split_embedding(prec, guide):
+    """nkf_filter runs the 16-bit embedding in two launches, the cross-kernel
+    tiles while the host decomposes A and the mix after F arrives; the same
+    landmarks through nkf_filter_landmarks take the one-launch embedding.
+    The two differ only through the host-formed versus the device-formed A
+    (last-bit differences, amplified by F = Q Lambda^{-1/2} and its FP32
+    rounding in the 16-bit mix), far inside the forms' own 45 dB bar."""
+    nkf = _nkf()
+    if guide == "patch":
+        f, prm = synth.workload("color_nlm_1024", 150, 97)
+        kw = dict(guide="patch", patch_radius=prm["patch_radius"], spatial="box", sigma_s=1.0)
+    else:
+        f, prm = synth.workload("hyperspectral_512x128", 70, 61)
+        kw = dict(sigma_s=prm["sigma_s"])
+    ft = torch.from_numpy(f).cuda()
+    common = dict(sigma_r=prm["sigma_r"], radius=prm["S"], precision=prec)
+    g, reff = nkf.filter(ft, r=prm["r"], iters=3, seed=prm["landmark_seed"], return_r_eff=True, **common, **kw)
+    kmk = {k: v for k, v in kw.items() if k in ("guide", "patch_radius")}
+    c = nkf.kmeans(ft, r=prm["r"], iters=3, seed=prm["landmark_seed"], precision=prec, **kmk)
+    _, _, F, reff2 = nkf.landmark_factor(c.cpu().numpy().astype(np.float64), prm["sigma_r"])
+    g2 = nkf.filter_landmarks(ft, c, F, **common, **kw)
+    torch.cuda.synchronize()
+    a, b = g.cpu().numpy().astype(np.float64), g2.cpu().numpy().astype(np.float64)
+    d = np.abs(a - b).max()
+    scale = float(np.abs(f).max())
+    ps = exact.psnr(a, b, scale)
+    print(f"[split embedding {prec} {guide}] r_eff {reff}/{reff2}: max|dg| {d:.3e} (data max {scale:.3g}), "
+          f"PSNR {ps:.1f} dB", flush=True)
+    assert reff == reff2
+    assert ps >= 90.0
