@@ -644,7 +644,7 @@ void carve_km(Carve &cv, const Resolved &rs, int r, KmBufs &b) {
 nkf_status run_lloyd(nkf_ctx *ctx, const Resolved &rs, int r, float *c, int iters, int *labels,
                      const KmBufs &b, int prec) {
   StageTimer tm(ctx, NKF_STAGE_KMEANS);
-  if (use_mfma_distance(rs.g, prec)) {
+  if (use_mfma_kmeans(rs.g, prec)) {
     // the partial-sum buffer doubles as the scratch of the centring offsets
     if (iters > 0) HIP_TRY(ctx, launch_guide_mean(rs.g, b.mu, b.sums, ctx->stream));
     for (int it = 0; it < iters; ++it)
@@ -1111,7 +1111,7 @@ nkf_status nkf_filter(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, 
     if (!ctx->copy_done) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->copy_done, hipEventDisableTiming));
     HIP_TRY(ctx, hipEventRecord(ctx->copy_done, ctx->stream));
     // landmark-independent work runs on the device while the host factors A
-    const bool mean_ready = prm->kmeans_iters > 0 && use_mfma_distance(rs.g, prm->prec);
+    const bool mean_ready = prm->kmeans_iters > 0 && use_mfma_kmeans(rs.g, prm->prec);
     if ((st = run_pre(ctx, rs, prm, fb, mean_ready ? kb.mu : nullptr)) != NKF_OK) return st;
     if (fb.bsplit)
       HIP_TRY(ctx, launch_embed_mfma_b(rs.g, c, r, fb.mu, prm->sigma_r, prm->prec, fb.bsplit, fb.lm, ctx->stream));

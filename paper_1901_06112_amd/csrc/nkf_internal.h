@@ -72,6 +72,10 @@ hipError_t launch_kmeans_step_mfma(const Guide &g, float *c, int r, const float 
                                    int *labels, void *lm_scratch, hipStream_t s);
 // Whether the 16-bit MFMA distance path serves this guide / precision.
 inline bool use_mfma_distance(const Guide &g, int prec) { return prec != 0 && g.D > 8; }
+// The 16-bit forms' k-means takes the matrix cores from D > 32; below, one
+// 32-wide K step and half-empty landmark tiles make the FP32 VALU assignment
+// (also the more exact one) the faster.
+inline bool use_mfma_kmeans(const Guide &g, int prec) { return prec != 0 && g.D > 32; }
 
 // ---- kernels_embed.hip ------------------------------------------------------
 // f0[c] = center (finite) or (min_c + max_c) / 2 over f.
