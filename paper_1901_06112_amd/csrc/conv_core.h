@@ -18,6 +18,8 @@
 //               wr, w1' in wc): the row pass keeps both w1 and w1' rows in two
 //               rings, the column pass takes w1' over the first and w1 over
 //               the second                                          -> partials
+//   MODE_DS     MODE_DUDIR and MODE_SIGS in one pass: the w1 column pass over
+//               the w1 rows gives du_dir, the w1' one the sigma_s terms
 //   MODE_ADJ    Yb_k = w * (beta u_k), Ya_kc = w * (a_c u_k):
 //               du_k(x) = du_dir_k(x) + Yb_k(x) + sum_c f~_c(x) Ya_kc(x) -> HBM
 //               df_c(x) = sum_k u_k(x) Ya_kc(x)                  -> registers
@@ -50,7 +52,7 @@ constexpr int kBlock = 256;
 constexpr int kTW = 32;
 constexpr int kTWP = kTW + 4;  // ring row stride (floats): rows shift by 4 banks
 
-enum Mode { MODE_FWD = 0, MODE_DUDIR = 1, MODE_SIGS = 2, MODE_ADJ = 3 };
+enum Mode { MODE_FWD = 0, MODE_DUDIR = 1, MODE_SIGS = 2, MODE_ADJ = 3, MODE_DS = 4 };
 
 struct ConvArgs {
   int H, W, C, r_eff;
@@ -104,9 +106,10 @@ struct Cfg {
   static constexpr int UPL = RAWU_SEP ? NP : 0;               // index of the raw-u staged plane
   static constexpr int WIN = ((RUN + 2 * S + 3) / 4) * 4;
   static constexpr int STG = NPU * PSTG;                      // staging floats
-  static constexpr int RINGF = NP * PR * (MODE == MODE_SIGS ? 2 : 1);  // convolved-row ring floats
+  static constexpr bool TWO_RINGS = MODE == MODE_SIGS || MODE == MODE_DS;  // w1 and w1' rows
+  static constexpr int RINGF = NP * PR * (TWO_RINGS ? 2 : 1);  // convolved-row ring floats
   static constexpr int URINGF = FWD ? RINGX * kTWP : 0;       // raw-u ring floats (forward)
-  static constexpr int EXF = (MODE == MODE_DUDIR || MODE == MODE_ADJ) ? NP * RC * kTW : 0;
+  static constexpr int EXF = (MODE == MODE_DUDIR || MODE == MODE_ADJ || MODE == MODE_DS) ? NP * RC * kTW : 0;
   static constexpr int ETAB = FWD ? NCH_MAX * RC * kTW : 0;   // epilogue eta tile
   static constexpr int MAIN = STG + RINGF + URINGF + EXF;
   static constexpr int SMEM = MAIN > ETAB ? MAIN : ETAB;
@@ -202,7 +205,8 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
   constexpr int SW = K::SW, RUN = K::RUN, SEGS = K::SEGS, LAG = K::LAG, RING = K::RING;
   constexpr int NCH_MAX = K::NCH_MAX, NCHAN = K::NCHAN, UPL = K::UPL;
   constexpr bool FWD = K::FWD;
-  constexpr bool BWD_AB = MODE == MODE_DUDIR || MODE == MODE_SIGS;  // contraction weights a, beta
+  constexpr bool BWD_AB = MODE == MODE_DUDIR || MODE == MODE_SIGS || MODE == MODE_DS;  // weights a, beta
+  constexpr bool SIGT = MODE == MODE_SIGS || MODE == MODE_DS;     // the sigma_s terms
   __shared__ __attribute__((aligned(16))) float smem[K::SMEM];
   float *stg = smem;                        // [NPU][RC][SW], plane stride PSTG
   float *ring = smem + K::STG;              // [NP][RINGX][kTWP], plane stride PR
@@ -392,7 +396,7 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
               if (mirror) dst[RING * kTWP + i] = sf;
             }
           }
-          if constexpr (MODE == MODE_SIGS) {
+          if constexpr (SIGT) {
             // the w1' rows, in the second ring
             float *dst2 = dst + NP * K::PR;
 #pragma unroll
@@ -448,11 +452,11 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
             const int ty0k = opaque(ty * TH);
             const int gx = tx0 + c_x;
             const float *uk = a.u + (int64_t)k * N;
-            float cu[MODE == MODE_SIGS ? RUN : 1];
+            float cu[SIGT ? RUN : 1];
 #pragma unroll
             for (int i = 0; i < RUN; ++i) {
               // SIGS: w1' down the w1 rows here, w1 down the w1' rows below
-              const double z = fir_sym<S>(MODE == MODE_SIGS ? a.wc : wcol, &win[i]);
+              const double z = fir_sym<S>(SIGT ? a.wc : wcol, &win[i]);
               const int gy = ty0k + o0 + i;
               const bool inpix = oc < a.nch && gy < H && gx < W;
               const int pix = inpix ? gy * W + gx : 0;
@@ -463,7 +467,9 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
                 } else {
                   const float uo = inpix ? uk[pix] : 0.0f;
                   sacc = fma((double)(uo * coef), z, sacc);
-                  if constexpr (MODE == MODE_SIGS) cu[i] = uo * coef;
+                  if constexpr (SIGT) cu[i] = uo * coef;
+                  if constexpr (MODE == MODE_DS)  // du_dir from the w1 column pass of the same rows
+                    ex[(c_p * RC + c_sub * RUN + i) * kTW + c_x] = coef * (float)fir_sym<S>(wcol, &win[i]);
                 }
               } else {  // MODE_ADJ
                 float coef = 1.0f;
@@ -476,14 +482,14 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
                 ex[(c_p * RC + c_sub * RUN + i) * kTW + c_x] = coef * (float)z;
               }
             }
-            if constexpr (MODE == MODE_SIGS) {
+            if constexpr (SIGT) {
 #pragma unroll
               for (int j = 0; j < RUN + 2 * S; ++j) win[j] = col[NP * K::PR + j * kTWP];
 #pragma unroll
               for (int i = 0; i < RUN; ++i) sacc = fma((double)cu[i], fir_sym<S>(wcol, &win[i]), sacc);
             }
           }
-          if constexpr (MODE == MODE_DUDIR || MODE == MODE_ADJ) {
+          if constexpr (MODE == MODE_DUDIR || MODE == MODE_ADJ || MODE == MODE_DS) {
             // combine the NP planes of each pixel of the chunk
             __syncthreads();
             const int ty0k = opaque(ty * TH);
@@ -513,7 +519,7 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
   const int gx = tx0 + c_x;
   if constexpr (MODE == MODE_DUDIR) {
     return;
-  } else if constexpr (MODE == MODE_SIGS) {
+  } else if constexpr (SIGT) {
     // block sum of the per-thread FP64 partials, in a fixed order
     __syncthreads();
     double *red = reinterpret_cast<double *>(smem);

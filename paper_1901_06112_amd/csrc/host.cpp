@@ -1227,17 +1227,15 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
     bp.wr = rs.taps;
     bp.wc = rs.taps;
     bp.force_nch = ctx->conv_chunks;
-    bp.mode = 1;
     bp.plane_out = dud;
-    HIP_TRY(ctx, launch_bwd_conv(bp, ctx->stream));
     if (want_S) {
+      // du_dir and the sigma_s terms in one pass over the same planes:
       // dw/dsigma_s = w1' (x) w1 + w1 (x) w1', w1'(t) = w1(t) t^2 / sigma_s^3
       Taps dt = rs.taps;
       const double s3 = prm->sigma_s * prm->sigma_s * prm->sigma_s;
       for (int t = -rs.S; t <= rs.S; ++t)
         dt.w[t + rs.S] = (float)(exp(-(double)t * t / (2.0 * prm->sigma_s * prm->sigma_s)) * t * t / s3);
-      bp.mode = 2;  // both terms in one pass: w1 in wr, w1' in wc
-      bp.plane_out = nullptr;
+      bp.mode = 4;  // w1 in wr, w1' in wc
       bp.partials = sig;
       bp.wr = rs.taps;
       bp.wc = dt;
@@ -1246,6 +1244,9 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
       bp.wr = bp.wc = rs.taps;
       bp.nblocks_out = nullptr;
       bp.partials = nullptr;
+    } else {
+      bp.mode = 1;
+      HIP_TRY(ctx, launch_bwd_conv(bp, ctx->stream));
     }
     bp.mode = 3;
     bp.plane_in = dud;

@@ -193,11 +193,12 @@ __global__ __launch_bounds__(kRBlock) void reduce_kernel(Guide g, int64_t N, con
 template <int MODE>
 hipError_t launch_mode(ConvArgs a, int S, hipStream_t s, int *nblocks) {
   switch (S) {
-  // the fused sigma_s pass holds two tap sets; past S = 10 it takes 16-row
-  // chunks so that its row windows (RUN + 2S values) still fit in registers
+  // the fused sigma_s pass holds two tap sets; past S = 10 (past S = 8 when
+  // it also forms du_dir) it takes 16-row chunks so that its row windows
+  // (RUN + 2S values) still fit in registers
 #define NKF_CASE(SV)                                                               \
   case SV:                                                                         \
-    if constexpr (MODE == MODE_SIGS && SV > 10)                                    \
+    if constexpr ((MODE == MODE_SIGS && SV > 10) || (MODE == MODE_DS && SV > 8))   \
       return launch_one<SV, 4, true, 16, MODE, 512>(a, s, 3, 1, nblocks);      \
     else                                                                           \
       return launch_one<SV, 4, true, 32, MODE, 512>(a, s, 3, 1, nblocks);
@@ -252,6 +253,7 @@ hipError_t launch_bwd_conv(const BwdConvProblem &pb, hipStream_t s) {
     case 1: e = launch_mode<MODE_DUDIR>(a, pb.S, s, &nb); break;
     case 2: e = launch_mode<MODE_SIGS>(a, pb.S, s, &nb); break;
     case 3: e = launch_mode<MODE_ADJ>(a, pb.S, s, &nb); break;
+    case 4: e = launch_mode<MODE_DS>(a, pb.S, s, &nb); break;
     default: break;
   }
   if (pb.nblocks_out) *pb.nblocks_out = nb;

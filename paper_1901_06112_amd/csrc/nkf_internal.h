@@ -156,7 +156,7 @@ hipError_t launch_wk(const WkProblem &pb, hipStream_t s);
 // ---- kernels_bwd.hip --------------------------------------------------------
 // Backward passes (C <= 3).  mode 1: du_dir planes; 2: sigma_s partial sums
 // (one double per block, with row taps wr and column taps wc); 3: adjoint
-// convolutions -> du planes and df.
+// convolutions -> du planes and df; 4: modes 1 and 2 in one pass.
 struct BwdConvProblem {
   int mode, H, W, C, S, r_eff;
   const float *f, *f0, *u, *ab, *plane_in, *G, *eta;
