@@ -440,7 +440,7 @@ __device__ __forceinline__ void tile_products(const MArgs &a, const float *raw, 
 // LDS bytes of the k-means kernel before the one-hot matrix (halves of size hb)
 __host__ __device__ __forceinline__ size_t lloyd_base_bytes(const MArgs &a, int TP, int hb) {
   return (size_t)hb * a.RP * a.DS + sizeof(float) * ((size_t)a.raw_floats + 8 + a.RP) +
-         sizeof(int) * (2 * kMaxChunks + TP + a.g.D);
+         sizeof(int) * (2 * kMaxChunks + TP + a.g.D + a.RP);
 }
 
 // Minimum of (value, index) over the 16 lanes of a DPP row, lowest index on
@@ -493,8 +493,9 @@ struct Split<2> {
 // A = one-hot labels (16 clusters x 32 pixels), B = the centred guide values
 // split into 16-bit parts (32 pixels x 16 dimensions), FP32 accumulators held
 // by the waves for the whole launch: wave w owns the dimension tiles
-// w + NW m (m < MDT) for all NT cluster tiles; dimension D carries the count
-// (value 1 for every pixel).
+// w + NW m (m < MDT) for all NT cluster tiles.  The counts are integer LDS
+// increments in the argmin (exact, order-free), so D = 16 n guides need no
+// extra tile for a count column and every wave owns the same number of tiles.
 template <int PREC, int NT, int BT, int MDT, int PF>
 __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
   using T = typename Half<PREC>::T;
@@ -509,12 +510,13 @@ __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
   int *tab_nv = tab_off + kMaxChunks;                                         // [kMaxChunks]
   int *labs = tab_nv + kMaxChunks;                                            // [TP]
   int *dmap = labs + TP;                                                      // [D]
-  float *sacc = reinterpret_cast<float *>(dmap + a.g.D);                      // [r][D+1] (lds_acc)
+  int *cnt = dmap + a.g.D;                                                    // [RP] (GEMM path)
+  float *sacc = reinterpret_cast<float *>(cnt + a.RP);                        // [r][D+1] (lds_acc)
   // GEMM path: one-hot label matrix [RP][TP + 8] (16-bit 0 / 1), 16-byte aligned
   T *oh = reinterpret_cast<T *>(smem_raw + ((lloyd_base_bytes(a, TP, sizeof(T)) + 15) & ~(size_t)15));
   constexpr int OHS = TP + 8;
   const int D = a.g.D, DA = D + 1;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col = lane & 15, rq = lane >> 4;
   double *slot = a.partials + (size_t)blockIdx.x * a.r * DA;
 
@@ -524,6 +526,7 @@ __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
   for (int e = tid; e < TP; e += BT) labs[e] = -1;
   if constexpr (MDT > 0) {
     for (int e = tid; e < a.RP * OHS; e += BT) oh[e] = (T)0.0f;
+    for (int e = tid; e < a.RP; e += BT) cnt[e] = 0;
   } else {
     if (a.lds_acc) {
       for (int e = tid; e < a.r * DA; e += BT) sacc[e] = 0.0f;
@@ -542,10 +545,12 @@ __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
 #pragma unroll
     for (int m = 0; m < MDT; ++m) {
       const int d = 16 * (w + NW * m) + col;
-      doff[m] = d < D ? dmap[d] : (d == D ? -2 : -1);
+      doff[m] = d < D ? dmap[d] : -1;
     }
   }
-  const int ndt = (DA + 15) / 16;  // dimension tiles, count column included
+  const int ndt = (D + 15) / 16;  // dimension tiles of the GEMM sums
+  // dimension tiles w + NW m (m < MDT) owned by this wave
+  const int nown = MDT > 0 ? max(0, min(MDT, (ndt - w + NW - 1) / NW)) : 0;
   floatx4 sacc_r[MDT > 0 ? MDT : 1][NT];
 #pragma unroll
   for (int m = 0; m < (MDT > 0 ? MDT : 1); ++m)
@@ -600,7 +605,10 @@ __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
             // move this pixel's one-hot entry from the previous tile's label
             const int old = labs[pxl];
             if (old >= 0) oh[old * OHS + pxl] = (T)0.0f;
-            if (valid) oh[bi * OHS + pxl] = (T)1.0f;
+            if (valid) {
+              oh[bi * OHS + pxl] = (T)1.0f;
+              atomicAdd(&cnt[bi], 1);
+            }
           }
           labs[pxl] = valid ? bi : -1;
           if (valid && a.labels) a.labels[ti.x0 + pxl] = bi;
@@ -609,37 +617,44 @@ __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
     }
     __syncthreads();
     if constexpr (MDT > 0) {
-      // one-hot GEMM over the tile's pixels, 32 per K step
+      // one-hot GEMM over the tile's pixels, 32 per K step.  The number of
+      // dimension tiles this wave owns is uniform and picks a loop of fixed
+      // length: no branches between the accumulators' updates, which kept
+      // them moving between registers
+      auto sums = [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
 #pragma unroll
-      for (int ks = 0; ks < TP / 32; ++ks) {
-        const int px0 = 32 * ks + 8 * rq;  // this lane's 8 pixels (K rows)
-        V bp[MDT][NPART];
+        for (int ks = 0; ks < TP / 32; ++ks) {
+          const int px0 = 32 * ks + 8 * rq;  // this lane's 8 pixels (K rows)
+          V bp[M][NPART];
 #pragma unroll
-        for (int m = 0; m < MDT; ++m) {
-          if (w + NW * m >= ndt) break;
-          // v = raw value (dimension column), 1 (count column) or 0 (padding)
-          const bool dim = doff[m] >= 0;
-          const float va = doff[m] == -2 ? 1.0f : 0.0f;
-          const float *src = raw + px0 * a.pxstride + (dim ? doff[m] : 0);
+          for (int m = 0; m < M; ++m) {
+            // v = raw value (dimension column) or 0 (padding)
+            const bool dim = doff[m] >= 0;
+            const float *src = raw + px0 * a.pxstride + (dim ? doff[m] : 0);
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const float v = dim ? src[j * a.pxstride] : va;
-            T pp[NPART];
-            Split<PREC>::parts(v, pp);
+            for (int j = 0; j < 8; ++j) {
+              const float v = dim ? src[j * a.pxstride] : 0.0f;
+              T pp[NPART];
+              Split<PREC>::parts(v, pp);
 #pragma unroll
-            for (int q = 0; q < NPART; ++q) bp[m][q][j] = pp[q];
+              for (int q = 0; q < NPART; ++q) bp[m][q][j] = pp[q];
+            }
+          }
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt) {
+            const V av = *reinterpret_cast<const V *>(&oh[(16 * tt + col) * OHS + px0]);
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+#pragma unroll
+              for (int q = 0; q < NPART; ++q) sacc_r[m][tt] = Half<PREC>::mma(av, bp[m][q], sacc_r[m][tt]);
           }
         }
-#pragma unroll
-        for (int tt = 0; tt < NT; ++tt) {
-          const V av = *reinterpret_cast<const V *>(&oh[(16 * tt + col) * OHS + px0]);
-#pragma unroll
-          for (int m = 0; m < MDT; ++m) {
-            if (w + NW * m >= ndt) break;
-#pragma unroll
-            for (int q = 0; q < NPART; ++q) sacc_r[m][tt] = Half<PREC>::mma(av, bp[m][q], sacc_r[m][tt]);
-          }
-        }
+      };
+      if (nown == MDT) {
+        sums(std::integral_constant<int, MDT>{});
+      } else if constexpr (MDT == 2) {
+        if (nown == 1) sums(std::integral_constant<int, 1>{});
       }
     } else {
       // per-cluster sums of the centred guide vectors with atomics: wave w
@@ -673,7 +688,7 @@ __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
 #pragma unroll
     for (int m = 0; m < MDT; ++m) {
       const int d = 16 * (w + NW * m) + col;
-      if (d >= DA) continue;
+      if (d >= D) continue;
 #pragma unroll
       for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
@@ -682,6 +697,9 @@ __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
           if (k < a.r) slot[(size_t)k * DA + d] = (double)sacc_r[m][tt][i];
         }
     }
+    // the counts are complete: the last tile's increments precede the barrier
+    // ahead of its sums
+    for (int k = tid; k < a.r; k += BT) slot[(size_t)k * DA + D] = (double)cnt[k];
   } else if (a.lds_acc) {
     __syncthreads();
     for (int e = tid; e < a.r * DA; e += BT) slot[e] = (double)sacc[e];
@@ -900,7 +918,7 @@ size_t ct_bytes(const MArgs &a) {
 
 size_t lloyd_lds(const MArgs &a, int TP, size_t ctb, bool lds_acc, bool gemm_acc) {
   size_t b = ctb + sizeof(float) * ((size_t)a.raw_floats + 8 + a.RP) +
-             sizeof(int) * (2 * kMaxChunks + TP + a.g.D);
+             sizeof(int) * (2 * kMaxChunks + TP + a.g.D + a.RP);
   if (lds_acc) b += sizeof(float) * (size_t)a.r * (a.g.D + 1);
   if (gemm_acc) b = ((b + 15) & ~(size_t)15) + (ctb / a.DS) * (TP + 8);  // one-hot [RP][TP + 8]
   return b;
@@ -933,7 +951,7 @@ LloydPlan plan_lloyd(const Guide &g, int r) {
   {
     const MArgs a = make_args(g, nullptr, r, nullptr, 128);
     if (a.Dp / 8 > kMaxChunks) return {0, 0, false, 0, false};
-    const int ndt = (g.D + 1 + 15) / 16;
+    const int ndt = (g.D + 15) / 16;
     const int mdt = (ndt + 7) / 8;
     const int NT = a.RP / 16;
     const size_t l = lloyd_lds(a, 128, ct_bytes<PREC>(a), false, true);
