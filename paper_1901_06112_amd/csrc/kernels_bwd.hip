@@ -60,8 +60,14 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 // A = b^T (16 landmarks x 4 pixels), B = du_dir (4 pixels x 16 planes); wave w
 // keeps the output tiles w, w + 4, ... of R in registers for the whole launch
 // (lane l, element i holds R[16 jt + l/16 + 4 i][16 kt + l%16]).
-// LDS (doubles): bs[r][65], wj[r][64] (= db_j b_j / sigma_r^2), red[256];
-// floats: pt[D][64], dus[r_eff][64], duds[r_eff][65].
+// LDS (doubles): bs[r][65], wj[r][64] (= db_j b_j / sigma_r^2), red[256],
+// Fs[r_eff][4][NJ] (Fs[k][kg][m] = F[kg + 4 m][k], so that the db loop reads
+// its F values from LDS, one broadcast read per pair, instead of one scalar
+// load and wait per value); floats: pt[D][64], dus[r_eff][64], duds[r_eff][65].
+// NJ: landmarks per thread group rounded up (8 or 16), the length of the
+// register-blocked loops, so that the accumulators are updated without
+// branches (a landmark past r contributes zero).
+template <int NJ>
 __global__ __launch_bounds__(kRBlock) void reduce_kernel(Guide g, int64_t N, const float *__restrict__ c, int r,
                                                          const double *__restrict__ F, int r_eff, double sigma_r,
                                                          const float *__restrict__ du, const float *__restrict__ dud,
@@ -72,7 +78,8 @@ __global__ __launch_bounds__(kRBlock) void reduce_kernel(Guide g, int64_t N, con
   double *bs = sm;
   double *wj = bs + (size_t)r * kRS;
   double *red = wj + (size_t)r * kRTile;                     // [256]
-  float *pt = reinterpret_cast<float *>(red + kRBlock);      // [D][64]
+  double *Fs = red + kRBlock;                                // [r_eff][4][NJ]
+  float *pt = reinterpret_cast<float *>(Fs + (size_t)4 * NJ * r_eff);  // [D][64]
   float *dus = pt + (size_t)D * kRTile;                      // [r_eff][64]
   float *duds = dus + (size_t)r_eff * kRTile;                // [r_eff][65]
   const int tid = threadIdx.x, lane = tid & 63;
@@ -84,10 +91,16 @@ __global__ __launch_bounds__(kRBlock) void reduce_kernel(Guide g, int64_t N, con
   const double inv_s3 = inv_s2 / sigma_r;
   const int ntj = (r + 15) / 16, ntk = (r_eff + 15) / 16;
   const int nt = want_R ? ntj * ntk : 0;
+  const int nq = nt > kg ? min(4, (nt - kg + 3) / 4) : 0;  // R tiles kg + 4 q of this wave
   double4_t racc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) racc[q] = double4_t{0.0, 0.0, 0.0, 0.0};
   double sr_acc = 0.0;
+  for (int e = tid; e < 4 * NJ * r_eff; e += kRBlock) {
+    const int k = e / (4 * NJ), rem = e - k * 4 * NJ, q = rem / NJ, m = rem - q * NJ;
+    const int j = q + 4 * m;
+    Fs[e] = j < r ? F[(size_t)j * r_eff + k] : 0.0;
+  }  // ordered before its first use by the barrier after the tile staging
   for (int64_t base = (int64_t)blockIdx.x * kRTile; base < N; base += (int64_t)gridDim.x * kRTile) {
     // stage the tile: thread (px, kg) takes planes k = kg + 4 q of its pixel;
     // every load is issued before the first LDS store, so a tile costs one
@@ -95,18 +108,23 @@ __global__ __launch_bounds__(kRBlock) void reduce_kernel(Guide g, int64_t N, con
     {
       const int64_t x = base + px;
       const bool xin = x < N;
-      float vdu[kRMaxJ], vdud[kRMaxJ];
+      float vdu[NJ], vdud[NJ];
+      // out-of-range planes and pixels load plane 0 / the last pixel (always
+      // in bounds, no branch around the loads) and are zeroed afterwards
+      const int64_t xc = xin ? x : N - 1;
 #pragma unroll
-      for (int q = 0; q < kRMaxJ; ++q) {
+      for (int q = 0; q < NJ; ++q) {
         const int k = kg + 4 * q;
         const bool ok = xin && k < r_eff;
-        vdu[q] = ok ? du[(int64_t)k * N + x] : 0.0f;
-        vdud[q] = ok ? dud[(int64_t)k * N + x] : 0.0f;
+        const int64_t o = (int64_t)(k < r_eff ? k : 0) * N + xc;
+        const float a = du[o], b = dud[o];
+        vdu[q] = ok ? a : 0.0f;
+        vdud[q] = ok ? b : 0.0f;
       }
       __syncthreads();
       for (int d = kg; d < D; d += 4) pt[d * kRTile + px] = xin ? guide_elem(g, x, d) : 0.0f;
 #pragma unroll
-      for (int q = 0; q < kRMaxJ; ++q) {
+      for (int q = 0; q < NJ; ++q) {
         const int k = kg + 4 * q;
         if (k < r_eff) {
           dus[k * kRTile + px] = vdu[q];
@@ -117,17 +135,17 @@ __global__ __launch_bounds__(kRBlock) void reduce_kernel(Guide g, int64_t N, con
     __syncthreads();
     const bool valid = base + px < N;
     // db_j = sum_k F[j][k] du_k for this thread's landmarks: each du_k read once
-    double db[kRMaxJ];
+    double db[NJ];
 #pragma unroll
-    for (int m = 0; m < kRMaxJ; ++m) db[m] = 0.0;
+    for (int m = 0; m < NJ; ++m) db[m] = 0.0;
     for (int k = 0; k < r_eff; ++k) {
       const double duk = (double)dus[k * kRTile + px];
+      const double *fk = Fs + (size_t)(4 * k + kg) * NJ;
 #pragma unroll
-      for (int m = 0; m < kRMaxJ; ++m)
-        if (m < nj) db[m] = fma(F[(kg + 4 * m) * r_eff + k], duk, db[m]);
+      for (int m = 0; m < NJ; ++m) db[m] = fma(fk[m], duk, db[m]);
     }
 #pragma unroll
-    for (int m = 0; m < kRMaxJ; ++m) {
+    for (int m = 0; m < NJ; ++m) {
       if (m >= nj) continue;
       const int j = kg + 4 * m;
       double d2 = 0.0;
@@ -151,19 +169,39 @@ __global__ __launch_bounds__(kRBlock) void reduce_kernel(Guide g, int64_t N, con
         if (x < N) dp[x * D + d] = (float)(-s);
       }
     }
-    // R tiles on the matrix cores, 4 pixels per step
+    // R tiles on the matrix cores, 4 pixels per step, two accumulation chains
+    // per tile; the wave's tile count (uniform) picks a loop of fixed length
+    auto rtiles = [&](auto qc) {
+      constexpr int Q = decltype(qc)::value;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int t = kg + 4 * q;
-      if (t >= nt) break;
-      const int jt = t / ntk, kt = t - jt * ntk;
-      const int ja = 16 * jt + (lane & 15), kb = 16 * kt + (lane & 15);
-      for (int s4 = 0; s4 < kRTile / 4; ++s4) {
-        const int pq = 4 * s4 + (lane >> 4);
-        const double av = ja < r ? bs[ja * kRS + pq] : 0.0;
-        const double bv = kb < r_eff ? (double)duds[kb * kRS + pq] : 0.0;
-        racc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, racc[q], 0, 0, 0);
+      for (int q = 0; q < Q; ++q) {
+        const int t = kg + 4 * q;
+        const int jt = t / ntk, kt = t - jt * ntk;
+        const int ja = 16 * jt + (lane & 15), kb = 16 * kt + (lane & 15);
+        // rows past r (r_eff) read row 0 and are zeroed after the load: no
+        // branch around the loads
+        const bool aok = ja < r, bok = kb < r_eff;
+        const double *arow = bs + (aok ? ja : 0) * kRS + (lane >> 4);
+        const float *brow = duds + (bok ? kb : 0) * kRS + (lane >> 4);
+        double4_t a1 = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int s4 = 0; s4 < kRTile / 4; s4 += 2) {
+          const double av0 = aok ? arow[4 * s4] : 0.0;
+          const double bv0 = bok ? (double)brow[4 * s4] : 0.0;
+          const double av1 = aok ? arow[4 * s4 + 4] : 0.0;
+          const double bv1 = bok ? (double)brow[4 * s4 + 4] : 0.0;
+          racc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av0, bv0, racc[q], 0, 0, 0);
+          a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av1, bv1, a1, 0, 0, 0);
+        }
+        racc[q] += a1;
       }
+    };
+    switch (nq) {
+      case 4: rtiles(std::integral_constant<int, 4>{}); break;
+      case 3: rtiles(std::integral_constant<int, 3>{}); break;
+      case 2: rtiles(std::integral_constant<int, 2>{}); break;
+      case 1: rtiles(std::integral_constant<int, 1>{}); break;
+      default: break;
     }
   }
   __syncthreads();
@@ -265,9 +303,11 @@ int bwd_reduce_blocks(int64_t N) {
   return (int)(b < 1024 ? b : 1024);
 }
 
+static int reduce_nj(int r) { return r <= 32 ? 8 : kRMaxJ; }
+
 size_t bwd_reduce_lds(int r, int r_eff, int D, int want_R) {
   (void)want_R;
-  return sizeof(double) * ((size_t)r * kRS + (size_t)r * kRTile + kRBlock) +
+  return sizeof(double) * ((size_t)r * kRS + (size_t)r * kRTile + kRBlock + (size_t)4 * reduce_nj(r) * r_eff) +
          sizeof(float) * ((size_t)D * kRTile + (size_t)r_eff * kRTile + (size_t)r_eff * kRS);
 }
 
@@ -305,13 +345,17 @@ hipError_t launch_bwd_reduce(const Guide &g, const float *c, int r, const double
                              const float *du, const float *dud, float *dp, int want_R, double *partials,
                              hipStream_t s) {
   const int64_t N = (int64_t)g.H * g.W;
+  if (r < 1 || r > 4 * kRMaxJ) return hipErrorInvalidValue;
   const size_t sm = bwd_reduce_lds(r, r_eff, g.D, want_R);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(reduce_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(reduce_kernel, dim3(bwd_reduce_blocks(N)), dim3(kRBlock), sm, s, g, N, c, r, F, r_eff, sigma_r,
-                     du, dud, dp, want_R, partials);
-  return hipGetLastError();
+  auto launch = [&](auto kern) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(bwd_reduce_blocks(N)), dim3(kRBlock), sm, s, g, N, c, r, F, r_eff, sigma_r, du,
+                       dud, dp, want_R, partials);
+    return hipGetLastError();
+  };
+  return reduce_nj(r) == 8 ? launch(reduce_kernel<8>) : launch(reduce_kernel<kRMaxJ>);
 }
 
 }  // namespace nkf
