@@ -451,7 +451,7 @@ __device__ __forceinline__ void row16_argmin(float &best, int &bi) {
     constexpr int C = decltype(ctrl)::value;
     const float ob = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(best), C, 0xf, 0xf, false));
     const int oi = __builtin_amdgcn_update_dpp(0, bi, C, 0xf, 0xf, false);
-    const bool take = ob < best || (ob == best && oi < bi);
+    const bool take = (ob < best) | ((ob == best) & (oi < bi));  // no short circuit: no branch
     best = take ? ob : best;
     bi = take ? oi : bi;
   };
@@ -629,12 +629,14 @@ __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
           V bp[M][NPART];
 #pragma unroll
           for (int m = 0; m < M; ++m) {
-            // v = raw value (dimension column) or 0 (padding)
+            // v = raw value (dimension column) or 0 (padding); the padding
+            // lanes read dimension 0 (in bounds), so no branch around the load
             const bool dim = doff[m] >= 0;
             const float *src = raw + px0 * a.pxstride + (dim ? doff[m] : 0);
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-              const float v = dim ? src[j * a.pxstride] : 0.0f;
+              const float lv = src[j * a.pxstride];
+              const float v = dim ? lv : 0.0f;
               T pp[NPART];
               Split<PREC>::parts(v, pp);
 #pragma unroll
@@ -727,11 +729,13 @@ __global__ __launch_bounds__(BT) void embed_mfma_kernel(MArgs a) {
   float *cn2 = bs + TP * (a.RP + 4);                                          // [RP]
   int *tab_off = reinterpret_cast<int *>(cn2 + a.RP);                         // [kMaxChunks]
   int *tab_nv = tab_off + kMaxChunks;                                         // [kMaxChunks]
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col = lane & 15, rq = lane >> 4;
   // b-tile row stride == 4 (mod 16): the exp stores (rows 4 rq + i, columns
   // col) and the mix reads (rows col, columns 4 s + rq) hit distinct banks
   const int BS = a.RP + 4;
+  // output tiles w + NW m (m < MAXT2) of this wave with 16 (w + NW m) < RE
+  const int nmix = max(0, min(MAXT2, (a.RE / 16 - w + NW - 1) / NW));
 
   if constexpr (EM != 2) {
     load_landmarks(a, ct, cn2, BT, ct_lo);
@@ -789,30 +793,48 @@ __global__ __launch_bounds__(BT) void embed_mfma_kernel(MArgs a) {
         continue;
       }
     }
-    // U[k'][px] = sum_j F[j][k'] b[px][j]: A = F^T, B = b^T (LDS)
+    // U[k'][px] = sum_j F[j][k'] b[px][j]: A = F^T, B = b^T (LDS).  The
+    // wave's tile count is uniform and picks a loop of fixed length, so that
+    // fa is only ever indexed by constants (a break out of the unrolled loop
+    // left it indexed at run time, in scratch memory)
+    auto mix = [&](auto mc) {
+      constexpr int M = decltype(mc)::value;
 #pragma unroll
-    for (int m = 0; m < MAXT2; ++m) {
-      const int t2 = w + NW * m;
-      if (16 * t2 >= a.RE) break;
-      for (int gp = 0; gp < TP / 16; ++gp) {
-        floatx4 o = {0.f, 0.f, 0.f, 0.f};
-        const float *bcol = bs + (16 * gp + col) * BS + rq;
+      for (int m = 0; m < M; ++m) {
+        const int t2 = w + NW * m;
+#pragma unroll 1
+        for (int gp = 0; gp < TP / 16; ++gp) {
+          floatx4 o = {0.f, 0.f, 0.f, 0.f};
+          const float *bcol = bs + (16 * gp + col) * BS + rq;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          float av;
-          if constexpr (FREG)
-            av = fa[m][s];
-          else
-            av = fval(m, s);
-          o = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bcol[4 * s], o, 0, 0, 0);
+          for (int s = 0; s < KS; ++s) {
+            float av;
+            if constexpr (FREG)
+              av = fa[m][s];
+            else
+              av = fval(m, s);
+            o = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bcol[4 * s], o, 0, 0, 0);
+          }
+          // lane holds U[k' = 16 t2 + 4 rq + i][pixel 16 gp + col]
+          const int pxl = 16 * gp + col;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int kp = 16 * t2 + 4 * rq + i;
+            if (kp < a.r_eff && pxl < ti.nvalid) a.u[(int64_t)kp * a.N + ti.x0 + pxl] = o[i];
+          }
         }
-        // lane holds U[k' = 16 t2 + 4 rq + i][pixel 16 gp + col]
-        const int pxl = 16 * gp + col;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int kp = 16 * t2 + 4 * rq + i;
-          if (kp < a.r_eff && pxl < ti.nvalid) a.u[(int64_t)kp * a.N + ti.x0 + pxl] = o[i];
-        }
+      }
+    };
+    if (nmix == MAXT2) {
+      mix(std::integral_constant<int, MAXT2>{});
+    } else if constexpr (MAXT2 > 1) {
+      if (nmix == 1) {
+        mix(std::integral_constant<int, 1>{});
+      } else if constexpr (MAXT2 > 2) {
+        if (nmix == 2)
+          mix(std::integral_constant<int, 2>{});
+        else if (nmix == 3)
+          mix(std::integral_constant<int, 3>{});
       }
     }
   }
