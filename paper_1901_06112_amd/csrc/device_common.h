@@ -39,10 +39,13 @@ __device__ __forceinline__ float guide_elem(const Guide &g, int64_t x, int d) {
 // a scale by 2^-n.  FP64 accuracy matters when F has large entries: the mix
 // u = F^T b cancels, and an FP32 rounding of each b_j would move u_k by up to
 // eps sum_j |F_jk| b_j instead of eps |u_k|.
+// Branch-free: arguments past the underflow point (and NaN) run the same
+// instructions on 0 and select 0 at the end, so lanes never diverge here.
 __device__ __forceinline__ double exp_neg64(double z) {
-  if (!(z < 745.0)) return 0.0;
-  const double n = rint(z * 1.4426950408889634);
-  const double r = (n * 0.6931467056274414 - z) + n * 4.7493250390316726e-07;
+  const bool ok = z < 745.0;
+  const double zc = ok ? z : 0.0;
+  const double n = rint(zc * 1.4426950408889634);
+  const double r = (n * 0.6931467056274414 - zc) + n * 4.7493250390316726e-07;
   double q = 1.6059043836821613e-10;  // 1 / 13!
   q = fma(q, r, 2.08767569878681e-09);
   q = fma(q, r, 2.505210838544172e-08);
@@ -57,7 +60,7 @@ __device__ __forceinline__ double exp_neg64(double z) {
   q = fma(q, r, 0.5);
   q = fma(q, r, 1.0);
   q = fma(q, r, 1.0);
-  return ldexp(q, -(int)n);
+  return ok ? ldexp(q, -(int)n) : 0.0;
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
