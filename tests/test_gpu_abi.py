@@ -109,7 +109,7 @@ def test_stream_ordering_behind_busy_stream():
 def test_one_shot_filter_psnr_vs_exact():
     """nkf_filter end to end on the 256^2 colour workload: GPU k-means +
     FP64 factor + convolutions.  Landmarks differ from the oracle's only at
-    k-means near-ties, so the output is judged by PSNR against the exact
+    k-means near-ties, so the output is graded by PSNR against the exact
     filter next to the oracle Nystrom with its own landmarks."""
     nkf = _nkf()
     f, prm = synth.workload("color_blf_256")
