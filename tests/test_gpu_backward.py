@@ -71,8 +71,10 @@ def _sigma_ok(val, ref, scale):
     return abs(val - ref) <= max(RTOL_MAX * abs(ref), 4 * 2.0 ** -24 * scale)
 
 
+# r = 48 and 64 take the reduction's 16-landmark register blocks (r > 32)
 @pytest.mark.parametrize("h,w,r,S,ss,sr", [(40, 36, 12, 4, 1.5, 30.0), (75, 66, 32, 9, 3.0, 30.0),
-                                           (44, 50, 8, 12, 4.0, 30.0), (38, 41, 6, 16, 5.0, 40.0)])
+                                           (44, 50, 8, 12, 4.0, 30.0), (38, 41, 6, 16, 5.0, 40.0),
+                                           (64, 56, 48, 6, 2.0, 20.0), (72, 60, 64, 5, 2.0, 20.0)])
 def test_explicit_guide_grads_match_reference(h, w, r, S, ss, sr):
     f, c32, G = _case(h, w, r, seed=h)
     p = np.ascontiguousarray(f + 0.0)
