@@ -638,7 +638,7 @@ void carve_km(Carve &cv, const Resolved &rs, int r, KmBufs &b) {
   b.lab_scratch = cv.take<int>(rs.N);
   b.mu = cv.take<float>(rs.D);
   b.lm = cv.take<unsigned char>(mfma_landmark_scratch_bytes(rs.g, r));
-  b.ct = cv.take<float>(kmeans_transposed_floats(r, rs.D));
+  b.ct = cv.take<float>(kmeans_transposed_floats(rs.g, r));
 }
 
 nkf_status run_lloyd(nkf_ctx *ctx, const Resolved &rs, int r, float *c, int iters, int *labels,

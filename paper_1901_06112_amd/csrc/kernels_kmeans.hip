@@ -501,18 +501,26 @@ static hipError_t assign_accumulate(const Guide &g, const float *c, int r, doubl
   }
   const int64_t N = (int64_t)g.H * g.W;
   int *lab = labels ? labels : label_scratch;
-  const size_t sm1 = sizeof(float) * ((size_t)g.D * kTilePx + 4 * kTilePx) + sizeof(int) * (4 * kTilePx + g.D);
-  const int RP = (r + kAssignRB - 1) / kAssignRB * kAssignRB;
-  hipLaunchKernelGGL(transpose_centroids_kernel, dim3((g.D * RP + 255) / 256), dim3(256), 0, s, c, r, g.D, RP, ct);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void *>(assign_generic_kernel),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(assign_generic_kernel, dim3(grid_for(N, kTilePx, 8192)), dim3(kBlock), sm1, s, g, N, ct,
-                     RP, r, lab);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  if (assign_mfma32_supported(g, r)) {
+    // the FP32 products on the matrix cores
+    e = launch_assign_mfma32(g, c, r, lab, ct, s);
+    if (e != hipSuccess) return e;
+  } else {
+    const size_t sm1 = sizeof(float) * ((size_t)g.D * kTilePx + 4 * kTilePx) + sizeof(int) * (4 * kTilePx + g.D);
+    const int RP = (r + kAssignRB - 1) / kAssignRB * kAssignRB;
+    hipLaunchKernelGGL(transpose_centroids_kernel, dim3((g.D * RP + 255) / 256), dim3(256), 0, s, c, r, g.D, RP,
+                       ct);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(assign_generic_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(assign_generic_kernel, dim3(grid_for(N, kTilePx, 8192)), dim3(kBlock), sm1, s, g, N, ct,
+                       RP, r, lab);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   const size_t acc_bytes = sizeof(float) * (size_t)r * (g.D + 1);
   const int use_lds = acc_bytes <= 96 * 1024;
   if (owned_applies(r, g.D)) {
@@ -540,7 +548,11 @@ static hipError_t assign_accumulate(const Guide &g, const float *c, int r, doubl
   return hipGetLastError();
 }
 
-size_t kmeans_transposed_floats(int r, int D) { return (size_t)D * (size_t)((r + kAssignRB - 1) / kAssignRB * kAssignRB); }
+size_t kmeans_transposed_floats(const Guide &g, int r) {
+  const size_t t = (size_t)g.D * (size_t)((r + kAssignRB - 1) / kAssignRB * kAssignRB);
+  const size_t m = assign_mfma32_supported(g, r) ? assign_mfma32_scratch_floats(g, r) : 0;
+  return t > m ? t : m;
+}
 
 size_t kmeans_partials_doubles(int r, int D) {
   // (the MFMA path: at most 256 blocks)

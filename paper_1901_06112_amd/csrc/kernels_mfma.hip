@@ -708,6 +708,139 @@ __global__ __launch_bounds__(BT) void lloyd_mfma_kernel(MArgs a) {
   }
 }
 
+// ---- FP32 assignment on the matrix cores (the FP32 form, D > 32) -----------
+// Labels of the FP32 form for wide guides with the tiles, staging, permuted
+// axis and argmin of the 16-bit k-means, the products p~.c~ on
+// v_mfma_f32_16x16x4f32 (FP32 operands and sums; 16 pixels x 16 landmarks x 4
+// dimensions per instruction) and the landmarks as FP32 [RP][DS] in LDS.  The
+// distances take the GEMM form |c~|^2 - 2 p~.c~ about an offset near the data,
+// landmark 0 of the current centroids (the distances do not depend on it), where
+// the VALU kernel sums (p - c)^2 directly; the labels differ from it only inside
+// the FP32 tie band.  Labels only: the FP32 form keeps its deterministic
+// owned-dimension cluster sums.
+__global__ __launch_bounds__(64) void prep_landmarks32_kernel(MArgs a, float *ctg, float *cn2g) {
+  const int k = blockIdx.x, lane = threadIdx.x, D = a.g.D;
+  float s = 0.0f;
+  for (int dd = lane; dd < a.DS; dd += 64) {
+    const int q = dd / a.RLP, el = dd - q * a.RLP;
+    float v = 0.0f;
+    if (k < a.r && q < a.NR && el < a.RL) {
+      const int d = q * a.RL + el;
+      v = a.c[k * D + d] - mu_of(a, d);
+    }
+    s = fmaf(v, v, s);
+    ctg[k * a.DS + dd] = v;
+  }
+  s = wave_sum(s);
+  if (lane == 0) cn2g[k] = k < a.r ? s : FLT_MAX;
+}
+
+// acc[t][i] = p~(pixel 16w + 4 rq + i) . c~(landmark 16t + col), FP32: lane
+// (row, kq) gives operand A = p~(pixel 16w + row, dimension 4s + kq) and B =
+// c~(landmark 16t + row, dimension 4s + kq) on the permuted axis.
+template <int NT>
+__device__ __forceinline__ void tile_products32(const MArgs &a, const float *raw, const int *tab_off,
+                                                const int *tab_nv, const float *ct, floatx4 (&acc)[NT]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int row = lane & 15, kq = lane >> 4;
+  const int pofs = (16 * w + row) * a.pxstride;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int nsteps = a.NR * a.RLP / 4;
+  for (int s = 0; s < nsteps; ++s) {
+    const int e = 4 * s + kq, q8 = e >> 3, o = e & 7;
+    const float lv = raw[tab_off[q8] + pofs + o];  // in bounds; past the chunk's valid count it is zeroed
+    const float av = o < tab_nv[q8] ? lv : 0.0f;
+    float bv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bv[t] = ct[(16 * t + row) * a.DS + e];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[t], acc[t], 0, 0, 0);
+  }
+}
+
+size_t assign32_lds(const MArgs &a) {
+  return sizeof(float) * ((size_t)a.RP * a.DS + a.raw_floats + 8 + a.RP) + sizeof(int) * 2 * kMaxChunks;
+}
+
+template <int NT, int BT, int PF>
+__global__ __launch_bounds__(BT) void assign_f32_kernel(MArgs a) {
+  constexpr int NW = BT / 64, TP = 16 * NW;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  float *ct = reinterpret_cast<float *>(smem_raw);                  // [RP][DS]
+  float *raw = ct + (size_t)a.RP * a.DS;                           // [raw_floats + 8]
+  float *cn2 = raw + a.raw_floats + 8;                             // [RP]
+  int *tab_off = reinterpret_cast<int *>(cn2 + a.RP);              // [kMaxChunks]
+  int *tab_nv = tab_off + kMaxChunks;                              // [kMaxChunks]
+  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int col = lane & 15, rq = lane >> 4;
+  {
+    const int n4 = a.RP * a.DS / 4;  // DS is a multiple of 8
+    const float4 *src = reinterpret_cast<const float4 *>(a.ctg);
+    float4 *dst = reinterpret_cast<float4 *>(ct);
+    for (int e = tid; e < n4; e += BT) dst[e] = src[e];
+    for (int k = tid; k < a.RP; k += BT) cn2[k] = a.cn2g[k];
+  }
+  build_tables(a, tab_off, tab_nv, nullptr, BT);
+  load_mu(a, raw_mu(a, raw), BT);
+  TilePrefetch<TP, BT> pre;
+  PatchPrefetch<TP, BT> ppre;
+  __syncthreads();  // the offsets in LDS before the first prefetch
+  if ((int)blockIdx.x < a.ntiles) {
+    if constexpr (PF == 1) pre.load(a, tile_info<TP>(a, blockIdx.x));
+    if constexpr (PF == 2) ppre.load(a, tile_info<TP>(a, blockIdx.x), raw_mu(a, raw));
+  }
+  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    const TileInfo ti = tile_info<TP>(a, t);
+    __syncthreads();
+    if constexpr (PF == 1)
+      pre.store(a, ti, raw, raw_mu(a, raw));
+    else if constexpr (PF == 2)
+      ppre.store(a, raw);
+    else
+      stage_raw<TP, BT>(a, ti, raw, raw_mu(a, raw));
+    __syncthreads();
+    if (t + (int)gridDim.x < a.ntiles) {
+      if constexpr (PF == 1) pre.load(a, tile_info<TP>(a, t + gridDim.x));
+      if constexpr (PF == 2) ppre.load(a, tile_info<TP>(a, t + gridDim.x), raw_mu(a, raw));
+    }
+    floatx4 acc[NT];
+    tile_products32<NT>(a, raw, tab_off, tab_nv, ct, acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float best = FLT_MAX;
+      int bi = 0x7fffffff;
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt) {
+        const int k = 16 * tt + col;
+        const float v = cn2[k] - 2.0f * acc[tt][i];  // padded landmarks: cn2 = FLT_MAX
+        const bool take = v < best;
+        best = take ? v : best;
+        bi = take ? k : bi;
+      }
+      row16_argmin(best, bi);
+      if (bi >= a.r) bi = 0;  // non-finite guide values: no comparison succeeded
+      const int pxl = 16 * w + 4 * rq + i;
+      if (col == 0 && pxl < ti.nvalid) a.labels[ti.x0 + pxl] = bi;
+    }
+  }
+}
+
+template <int NT>
+hipError_t launch_assign32_nt(const MArgs &a, size_t lds, hipStream_t s) {
+  constexpr int BT = 512, TP = 16 * BT / 64;
+  const int nb = a.ntiles < 1024 ? (a.ntiles < 1 ? 1 : a.ntiles) : 1024;
+  auto go = [&](auto kern) {
+    hipError_t e = set_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(BT), lds, s, a);
+    return hipGetLastError();
+  };
+  if (TilePrefetch<TP, BT>::usable(a)) return go(assign_f32_kernel<NT, BT, 1>);
+  if (PatchPrefetch<TP, BT>::usable(a)) return go(assign_f32_kernel<NT, BT, 2>);
+  return go(assign_f32_kernel<NT, BT, 0>);
+}
+
 // ---- embedding --------------------------------------------------------------
 // MAXT2: output tiles (16 planes of u) per wave.  The wave's rows of F^T stay
 // in registers when they fit (FREG), else they are read from memory.
@@ -1105,6 +1238,36 @@ bool mfma_path_supported(const Guide &g, int r, int prec) {
   size_t lds = 0;
   if (prec == 1) return plan_lloyd<1>(g, r).ok && plan_embed<1>(g, r, &lds) != 0;
   return plan_lloyd<2>(g, r).ok && plan_embed<2>(g, r, &lds) != 0;
+}
+
+bool assign_mfma32_supported(const Guide &g, int r) {
+  // narrow guides stay on the VALU kernel (PCA guide, D = 25: 104 -> 138 us per
+  // iteration on the matrix cores), as in the 16-bit forms
+  if (g.D <= 32 || r < 1 || r > 256) return false;
+  const MArgs a = make_args(g, nullptr, r, nullptr, 128);
+  return a.Dp / 8 <= kMaxChunks && assign32_lds(a) <= kLdsMax;
+}
+
+size_t assign_mfma32_scratch_floats(const Guide &g, int r) {
+  const MArgs a = make_args(g, nullptr, r, nullptr, 128);
+  return (size_t)a.RP * a.DS + a.RP;
+}
+
+hipError_t launch_assign_mfma32(const Guide &g, const float *c, int r, int *labels, float *scratch,
+                                hipStream_t s) {
+  if (!assign_mfma32_supported(g, r)) return hipErrorInvalidValue;
+  MArgs a = make_args(g, c, r, c, 128);  // centring offset: landmark 0
+  a.labels = labels;
+  float *ctg = scratch, *cn2g = scratch + (size_t)a.RP * a.DS;
+  a.ctg = ctg;
+  a.cn2g = cn2g;
+  hipLaunchKernelGGL(prep_landmarks32_kernel, dim3(a.RP), dim3(64), 0, s, a, ctg, cn2g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = assign32_lds(a);
+  if (a.RP == 64) return launch_assign32_nt<4>(a, lds, s);
+  if (a.RP == 128) return launch_assign32_nt<8>(a, lds, s);
+  return launch_assign32_nt<16>(a, lds, s);
 }
 
 size_t mfma_landmark_scratch_bytes(const Guide &g, int r) {

@@ -34,15 +34,24 @@ hipError_t launch_gather_landmarks(const Guide &g, const int64_t *idx, int r, fl
                                    hipStream_t s);
 // Size (doubles) of the per-block partial-sum buffer of one Lloyd step.
 size_t kmeans_partials_doubles(int r, int D);
-// Size (floats) of the transposed landmark copy [D][r rounded up to 8].
-size_t kmeans_transposed_floats(int r, int D);
+// Size (floats) of the landmark scratch of the FP32 assignment: the transposed
+// copy [D][r rounded up to 8] of the VALU kernel, or the prepared FP32 tile of
+// the matrix-core kernel, whichever is larger.
+size_t kmeans_transposed_floats(const Guide &g, int r);
 // One Lloyd iteration in place on c [r, D]: assignment (labels nullable),
 // per-block cluster sums into `partials`, ordered reduction and mean update;
-// ct is scratch of kmeans_transposed_floats(r, D) floats.
+// ct is scratch of kmeans_transposed_floats(g, r) floats.
 hipError_t launch_kmeans_step(const Guide &g, float *c, int r, double *partials, int *labels,
                               int *label_scratch, float *ct, hipStream_t s);
 
 // ---- kernels_mfma.hip -------------------------------------------------------
+// FP32 form, D > 32: labels of every pixel from the FP32 products on the matrix
+// cores (v_mfma_f32_16x16x4f32), when the FP32 landmark tile fits in LDS;
+// scratch holds assign_mfma32_scratch_floats(g, r) floats.
+bool assign_mfma32_supported(const Guide &g, int r);
+size_t assign_mfma32_scratch_floats(const Guide &g, int r);
+hipError_t launch_assign_mfma32(const Guide &g, const float *c, int r, int *labels, float *scratch,
+                                hipStream_t s);
 // Distance step on MFMA with 16-bit centred operands (prec 1 = BF16, 2 = FP16).
 // Whether the LDS plan of the 16-bit path fits this guide and landmark count.
 bool mfma_path_supported(const Guide &g, int r, int prec);
