@@ -63,11 +63,15 @@ enum { NKF_GUIDE_EXPLICIT = 0, NKF_GUIDE_SELF = 1, NKF_GUIDE_PATCH = 2 };
 /* Input precision of the distance / embedding contraction (k-means assignment
  * and the cross kernel B).  FP32 is the plain form; BF16 and FP16 round the
  * centred guide and landmarks to 16 bits and accumulate in FP32, with the
- * squared norms kept in FP32/FP64.  The Gaussian-window convolutions store
- * FP32 and accumulate each pass in FP64 in every form; the box window on up
- * to three channels keeps its window sums and the contraction in FP64, with
- * the embedding planes stored in FP64 in the plain form and FP32 in the
- * 16-bit forms. */
+ * squared norms kept in FP32/FP64 (the embedding's products as 16-bit hi + lo
+ * pairs).  On up to three channels the Gaussian-window convolutions store
+ * FP32 and accumulate each pass in FP64 in every form; on more channels the
+ * plain form does the same per channel, and the 16-bit forms evaluate each
+ * window as K_hat(x, y) = u(x).u(y) on the matrix cores (Eq. (num1) with
+ * K_hat, 16-bit hi + lo embedding operands, FP32 sums) when r <= 64, and
+ * like the plain form otherwise.  The box window on up to three channels keeps its window sums and
+ * the contraction in FP64, with the embedding planes stored in FP64 in the
+ * plain form and FP32 in the 16-bit forms. */
 enum { NKF_PREC_FP32 = 0, NKF_PREC_BF16 = 1, NKF_PREC_FP16 = 2 };
 
 typedef struct {
