@@ -448,10 +448,40 @@ def leg_pca_nlm(steps, warmup):
     return out
 
 
-def leg_diff(steps, warmup):
+def _on_streams(imgs, fn, streams):
+    """fn(img) for every image, image i on stream i mod len(streams) from its
+    own host thread (a library context per stream, created on first use; the
+    library's calls release the interpreter lock), so the small images of a
+    batch overlap on the GPU and one image's host finish of the sigma
+    gradients overlaps the others' work."""
+    import threading
+
+    import torch
+    nst = len(streams)
+    errors = []
+
+    def worker(t):
+        try:
+            with torch.cuda.stream(streams[t]):
+                for i in range(t, len(imgs), nst):
+                    fn(imgs[i])
+        except BaseException as e:  # re-raised on the calling thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(nst)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    if errors:
+        raise errors[0]
+
+
+def leg_diff(steps, warmup, nstreams=4):
     """Differentiation batch: eight images, landmarks fixed (k-means outside the
     timed region), forward and forward + hand-written backward (df, dp,
-    d sigma_r, d sigma_s), one call per image on one stream."""
+    d sigma_r, d sigma_s): one call per image, the images spread over
+    `nstreams` streams (the one-stream figures beside them)."""
     import numpy as np
     import torch
 
@@ -469,26 +499,38 @@ def leg_diff(steps, warmup):
     kw = dict(sigma_s=prm["sigma_s"], sigma_r=prm["sigma_r"], radius=prm["S"])
     npx = sum(h * w for h, w in sizes)
 
-    def fwd():
-        for ft, c, Q, al, F, reff, G in imgs:
-            nkf.filter_landmarks(ft, c, F, **kw)
+    def fwd_img(im):
+        ft, c, Q, al, F, reff, G = im
+        nkf.filter_landmarks(ft, c, F, **kw)
 
-    def fwdbwd():
+    def fwdbwd_img(im):
         # as the autograd function runs it: the backward reuses the forward's
         # output and eta_hat, and recomputes the embedding
-        for ft, c, Q, al, F, reff, G in imgs:
-            out, eta = nkf.filter_landmarks(ft, c, F, return_eta=True, **kw)
-            nkf.filter_backward(ft, c, Q, al, reff, G, out=out, eta=eta, **kw)
+        ft, c, Q, al, F, reff, G = im
+        out, eta = nkf.filter_landmarks(ft, c, F, return_eta=True, **kw)
+        nkf.filter_backward(ft, c, Q, al, reff, G, out=out, eta=eta, **kw)
 
-    ms_f, _, _ = _timed(fwd, steps, warmup)
-    ms_b, _, _ = _timed(fwdbwd, steps, warmup)
+    ms_f1, _, _ = _timed(lambda: [fwd_img(im) for im in imgs], steps, warmup)
+    ms_b1, _, _ = _timed(lambda: [fwdbwd_img(im) for im in imgs], steps, warmup)
+    streams = [torch.cuda.Stream() for _ in range(nstreams)]  # default priority
+    stream_error = None
+    try:
+        ms_f, _, _ = _timed(lambda: _on_streams(imgs, fwd_img, streams), steps, warmup)
+        ms_b, _, _ = _timed(lambda: _on_streams(imgs, fwdbwd_img, streams), steps, warmup)
+    except Exception as e:  # reported in the line; the one-stream figures stand
+        torch.cuda.synchronize()
+        stream_error = f"{type(e).__name__}: {e}"
+        ms_f, ms_b, nstreams = ms_f1, ms_b1, 1
     T = 2 * prm["S"] + 1
     fl_f = sum(fwd_flops_per_pixel(im[5], prm["r"], 3, 3, T) * im[0].shape[0] * im[0].shape[1] for im in imgs)
     fl_fb = fl_f + sum(bwd_flops_per_pixel(im[5], prm["r"], 3, 3, T) * im[0].shape[0] * im[0].shape[1]
                        for im in imgs)
     return {"images": [list(s) for s in sizes], "pixels": npx, "r": prm["r"], "S": prm["S"],
+            "streams": nstreams,
             "fwd_ms": round(ms_f, 3), "fwd_Mpixel_s": round(npx / ms_f / 1e3, 2),
             "fwd_bwd_ms": round(ms_b, 3), "fwd_bwd_Mpixel_s": round(npx / ms_b / 1e3, 2),
+            "one_stream": {"fwd_ms": round(ms_f1, 3), "fwd_bwd_ms": round(ms_b1, 3)},
+            "stream_error": stream_error,
             "roofline": {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS,
                          "fwd_achieved": round(fl_f / (ms_f * 1e-3) / 1e12, 2),
                          "fwd_frac": round(fl_f / (ms_f * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),

@@ -41,6 +41,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <atomic>
 #include <math.h>
 
 #include "device_common.h"
@@ -608,16 +610,19 @@ __global__ __launch_bounds__(BT) void conv_kernel(ConvArgs a) {
   }
 }
 
-// Compute units of the current device (cached per device).
+// Compute units of the current device (cached per device; contexts on other
+// host threads may fill the cache concurrently, each storing the same value).
 inline int device_cus() {
-  static int cus[64] = {0};
+  static std::atomic<int> cus[64] = {};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (cus[dev] == 0) {
+  int v = cus[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
     int n = 0;
-    cus[dev] = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0 ? n : 256;
+    v = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0 ? n : 256;
+    cus[dev].store(v, std::memory_order_relaxed);
   }
-  return cus[dev];
+  return v;
 }
 
 // Tile geometry and launch of one kernel instantiation.
