@@ -23,6 +23,17 @@ namespace {
 
 inline double sgn(double x) { return x < 0.0 ? -1.0 : 1.0; }
 
+// a . b over n entries in four partial sums (a single running sum is a chain
+// of dependent FMAs, bound by their latency)
+inline double dot4(const double *a, const double *b, int n) {
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  int i = 0;
+  for (; i + 4 <= n; i += 4)
+    for (int u = 0; u < 4; ++u) s[u] += a[i + u] * b[i + u];
+  for (; i < n; ++i) s[0] += a[i] * b[i];
+  return (s[0] + s[1]) + (s[2] + s[3]);
+}
+
 }  // namespace
 
 namespace {
@@ -71,12 +82,18 @@ int sym_eig_impl(int n, const double *A, double *w, double *V) {
     for (int i = 0; i < m; ++i) {
       const double *row = &T[(k + 1 + i) * n + (k + 1)];
       const double vi = v[i];
-      double acc = 0.0;
-      for (int j = 0; j < i; ++j) {
-        acc += row[j] * v[j];
+      double a4[4] = {0.0, 0.0, 0.0, 0.0};  // the row's dot product in four partial sums (dot4)
+      int j = 0;
+      for (; j + 4 <= i; j += 4)
+        for (int u = 0; u < 4; ++u) {
+          a4[u] += row[j + u] * v[j + u];
+          p[j + u] += row[j + u] * vi;
+        }
+      for (; j < i; ++j) {
+        a4[0] += row[j] * v[j];
         p[j] += row[j] * vi;
       }
-      p[i] += acc + row[i] * vi;
+      p[i] += ((a4[0] + a4[1]) + (a4[2] + a4[3])) + row[i] * vi;
     }
     for (int i = 0; i < m; ++i) p[i] *= beta;
     double ptv = 0.0;
@@ -258,12 +275,18 @@ int sym_eig_top(int n, const double *A, int k, double *w, double *V) {
     for (int i = 0; i < m; ++i) {
       const double *row = &T[(kk + 1 + i) * n + (kk + 1)];
       const double vi = v[i];
-      double acc = 0.0;
-      for (int j = 0; j < i; ++j) {
-        acc += row[j] * v[j];
+      double a4[4] = {0.0, 0.0, 0.0, 0.0};  // the row's dot product in four partial sums (dot4)
+      int j = 0;
+      for (; j + 4 <= i; j += 4)
+        for (int u = 0; u < 4; ++u) {
+          a4[u] += row[j + u] * v[j + u];
+          p[j + u] += row[j + u] * vi;
+        }
+      for (; j < i; ++j) {
+        a4[0] += row[j] * v[j];
         p[j] += row[j] * vi;
       }
-      p[i] += acc + row[i] * vi;
+      p[i] += ((a4[0] + a4[1]) + (a4[2] + a4[3])) + row[i] * vi;
     }
     for (int i = 0; i < m; ++i) p[i] *= beta;
     double ptv = 0.0;
@@ -413,9 +436,7 @@ int sym_eig_top(int n, const double *A, int k, double *w, double *V) {
       if (betas[kk] == 0.0) continue;
       const int m = n - kk - 1;
       const double *v = &R[(size_t)kk * n];
-      double dot = 0.0;
-      for (int i = 0; i < m; ++i) dot += v[i] * xv[kk + 1 + i];
-      dot *= betas[kk];
+      double dot = dot4(v, xv + kk + 1, m) * betas[kk];
       for (int i = 0; i < m; ++i) xv[kk + 1 + i] -= dot * v[i];
     }
     const int col = k - 1 - j;
