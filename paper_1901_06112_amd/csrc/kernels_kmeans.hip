@@ -4,9 +4,11 @@
 // One Lloyd iteration = assignment (nearest centroid, ties to the lowest
 // index) fused with the per-cluster sums, then the mean update.  Small guide
 // dimensions (D <= 4, explicit or self guide) run one pixel per lane with the
-// centroids in LDS; larger D (hyperspectral bands, NLM patches) use an LDS
-// pixel tile and register-blocked distances, then a separate accumulation
-// pass.  The 16-bit precision form of the assignment is in kernels_mfma.hip.
+// centroids in LDS; larger D use a labels pass, then a separate accumulation
+// pass: for D > 32 (hyperspectral bands, NLM patches) the labels come from
+// FP32 products on the matrix cores (kernels_mfma.hip), else from an LDS pixel
+// tile with register-blocked distances on the VALU (below).  The 16-bit
+// precision forms' k-means is in kernels_mfma.hip.
 #include <hip/hip_runtime.h>
 #include <float.h>
 
@@ -139,7 +141,8 @@ __global__ void transpose_centroids_kernel(const float *__restrict__ c, int r, i
   ct[e] = k < r ? c[k * D + d] : 0.0f;
 }
 
-// Nearest landmark of every pixel for any D (Algorithm 1, assignment): a
+// Nearest landmark of every pixel for any D (Algorithm 1, assignment; used for
+// D <= 32 and when the matrix-core form's landmark tile does not fit LDS): a
 // 64-pixel tile staged in LDS as [D][64]; wave kg scans the contiguous
 // cluster range [kg CW, (kg + 1) CW) (CW a multiple of kAssignRB) with the
 // landmarks transposed, so the clusters of a register block are 16-byte
