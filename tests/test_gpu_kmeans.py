@@ -56,11 +56,13 @@ def _near_tie(P, c, rel=2e-5):
 # hyper and patch: D + 1 > 64 (64-dimension slices); hyper with r = 256: the
 # FP32 sums do not fit in LDS (FP64 sums in the block's slot); patch2 (5x5x3
 # patches, D + 1 = 76): three pixel stripes per block in the sums, each
-# crossing image rows of an odd width
+# crossing image rows of an odd width.  The FP32 labels of D > 32 come from the
+# matrix cores: 4, 8 and 16 landmark tiles (r = 64, 128, 256 with patch2); hyper
+# with r = 256 does not fit their LDS tile and takes the VALU kernel
 @pytest.mark.parametrize("kind,h,w,r", [("self3", 70, 90, 32), ("explicit2", 64, 64, 8),
                                          ("explicit25", 50, 46, 31), ("hyper", 40, 36, 64),
                                          ("hyper", 40, 36, 256), ("patch", 48, 40, 128),
-                                         ("patch2", 37, 53, 16)])
+                                         ("patch2", 37, 53, 16), ("patch2", 41, 47, 256)])
 def test_seed_and_one_lloyd_step(kind, h, w, r):
     nkf = _nkf()
     f, p, guide, P = _case(kind, h, w)
