@@ -47,6 +47,7 @@ __global__ void gather_kernel(Guide g, const int64_t *__restrict__ idx, int r,
 // wave's atomics on the same words.  The sets (stride padded by one double so
 // that they start on different banks) are summed in a fixed order at the end.
 constexpr int kSmallCopiesMax = 32;
+constexpr int kSmallPx = 4;  // pixels per thread and pass of the small-D assignment
 constexpr size_t kSmallCopiesLds = 64 * 1024;
 
 template <int D>
@@ -72,48 +73,48 @@ __global__ __launch_bounds__(kBlock) void assign_small_kernel(const float *__res
   }
   for (int i = tid; i < ncopy * cstride; i += kBlock) sacc_all[i] = 0.0;
   __syncthreads();
-  // two pixels per thread per pass share each centroid read and interleave
-  // two independent distance chains
+  // kSmallPx pixels per thread per pass share each centroid read and
+  // interleave independent distance chains
+  constexpr int PX = kSmallPx;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t x0 = (int64_t)blockIdx.x * kBlock + tid; x0 < N; x0 += 2 * stride) {
-    const int64_t x1 = x0 + stride;
-    const bool v1 = x1 < N;
-    float pv0[D], pv1[D];
+  for (int64_t xb = (int64_t)blockIdx.x * kBlock + tid; xb < N; xb += PX * stride) {
+    float pv[PX][D];
+    bool vv[PX];
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-      pv0[j] = P[x0 * D + j];
-      pv1[j] = v1 ? P[x1 * D + j] : 0.0f;
+    for (int q = 0; q < PX; ++q) {
+      const int64_t x = xb + q * stride;
+      vv[q] = x < N;
+#pragma unroll
+      for (int j = 0; j < D; ++j) pv[q][j] = vv[q] ? P[x * D + j] : 0.0f;
     }
-    float b0 = FLT_MAX, b1 = FLT_MAX;
-    int i0 = 0, i1 = 0;
+    float b[PX];
+    int bi[PX];
+#pragma unroll
+    for (int q = 0; q < PX; ++q) b[q] = FLT_MAX, bi[q] = 0;
     for (int k = 0; k < r; ++k) {
-      float d0 = sc[k * DS + D], d1 = d0;
+      float d[PX];
+#pragma unroll
+      for (int q = 0; q < PX; ++q) d[q] = sc[k * DS + D];
 #pragma unroll
       for (int j = 0; j < D; ++j) {
         const float cj = sc[k * DS + j];
-        d0 = fmaf(pv0[j], cj, d0);
-        d1 = fmaf(pv1[j], cj, d1);
+#pragma unroll
+        for (int q = 0; q < PX; ++q) d[q] = fmaf(pv[q][j], cj, d[q]);
       }
-      if (d0 < b0) {
-        b0 = d0;
-        i0 = k;
-      }
-      if (d1 < b1) {
-        b1 = d1;
-        i1 = k;
-      }
-    }
-    if (labels) {
-      labels[x0] = i0;
-      if (v1) labels[x1] = i1;
+#pragma unroll
+      for (int q = 0; q < PX; ++q)
+        if (d[q] < b[q]) {
+          b[q] = d[q];
+          bi[q] = k;
+        }
     }
 #pragma unroll
-    for (int j = 0; j < D; ++j) atomicAdd(&sacc[i0 * (D + 1) + j], (double)pv0[j]);
-    atomicAdd(&sacc[i0 * (D + 1) + D], 1.0);
-    if (v1) {
+    for (int q = 0; q < PX; ++q) {
+      if (!vv[q]) continue;
+      if (labels) labels[xb + q * stride] = bi[q];
 #pragma unroll
-      for (int j = 0; j < D; ++j) atomicAdd(&sacc[i1 * (D + 1) + j], (double)pv1[j]);
-      atomicAdd(&sacc[i1 * (D + 1) + D], 1.0);
+      for (int j = 0; j < D; ++j) atomicAdd(&sacc[bi[q] * (D + 1) + j], (double)pv[q][j]);
+      atomicAdd(&sacc[bi[q] * (D + 1) + D], 1.0);
     }
   }
   __syncthreads();
