@@ -90,6 +90,8 @@ __global__ __launch_bounds__(BT) void embed_kernel(Guide g, int64_t N, const flo
       double pv[DS > 0 ? DS : 1];
 #pragma unroll
       for (int d = 0; d < DS; ++d) pv[d] = valid ? (double)guide_elem(g, x, d) : 0.0;
+      // two landmarks in flight per thread hide the FP64 exponential's latency
+#pragma unroll 2
       for (int k = kg; k < r; k += NG) {
         double acc = 0.0;
 #pragma unroll
