@@ -17,6 +17,8 @@ High-Dimensional Kernel Filtering", that it follows):
                   Algorithm 1 in the paper's own alpha_k / v_k form, plus a
                   per-pixel evaluation of the same approximation before the sum
                   switch, and small dense K / K-hat matrices.
+* ``recursive``-- Young and van Vliet's recursive Gaussian (Section IV's O(1)
+                  Gaussian filter) with zero extension at the borders.
 * ``grad``     -- an independent float64 autograd formulation (symmetric
                   A^{-1/2} form) used as the gradient reference, and central
                   finite differences.

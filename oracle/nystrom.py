@@ -21,6 +21,7 @@ from __future__ import annotations
 import numpy as np
 
 from .exact import range_kernel_sqdist, spatial_taps
+from .recursive import recursive_gauss_2d
 
 DEFAULT_TAU = 1e-10
 
@@ -87,6 +88,16 @@ def conv_zero(img, w1):
     return out
 
 
+def spatial_filter(sigma_s, S, spatial):
+    """img -> (w * img): the truncated window of radius S ("gaussian", "box"),
+    or Young and van Vliet's recursive Gaussian ("recursive", S unused; see
+    ``oracle.recursive``)."""
+    if spatial == "recursive":
+        return lambda img: recursive_gauss_2d(img, sigma_s)
+    w1 = spatial_taps(sigma_s, S, spatial)
+    return lambda img: conv_zero(img, w1)
+
+
 def nystrom_filter(f, p, c, sigma_s, sigma_r, S, spatial="gaussian", tau=DEFAULT_TAU,
                    return_eta=False):
     """The fast filter of Section III with given landmarks ``c`` [r, D].
@@ -104,7 +115,7 @@ def nystrom_filter(f, p, c, sigma_s, sigma_r, S, spatial="gaussian", tau=DEFAULT
     f = np.asarray(f, np.float64)
     p = np.asarray(p, np.float64)
     H, W, C = f.shape
-    w1 = spatial_taps(sigma_s, S, spatial)
+    conv = spatial_filter(sigma_s, S, spatial)
     # all extrapolated eigenvectors at once: column k of V is v_k over the pixels
     alpha, V = extrapolated_eigvecs(c, p.reshape(H * W, -1), sigma_r, tau)
     V = V.reshape(H, W, -1)
@@ -112,8 +123,8 @@ def nystrom_filter(f, p, c, sigma_s, sigma_r, S, spatial="gaussian", tau=DEFAULT
     eta = np.zeros((H, W))
     for k, a_k in enumerate(alpha):
         v = V[:, :, k]
-        zeta += a_k * v[:, :, None] * conv_zero(v[:, :, None] * f, w1)
-        eta += a_k * v * conv_zero(v, w1)
+        zeta += a_k * v[:, :, None] * conv(v[:, :, None] * f)
+        eta += a_k * v * conv(v)
     with np.errstate(invalid="ignore", divide="ignore"):
         g = zeta / eta[:, :, None]
     # eta_hat carries no positivity guarantee: such pixels keep f(x)
