@@ -55,7 +55,20 @@ typedef enum {
   NKF_ERR_UNSUPPORTED = 5    /* valid request outside what this build implements    */
 } nkf_status;
 
-enum { NKF_SPATIAL_GAUSSIAN = 0, NKF_SPATIAL_BOX = 1 };
+/* Spatial kernels.  GAUSSIAN and BOX are the truncated windows of radius S.
+ * RECURSIVE is the O(1) recursive Gaussian of Young and van Vliet (Signal
+ * Processing 44, 1995) that Section IV uses for the Gaussian window: their
+ * third-order recursion run forwards and then backwards along each row and
+ * column, with their fit of the scale q to sigma_s (0.5 <= sigma_s <= 1000,
+ * else NKF_ERR_INVALID_ARG).  Its response is not truncated (radius is
+ * ignored) and approximates the Gaussian to within a few percent of its peak
+ * (about 10% wider in variance).  The image is extended by zeros, so each
+ * filtered line is that response convolved with the line.  Up to three
+ * channels (else NKF_ERR_UNSUPPORTED); forward calls only (the backward
+ * returns NKF_ERR_UNSUPPORTED).  Work and memory do not grow with sigma_s:
+ * the filtered planes take 2 r_eff (C + 1) H W' floats of workspace, W' = W
+ * rounded up to 16. */
+enum { NKF_SPATIAL_GAUSSIAN = 0, NKF_SPATIAL_BOX = 1, NKF_SPATIAL_RECURSIVE = 2 };
 /* Guide kinds: EXPLICIT = caller passes p [H, W, D]; SELF = p is f (D == C);
  * PATCH = nonlocal-means guide, the (2pr+1)^2 * C patch of f around each pixel
  * in (dy, dx, c) order, read from a symmetrically padded f (Section II, NLM). */
@@ -75,10 +88,12 @@ enum { NKF_GUIDE_EXPLICIT = 0, NKF_GUIDE_SELF = 1, NKF_GUIDE_PATCH = 2 };
 enum { NKF_PREC_FP32 = 0, NKF_PREC_BF16 = 1, NKF_PREC_FP16 = 2 };
 
 typedef struct {
-  double sigma_s;          /* spatial Gaussian width, > 0 (ignored by BOX except for radius = -1) */
+  double sigma_s;          /* spatial Gaussian width, > 0 (ignored by BOX except for radius = -1;
+                              RECURSIVE: 0.5 .. 1000)                                             */
   double sigma_r;          /* range kernel width, > 0; +INFINITY means k == 1                     */
   int r;                   /* landmarks, 1 <= r <= min(N, 256)                                  */
-  int radius;              /* window radius S, 0 <= S <= 16; -1 means ceil(3 sigma_s)           */
+  int radius;              /* window radius S, 0 <= S <= 16; -1 means ceil(3 sigma_s); unused by
+                              RECURSIVE                                                          */
   int spatial;             /* NKF_SPATIAL_*                                                      */
   int guide;               /* NKF_GUIDE_*                                                        */
   int patch_radius;        /* PATCH guide only: pr >= 0, D must equal C (2pr+1)^2                */
@@ -284,7 +299,8 @@ nkf_status nkf_seed_indices(int64_t N, int r, uint64_t seed, int64_t *idx_host);
 
 /* Host-only: the window radius the library uses for (radius, sigma_s) and
  * the one-dimensional taps w1[0 .. 2S] (float32, as uploaded).  taps_host
- * nullable; returns S via *S_out. */
+ * nullable; returns S via *S_out.  NKF_ERR_UNSUPPORTED for RECURSIVE, which
+ * has no taps. */
 nkf_status nkf_spatial_taps(int radius, double sigma_s, int spatial, int *S_out, float *taps_host);
 
 #ifdef __cplusplus

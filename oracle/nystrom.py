@@ -199,7 +199,7 @@ def storage_error_bound(f, p, c, sigma_s, sigma_r, S, spatial="gaussian", tau=DE
     H, W, C = f.shape
     f0 = 0.5 * (f.min(axis=(0, 1)) + f.max(axis=(0, 1))) if center is None else center
     fc = f - f0
-    w1 = spatial_taps(sigma_s, S, spatial)
+    conv = spatial_filter(sigma_s, S, spatial)
     alpha, Wv = landmark_eig(c, sigma_r, tau)
     Fm = Wv / np.sqrt(alpha)[None, :]
     bx = cross_kernel_sr(c, p.reshape(H * W, -1), sigma_r)
@@ -212,10 +212,10 @@ def storage_error_bound(f, p, c, sigma_s, sigma_r, S, spatial="gaussian", tau=DE
     for k in range(U.shape[1]):
         uk = U[:, k].reshape(H, W)
         vk = Vm[:, k].reshape(H, W)
-        eta += uk * conv_zero(uk, w1)
-        eabs += vk * conv_zero(vk, w1)
-        zeta += uk[:, :, None] * conv_zero(uk[:, :, None] * fc, w1)
-        zabs += vk[:, :, None] * conv_zero(vk[:, :, None] * np.abs(fc), w1)
+        eta += uk * conv(uk)
+        eabs += vk * conv(vk)
+        zeta += uk[:, :, None] * conv(uk[:, :, None] * fc)
+        zabs += vk[:, :, None] * conv(vk[:, :, None] * np.abs(fc))
     with np.errstate(divide="ignore", invalid="ignore"):
         gt = zeta / eta[:, :, None]
         B = (zabs + np.abs(gt) * eabs[:, :, None]) / np.abs(eta)[:, :, None]

@@ -33,6 +33,7 @@ SOURCES = [
     "kernels_embed.hip",
     "kernels_conv.hip",
     "kernels_box.hip",
+    "kernels_rec.hip",
     "kernels_wk.hip",
     "kernels_bwd.hip",
     "kernels_mfma.hip",

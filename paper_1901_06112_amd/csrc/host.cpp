@@ -295,6 +295,8 @@ struct Resolved {
   Guide g;
   Taps taps;
   int box;  // spatial kernel is the box
+  int rec;  // spatial kernel is the recursive Gaussian
+  RecCoef rc;
 };
 
 // Validation shared by every device entry point.
@@ -313,14 +315,23 @@ nkf_status validate(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, co
   if (C > 1024) return fail(ctx, NKF_ERR_UNSUPPORTED, "C=%d exceeds 1024", C);
   if (!(prm->sigma_r > 0.0) || isnan(prm->sigma_r))
     return fail(ctx, NKF_ERR_INVALID_ARG, "sigma_r must be > 0 (got %g)", prm->sigma_r);
-  if (prm->spatial != NKF_SPATIAL_GAUSSIAN && prm->spatial != NKF_SPATIAL_BOX)
+  if (prm->spatial != NKF_SPATIAL_GAUSSIAN && prm->spatial != NKF_SPATIAL_BOX &&
+      prm->spatial != NKF_SPATIAL_RECURSIVE)
     return fail(ctx, NKF_ERR_INVALID_ARG, "unknown spatial kernel %d", prm->spatial);
-  if (prm->spatial == NKF_SPATIAL_GAUSSIAN || prm->radius < 0) {
+  const bool rec = prm->spatial == NKF_SPATIAL_RECURSIVE;
+  RecCoef rc{};
+  if (rec) {
+    if (!rec_coefficients(prm->sigma_s, &rc))
+      return fail(ctx, NKF_ERR_INVALID_ARG, "the recursive Gaussian needs %g <= sigma_s <= %g (got %g)",
+                  kRecSigmaMin, kRecSigmaMax, prm->sigma_s);
+    if (C > 3) return fail(ctx, NKF_ERR_UNSUPPORTED, "the recursive Gaussian supports C <= 3 (got %d)", C);
+  } else if (prm->spatial == NKF_SPATIAL_GAUSSIAN || prm->radius < 0) {
     if (!(prm->sigma_s > 0.0) || !isfinite(prm->sigma_s))
       return fail(ctx, NKF_ERR_INVALID_ARG, "sigma_s must be finite and > 0 (got %g)", prm->sigma_s);
   }
   if (prm->radius < -1) return fail(ctx, NKF_ERR_INVALID_ARG, "radius must be >= -1");
-  const int S = resolve_radius(prm->radius, prm->sigma_s);
+  // the recursive filter has no window: radius is unused
+  const int S = rec ? 0 : resolve_radius(prm->radius, prm->sigma_s);
   if (S > kMaxRadius)
     return fail(ctx, NKF_ERR_UNSUPPORTED, "window radius %d exceeds %d", S, kMaxRadius);
   const int64_t N = (int64_t)H * W;
@@ -371,6 +382,8 @@ nkf_status validate(nkf_ctx *ctx, int H, int W, int C, const float *f, int D, co
   rs.N = N;
   rs.g = g;
   rs.box = prm->spatial == NKF_SPATIAL_BOX;
+  rs.rec = rec;
+  rs.rc = rc;
   for (int t = 0; t < 2 * kMaxRadius + 1; ++t) rs.taps.w[t] = 0.0f;
   for (int t = -S; t <= S; ++t)
     rs.taps.w[t + S] = prm->spatial == NKF_SPATIAL_BOX
@@ -474,6 +487,7 @@ struct FwdBufs {
   float *eta_stat;  // eta_hat for the statistics when the caller passes no eta_out
   void *wk;         // operands of the windowed MFMA form (16-bit forms, C > 3), else null
   float *bsplit;    // cross-kernel tiles of the split 16-bit embedding (nkf_filter), else null
+  float *rec;       // filtered planes of the recursive Gaussian, else null
 };
 
 // The 16-bit forms on more than three channels evaluate the windows on MFMA
@@ -500,6 +514,7 @@ void carve_fwd(Carve &cv, const Resolved &rs, int r_eff, FwdBufs &b, int r, bool
   b.eta_stat = cv.take<float>(stats ? rs.N : 1);
   b.wk = wk_r ? static_cast<void *>(cv.take<unsigned char>(wk_scratch_bytes(rs.H, rs.W, rs.C, wk_r))) : nullptr;
   b.bsplit = split_prec ? cv.take<float>(embed_split_floats(rs.g, r_eff, split_prec)) : nullptr;
+  b.rec = rs.rec ? cv.take<float>(rec_plane_floats(rs.H, rs.W, rs.C, r_eff)) : nullptr;
 }
 
 // The landmark-independent part of the forward: the centring offsets f0,
@@ -557,6 +572,26 @@ nkf_status run_fwd(nkf_ctx *ctx, const Resolved &rs, const nkf_params *prm, cons
   // eta_hat for the statistics: the caller's, else the library's copy
   const bool want_stats = ctx->stats && ctx->dstat && stats_ok;
   if (want_stats && !eta_out) eta_out = b.eta_stat;
+  if (rs.rec) {
+    RecProblem rp{};
+    rp.H = rs.H;
+    rp.W = rs.W;
+    rp.C = rs.C;
+    rp.r_eff = r_eff;
+    rp.coef = rs.rc;
+    rp.f = rs.g.f;
+    rp.f0 = b.f0;
+    rp.u = b.u;
+    rp.out = out;
+    rp.eta_out = eta_out;
+    rp.planes = b.rec;
+    {
+      StageTimer tm(ctx, NKF_STAGE_CONV);
+      HIP_TRY(ctx, launch_rec(rp, ctx->stream));
+    }
+    if (want_stats) HIP_TRY(ctx, launch_eta_stats(eta_out, rs.N, ctx->dstat, ctx->stream));
+    return NKF_OK;
+  }
   if (box_path(rs)) {
     BoxProblem bx{};
     bx.H = rs.H;
@@ -875,6 +910,8 @@ nkf_status nkf_spatial_taps(int radius, double sigma_s, int spatial, int *S_out,
   if (radius < -1) return fail(nullptr, NKF_ERR_INVALID_ARG, "radius must be >= -1");
   if ((spatial == NKF_SPATIAL_GAUSSIAN || radius < 0) && !(sigma_s > 0.0 && isfinite(sigma_s)))
     return fail(nullptr, NKF_ERR_INVALID_ARG, "sigma_s must be finite and > 0");
+  if (spatial == NKF_SPATIAL_RECURSIVE)
+    return fail(nullptr, NKF_ERR_UNSUPPORTED, "the recursive Gaussian has no taps");
   if (spatial != NKF_SPATIAL_GAUSSIAN && spatial != NKF_SPATIAL_BOX)
     return fail(nullptr, NKF_ERR_INVALID_ARG, "unknown spatial kernel");
   const int S = resolve_radius(radius, sigma_s);
@@ -1151,6 +1188,7 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
     return fail(ctx, NKF_ERR_INVALID_ARG, "centroids, eigvecs_host, eigvals_host and grad_out are required");
   if (r_eff < 1 || r_eff > r) return fail(ctx, NKF_ERR_INVALID_ARG, "need 1 <= r_eff <= r");
   if (C > 3) return fail(ctx, NKF_ERR_UNSUPPORTED, "backward supports C <= 3 (got %d)", C);
+  if (rs.rec) return fail(ctx, NKF_ERR_UNSUPPORTED, "backward of the recursive Gaussian is not implemented");
   if (r > 64) return fail(ctx, NKF_ERR_UNSUPPORTED, "backward supports r <= 64 (got %d)", r);
   if (grad_p && rs.g.kind == GUIDE_PATCH)
     return fail(ctx, NKF_ERR_UNSUPPORTED, "guide gradient of the patch guide is not implemented");

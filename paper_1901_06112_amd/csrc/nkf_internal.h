@@ -140,6 +140,29 @@ int box_splits(int H, int W, int S, int r_eff, int num_cu, int u_fp64);
 size_t box_partials_doubles(int H, int W, int S, int r_eff, int num_cu, int u_fp64);
 hipError_t launch_box(const BoxProblem &pb, hipStream_t s);
 
+// ---- kernels_rec.hip --------------------------------------------------------
+// Recursive-Gaussian (Young and van Vliet) convolutions + contraction +
+// normalisation for C <= 3: parallel-form coefficients of the cascade.
+struct RecCoef {
+  double n0, n1, n2, n3;  // numerator of the causal half
+  double a1, a2, a3;      // feedback of the cascade's recursion
+};
+constexpr double kRecSigmaMin = 0.5, kRecSigmaMax = 1000.0;
+// False when sigma_s is outside [kRecSigmaMin, kRecSigmaMax].
+bool rec_coefficients(double sigma_s, RecCoef *c);
+struct RecProblem {
+  int H, W, C, r_eff;
+  RecCoef coef;
+  const float *f;     // [H, W, C]
+  const float *f0;    // [C] centring offsets
+  const float *u;     // [r_eff][N]
+  float *out;         // [H, W, C]
+  float *eta_out;     // nullable [N]
+  float *planes;      // rec_plane_floats(...) floats: the filtered planes
+};
+size_t rec_plane_floats(int H, int W, int C, int r_eff);
+hipError_t launch_rec(const RecProblem &pb, hipStream_t s);
+
 // ---- kernels_wk.hip ---------------------------------------------------------
 // Windowed Nystrom-kernel evaluation on MFMA for many channels (16-bit forms):
 // K_hat = U_keys U_queries^T per window, then zeta = (w K_hat)^T (f - f0).

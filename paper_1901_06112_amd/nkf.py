@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libnkf.so")
 NKF_OK, NKF_ERR_INVALID_ARG, NKF_ERR_OUT_OF_MEMORY, NKF_ERR_HIP, NKF_ERR_NUMERICAL, NKF_ERR_UNSUPPORTED = range(6)
 _STATUS = {1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "HIP", 4: "NUMERICAL", 5: "UNSUPPORTED"}
 
-SPATIAL = {"gaussian": 0, "box": 1}
+SPATIAL = {"gaussian": 0, "box": 1, "recursive": 2}
 GUIDE = {"explicit": 0, "self": 1, "patch": 2}
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
 

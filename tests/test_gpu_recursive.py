@@ -1,0 +1,160 @@
+"""GPU parity of the recursive-Gaussian path (Young and van Vliet's O(1)
+filter, the Gaussian of Section IV) against the FP64 oracle.
+
+Landmarks are fixed on both sides (the oracle's k-means result rounded to
+float32); the FP64 factor comes from the library's host routine.  Bar: max
+|g_gpu - g_oracle| <= 1e-4 on the 0-255 scale on every pixel whose first-order
+FP32 storage bound is below that, and within the bound elsewhere (the filtered
+planes are stored as FP32 between the column and row passes, as the truncated
+window's row ring is).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import kmeans, nystrom, recursive, seeding
+from paper_1901_06112_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_255 = 1e-4
+# one FP32 rounding of u, of the column-filtered planes, of the row sweep's
+# first half and of its sum
+EPS_STORE = 4 * 2.0 ** -24
+
+
+def _nkf():
+    from paper_1901_06112_amd import nkf
+    nkf.load_library()
+    return nkf
+
+
+def _landmarks(P, r, seed, iters):
+    c0 = P[seeding.distinct_indices(P.shape[0], r, seed)]
+    c, _, _ = kmeans.lloyd(P, c0, iters)
+    return c.astype(np.float32)
+
+
+def _run(f, p, c32, sigma_s, sigma_r, guide="explicit"):
+    nkf = _nkf()
+    _, _, F, reff = nkf.landmark_factor(c32.astype(np.float64), sigma_r)
+    ft = torch.from_numpy(np.ascontiguousarray(f, np.float32)).cuda()
+    pt = torch.from_numpy(np.ascontiguousarray(p, np.float32)).cuda() if guide == "explicit" else None
+    g, eta = nkf.filter_landmarks(ft, torch.from_numpy(c32).cuda(), F, pt, sigma_s=sigma_s, sigma_r=sigma_r,
+                                  spatial="recursive", guide=guide, return_eta=True)
+    torch.cuda.synchronize()
+    return g.cpu().numpy().astype(np.float64), eta.cpu().numpy().astype(np.float64), reff
+
+
+def _check(name, f, p, c32, sigma_s, sigma_r, g, region=None):
+    """1e-4 where the FP32 storage bound is below 1e-4, the bound elsewhere;
+    ``region`` = (y0, y1, x0, x1) restricts the comparison to a sub-window."""
+    f64, p64 = np.asarray(f, np.float64), np.asarray(p, np.float64)
+    go = nystrom.nystrom_filter(f64, p64, c32.astype(np.float64), sigma_s, sigma_r, 0, "recursive")
+    B = nystrom.storage_error_bound(f64, p64, c32.astype(np.float64), sigma_s, sigma_r, 0, "recursive")
+    if region is not None:
+        y0, y1, x0, x1 = region
+        go, B, g = go[y0:y1, x0:x1], B[y0:y1, x0:x1], g[y0:y1, x0:x1]
+    bound = EPS_STORE * B
+    err = np.abs(g - go)
+    well = bound <= TOL_255
+    n_ill = int((~well).sum())
+    print(f"[{name}] max|dg|={err.max():.3e}; well-conditioned ({int(well.sum())}) max|dg|="
+          f"{err[well].max() if well.any() else 0.0:.3e}; ill-conditioned entries {n_ill}", flush=True)
+    if well.any():
+        assert err[well].max() <= TOL_255
+    if n_ill:
+        assert np.all(err[~well] <= bound[~well])
+
+
+@pytest.mark.parametrize("h,w,sigma_s", [(96, 80, 3.0), (37, 101, 5.0), (203, 173, 2.0), (70, 130, 0.5)])
+def test_colour_blf(h, w, sigma_s):
+    # ragged row and column batches (203 = 12 * 16 + 11 rows, 173 -> 176 stored columns)
+    f, prm = synth.workload("color_blf_256", h, w)
+    c32 = _landmarks(f.reshape(-1, 3).astype(np.float64), prm["r"], prm["landmark_seed"], prm["iters"])
+    g, eta, _ = _run(f, f, c32, sigma_s, prm["sigma_r"])
+    _check(f"rec{h}x{w}s{sigma_s}", f, f, c32, sigma_s, prm["sigma_r"], g)
+    assert np.isfinite(eta).all()
+
+
+@pytest.mark.parametrize("C,h,w", [(1, 45, 66), (2, 64, 64), (3, 17, 16)])
+def test_channel_counts(C, h, w):
+    rng = np.random.default_rng(C)
+    f = synth.rectangles_image(h, w, 7, 12.0, seed=C)[:, :, :1].repeat(C, axis=2).astype(np.float32)
+    f += rng.normal(0, 8, f.shape).astype(np.float32)
+    c32 = _landmarks(f.reshape(-1, C).astype(np.float64), 9, C, 4)
+    g, _, _ = _run(f, f, c32, 2.5, 35.0)
+    _check(f"recC{C}", f, f, c32, 2.5, 35.0, g)
+
+
+@pytest.mark.parametrize("h,w,r", [(1, 1, 1), (1, 37, 3), (37, 1, 3), (5, 3, 4), (16, 16, 2)])
+def test_tiny_images(h, w, r):
+    rng = np.random.default_rng(h * 100 + w)
+    f = rng.uniform(0, 255, (h, w, 3)).astype(np.float32)
+    c32 = f.reshape(-1, 3)[seeding.distinct_indices(h * w, r, 5)].copy()
+    g, _, _ = _run(f, f, c32, 1.5, 50.0)
+    _check(f"rectiny{h}x{w}", f, f, c32, 1.5, 50.0, g)
+
+
+def test_wide_response_beyond_the_window_limit():
+    # sigma_s = 40: wider than the image and than any truncated window here
+    f, prm = synth.workload("color_blf_256", 90, 120)
+    c32 = _landmarks(f.reshape(-1, 3).astype(np.float64), 12, 3, 5)
+    g, _, _ = _run(f, f, c32, 40.0, 60.0)
+    _check("rec_sigma40", f, f, c32, 40.0, 60.0, g)
+
+
+def test_constant_image_exact_and_infinite_sigma_r_blur():
+    f = np.full((40, 50, 3), 77.0, np.float32)
+    rng = np.random.default_rng(2)
+    p = rng.uniform(0, 255, (40, 50, 3)).astype(np.float32)
+    c32 = p.reshape(-1, 3)[:6].copy()
+    g, _, _ = _run(f, p, c32, 2.0, 40.0)
+    np.testing.assert_array_equal(g, f)
+    f2 = synth.rectangles_image(40, 50, 6, 10.0, seed=3)
+    g2, _, reff = _run(f2, f2, c32, 2.0, float("inf"))
+    assert reff == 1
+    blur = recursive.recursive_gauss_2d(f2.astype(np.float64), 2.0)
+    blur /= recursive.recursive_gauss_2d(np.ones((40, 50)), 2.0)[:, :, None]
+    assert np.abs(g2 - blur).max() <= TOL_255
+
+
+def test_full_size_colour_2048_crops():
+    """2048^2, r = 32, sigma_s = 5 (the colour BLF workload with the recursive
+    Gaussian): two regions of the full-image call against the oracle on a crop
+    with a margin of the response's FP64 support (beyond it every weight is
+    below 1e-20), one at the image corner (true borders) and one inside,
+    across a 64-column and a 64-row block edge."""
+    nkf = _nkf()
+    f, prm = synth.workload("color_blf_2048")
+    P = f.reshape(-1, 3).astype(np.float64)
+    c32 = _landmarks(P[seeding.distinct_indices(P.shape[0], 32768, prm["landmark_seed"] + 100)], prm["r"],
+                     prm["landmark_seed"], prm["iters"])
+    _, _, F, _ = nkf.landmark_factor(c32.astype(np.float64), prm["sigma_r"])
+    g, _ = nkf.filter_landmarks(torch.from_numpy(f).cuda(), torch.from_numpy(c32).cuda(), F,
+                                sigma_s=5.0, sigma_r=prm["sigma_r"], spatial="recursive", return_eta=True)
+    g = g.cpu().numpy().astype(np.float64)
+    assert np.isfinite(g).all()
+    M = recursive.padding(5.0)
+    for name, (y0, x0), T in [("corner", (0, 0), 48), ("inside", (1000, 1000), 48)]:
+        ya, xa = max(0, y0 - M), max(0, x0 - M)
+        yb, xb = min(2048, y0 + T + M), min(2048, x0 + T + M)
+        crop = np.ascontiguousarray(f[ya:yb, xa:xb])
+        gc = g[ya:yb, xa:xb]
+        _check(f"rec2048_{name}", crop, crop, c32, 5.0, prm["sigma_r"], gc,
+               region=(y0 - ya, y0 - ya + T, x0 - xa, x0 - xa + T))
+
+
+def test_rejected_requests():
+    nkf = _nkf()
+    f = torch.zeros((8, 9, 4), device="cuda")
+    c = torch.zeros((2, 4), device="cuda")
+    F = np.eye(2)
+    with pytest.raises(RuntimeError, match="C <= 3"):
+        nkf.filter_landmarks(f, c, F, sigma_s=2.0, sigma_r=10.0, spatial="recursive")
+    f3 = torch.zeros((8, 9, 3), device="cuda")
+    c3 = torch.zeros((2, 3), device="cuda")
+    with pytest.raises(RuntimeError, match="sigma_s"):
+        nkf.filter_landmarks(f3, c3, F, sigma_s=0.4, sigma_r=10.0, spatial="recursive")
+    with pytest.raises(RuntimeError, match="no taps"):
+        nkf.spatial_taps(-1, 2.0, "recursive")
