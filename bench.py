@@ -539,11 +539,52 @@ def leg_diff(steps, warmup, nstreams=4):
                          "algorithmic_flops": {"fwd": fl_f, "fwd_bwd": fl_fb}}}
 
 
+def leg_recursive(steps, warmup):
+    """The colour BLF workload (2048^2 x 3, r = 32, sigma_r = 40, 15
+    iterations) with Young and van Vliet's recursive Gaussian in place of the
+    truncated window, at sigma_s = 5 (the truncated window's 31 x 31) and at
+    sigma_s = 20, where no truncated window here reaches (radius <= 16): the
+    recursive filter's work does not depend on sigma_s.  The conv stage's
+    roofline counts the bytes of its three passes: per pixel and embedding
+    plane u_k, the column pass reads u_k twice and writes, reads and writes
+    the C + 1 filtered planes; the row pass reads them twice and writes,
+    reads and writes its own; the contraction reads those and u_k once
+    (12 + 36 (C + 1) bytes), plus f read and g written once."""
+    import torch
+
+    from paper_1901_06112_amd import nkf, synth
+    f, prm = synth.workload("color_blf_2048")
+    H, W, C = f.shape
+    N = H * W
+    ft = torch.from_numpy(f).cuda()
+    out = {"H": H, "W": W, "C": C, "r": prm["r"], "sigma_r": prm["sigma_r"], "kmeans_iters": prm["iters"]}
+    gs = {}
+    for ss in (5.0, 20.0):
+        kw = dict(sigma_s=ss, sigma_r=prm["sigma_r"], r=prm["r"], iters=prm["iters"], seed=prm["landmark_seed"],
+                  spatial="recursive")
+        ms, st, (g, r_eff) = _timed(lambda: nkf.filter(ft, return_r_eff=True, **kw), steps, warmup, ft)
+        conv_s = st["conv"] * 1e-3
+        nbytes = N * (r_eff * (12 + 36 * (C + 1)) + 8 * C)
+        out[f"sigma_s_{ss:g}"] = {
+            "ms_per_call": round(ms, 3), "Mpixel_s": round(N / ms / 1e3, 2), "r_eff": r_eff, "stages_ms": st,
+            "conv_roofline": {"kernel": "rec_cols + rec_rows + rec_contract", "bound": "hbm", "unit": "GB/s",
+                              "achieved": round(nbytes / conv_s / 1e9, 1), "peak": PEAK_HBM_GBS,
+                              "frac": round(nbytes / conv_s / 1e9 / PEAK_HBM_GBS, 4),
+                              "algorithmic_bytes_per_launch": nbytes}}
+        gs[ss] = g
+    kw = dict(sigma_s=5.0, sigma_r=prm["sigma_r"], r=prm["r"], radius=prm["S"], iters=prm["iters"],
+              seed=prm["landmark_seed"])
+    g_fir = nkf.filter(ft, **kw)
+    out["psnr_recursive_vs_truncated_sigma5_dB"] = round(_psnr(gs[5.0], g_fir, 255.0), 2)
+    return out
+
+
 LEGS = {
     "hyperspectral": lambda s, w: leg_precision("hyperspectral_512x128", s, w),
     "nlm": lambda s, w: leg_precision("color_nlm_1024", s, w),
     "diff_batch": lambda s, w: leg_diff(s, w),
     "pca_nlm": lambda s, w: leg_pca_nlm(s, w),
+    "recursive": lambda s, w: leg_recursive(s, w),
 }
 
 

@@ -59,7 +59,7 @@ typedef enum {
  * RECURSIVE is the O(1) recursive Gaussian of Young and van Vliet (Signal
  * Processing 44, 1995) that Section IV uses for the Gaussian window: their
  * third-order recursion run forwards and then backwards along each row and
- * column, with their fit of the scale q to sigma_s (0.5 <= sigma_s <= 1000,
+ * column, with their fit of the scale q to sigma_s (0.5 <= sigma_s <= 200,
  * else NKF_ERR_INVALID_ARG).  Its response is not truncated (radius is
  * ignored) and approximates the Gaussian to within a few percent of its peak
  * (about 10% wider in variance).  The image is extended by zeros, so each
@@ -89,7 +89,7 @@ enum { NKF_PREC_FP32 = 0, NKF_PREC_BF16 = 1, NKF_PREC_FP16 = 2 };
 
 typedef struct {
   double sigma_s;          /* spatial Gaussian width, > 0 (ignored by BOX except for radius = -1;
-                              RECURSIVE: 0.5 .. 1000)                                             */
+                              RECURSIVE: 0.5 .. 200)                                              */
   double sigma_r;          /* range kernel width, > 0; +INFINITY means k == 1                     */
   int r;                   /* landmarks, 1 <= r <= min(N, 256)                                  */
   int radius;              /* window radius S, 0 <= S <= 16; -1 means ceil(3 sigma_s); unused by

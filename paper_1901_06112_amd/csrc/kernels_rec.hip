@@ -10,29 +10,43 @@
 // here in parallel form, h = h+ + h-, with h+ the causal half (h+[0] = h[0]/2,
 // h+[n] = h[n] for n > 0) and h- its mirror image.  For n > 0, h[n] is a sum
 // of the cascade's three causal geometric modes, so h+ is the response of
-//   y+[n] = n0 x[n] + n1 x[n-1] + n2 x[n-2] + n3 x[n-3]
-//           + a1 y+[n-1] + a2 y+[n-2] + a3 y+[n-3]
-// with n0..n3 fitted to h[0]/2, h[1], h[2], h[3]; y- runs the same recursion
-// from the other end.  Both start from rest at the line ends, which is exactly
-// the zero extension.  Each sweep reads only the input: a pass stores the
-// first sweep's result and the second sweep adds its own.
+// N(z) / A(z), A(z) = 1 - a1 z^-1 - a2 z^-2 - a3 z^-3 (the cascade's poles)
+// and N(z) = n0 + n1 z^-1 + n2 z^-2 + n3 z^-3 fitted to h[0]/2, h[1], h[2],
+// h[3].  It runs as the all-pole recursion followed by the numerator:
+//   w[n] = x[n] + a1 w[n-1] + a2 w[n-2] + a3 w[n-3],
+//   y+[n] = n0 w[n] + n1 w[n-1] + n2 w[n-2] + n3 w[n-3],
+// so (w[n-1], w[n-2], w[n-3]) is the whole state.  y- runs the same from the
+// other end.  Both start from rest at the line ends, which is exactly the
+// zero extension.
+//
+// Each line is one thread's, in two phases: phase A runs the all-pole
+// recursion along the whole line and keeps only its state at the start of
+// every chunk of the line; phase C walks the chunks from the far end, reloads
+// each chunk's inputs into registers, restarts the causal half from the kept
+// state (the same FP64 values as one full sweep), runs the anticausal half
+// back over the chunk, carried from the previous chunk, and stores y+ + y-
+// once.  Per line and pass: the input read twice, the output written once,
+// three doubles per chunk.
 //
 // For embedding plane u_k, the planes are u_k f~_c (f~ = f - f0) and u_k
 // itself (plane 0); every recursion runs in FP64, the filtered planes are
 // stored as FP32 between passes.
-//   columns   block (64 columns, k), wave = plane: each lane sweeps down and
-//             then up its column, forming the plane's input from u_k and f
-//             on the fly; V_kp = column-filtered planes;
-//   rows      block (64 rows, k), wave = plane: each lane sweeps right and
-//             then left along its row of V_kp, 16 columns per batch of four
-//             16-byte loads; Z_kp = filtered planes;
+//   columns   block (64 columns, two k), wave = (k, plane): each lane owns a
+//             column, chunks of 16 rows, the plane's input formed from u_k
+//             and f on the fly (f copied to channel planes first, so a wave
+//             reads only its channel, and both k of a block read it from the
+//             same cache lines); output V_kp = column-filtered planes;
+//   rows      block (64 rows, k), wave = plane: each lane owns a row of V_kp,
+//             chunks of 32 columns (eight 16-byte loads); the output Z_kp
+//             overwrites V_kp chunk by chunk (each chunk is read before it
+//             is written, by the same thread);
 //   contract  thread per pixel: eta = sum_k u_k Z_k0 and zeta_c =
 //             sum_k u_k Z_k(c+1) in FP64, g = zeta / eta + f0 (f where eta
 //             <= 0 or not finite).
-// Rows of V and Z are padded to Wp = W rounded up to 16 columns; the padding
-// columns of V hold zeros (the zero extension), those of Z are never read.
-// Every sweep prefetches its next batch of rows or columns while it computes
-// the current one.
+// Rows of V are padded to Wp = W rounded up to 32 columns; the padding
+// columns hold zeros (the zero extension) before the row pass and are never
+// read after it.  Every sweep prefetches its next chunk while it computes the
+// current one.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -45,109 +59,151 @@ namespace nkf {
 
 namespace {
 
-constexpr int kRB = 16;   // rows per batch of the column sweeps
-constexpr int kCB = 16;   // columns per batch of the row sweeps (four float4)
+constexpr int kRL = 16;   // rows per chunk of the column pass
+constexpr int kCL = 32;   // columns per chunk of the row pass (eight float4)
 
 struct RecArgs {
   int H, W, Wp, C, r_eff;
   int64_t N, plane;        // pixels; floats per stored plane (H * Wp)
   const float *f, *f0, *u;
-  float *V, *Z;
+  float *fpl;              // f as channel planes, [C][N]
+  float *V;                // the filtered planes, [r_eff][C + 1][H][Wp]
+  double *carry;           // causal states at chunk starts
   float *out, *eta_out;
   RecCoef k;
 };
 
-// One step of the causal recursion; x1..x3 and y1..y3 hold the last three
-// inputs and outputs.
+// One half of the filter; w1..w3 hold the all-pole recursion's last three
+// values.
 struct Rec {
-  double x1 = 0, x2 = 0, x3 = 0, y1 = 0, y2 = 0, y3 = 0;
+  double w1 = 0, w2 = 0, w3 = 0;
+  __device__ double advance(const RecCoef &c, double x) {
+    const double w = fma(c.a1, w1, fma(c.a2, w2, fma(c.a3, w3, x)));
+    w3 = w2;
+    w2 = w1;
+    w1 = w;
+    return w;
+  }
   __device__ double step(const RecCoef &c, double x) {
-    const double part = fma(c.n0, x, fma(c.n1, x1, fma(c.n2, x2, fma(c.n3, x3, fma(c.a3, y3, c.a2 * y2)))));
-    const double y = fma(c.a1, y1, part);
-    x3 = x2;
-    x2 = x1;
-    x1 = x;
-    y3 = y2;
-    y2 = y1;
-    y1 = y;
-    return y;
+    const double p1 = w1, p2 = w2, p3 = w3;
+    const double w = advance(c, x);
+    return fma(c.n0, w, fma(c.n1, p1, fma(c.n2, p2, c.n3 * p3)));
   }
 };
 
-__global__ __launch_bounds__(256) void rec_cols_kernel(RecArgs a) {
-  const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // 0: u_k, c + 1: u_k f~_c
-  const int k = blockIdx.y;
+constexpr int kColK = 2;  // embedding planes per block of the column pass
+
+__global__ __launch_bounds__(512) void planar_kernel(RecArgs a) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.N * a.C;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pix = i / a.C;
+    const int c = (int)(i - pix * a.C);
+    a.fpl[c * a.N + pix] = a.f[i];
+  }
+}
+
+__global__ __launch_bounds__(64 * kColK * 4) void rec_cols_kernel(RecArgs a) {
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int P = a.C + 1;
+  const int p = w % P;  // 0: u_k, c + 1: u_k f~_c
+  const int k = blockIdx.y * kColK + w / P;
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-  if (x >= a.Wp) return;
+  if (k >= a.r_eff || x >= a.Wp) return;
   const bool valid = x < a.W;
   const int xc = valid ? x : a.W - 1;  // in-bounds address; the value is dropped when !valid
   const float *__restrict__ up = a.u + (int64_t)k * a.N + xc;
-  const float *__restrict__ fp = a.f + (int64_t)xc * a.C + (p > 0 ? p - 1 : 0);
+  const float *__restrict__ fp = a.fpl + (int64_t)(p > 0 ? p - 1 : 0) * a.N + xc;
   const double f0 = p > 0 ? (double)a.f0[p - 1] : 0.0;
-  float *__restrict__ vp = a.V + ((int64_t)k * (a.C + 1) + p) * a.plane + x;
   const int H = a.H, Wp = a.Wp;
-  const int64_t us = a.W, fs = (int64_t)a.W * a.C;
+  const int64_t line = (int64_t)k * (a.C + 1) + p;
+  float *__restrict__ vp = a.V + line * a.plane + x;
+  const int nch = (H + kRL - 1) / kRL, nfull = H / kRL;
+  double *__restrict__ cs = a.carry + line * nch * 3 * Wp + x;  // [chunk][3][Wp]
+  const int64_t us = a.W, fs = a.W;
   auto input = [&](float uv, float fv) -> double {
     const double uu = valid ? (double)uv : 0.0;
     return p > 0 ? uu * ((double)fv - f0) : uu;
   };
-  const int nb = H / kRB;
-  float cu[kRB], cf[kRB], nu[kRB], nf[kRB], cv[kRB], nv[kRB];
-  // ---- down: y+ stored in V
-  {
-    auto load = [&](int y0, float (&U)[kRB], float (&F)[kRB]) {
+  auto load = [&](int y0, float (&U)[kRL], float (&F)[kRL]) {
 #pragma unroll
-      for (int j = 0; j < kRB; ++j) {
-        U[j] = up[(int64_t)(y0 + j) * us];
-        F[j] = p > 0 ? fp[(int64_t)(y0 + j) * fs] : 0.0f;
-      }
-    };
+    for (int j = 0; j < kRL; ++j) {
+      U[j] = up[(int64_t)(y0 + j) * us];
+      F[j] = fp[(int64_t)(y0 + j) * fs];  // plane 0 loads channel 0 and ignores it: no branch
+    }
+  };
+  auto keep = [&](int c, const Rec &r) {
+    cs[(int64_t)(3 * c + 0) * Wp] = r.w1;
+    cs[(int64_t)(3 * c + 1) * Wp] = r.w2;
+    cs[(int64_t)(3 * c + 2) * Wp] = r.w3;
+  };
+  auto restart = [&](int c) {
     Rec r;
-    if (nb > 0) load(0, cu, cf);
-    for (int b = 0; b < nb; ++b) {
-      if (b + 1 < nb) load((b + 1) * kRB, nu, nf);
+    r.w1 = cs[(int64_t)(3 * c + 0) * Wp];
+    r.w2 = cs[(int64_t)(3 * c + 1) * Wp];
+    r.w3 = cs[(int64_t)(3 * c + 2) * Wp];
+    return r;
+  };
+  float cu[kRL], cf[kRL], nu[kRL], nf[kRL];
+  // ---- phase A: causal states at the chunk starts
+  {
+    Rec r;
+    if (nfull > 0) load(0, cu, cf);
+    for (int c = 0; c < nfull; ++c) {
+      if (c + 1 < nfull) load((c + 1) * kRL, nu, nf);
+      keep(c, r);
 #pragma unroll
-      for (int j = 0; j < kRB; ++j) vp[(int64_t)(b * kRB + j) * Wp] = (float)r.step(a.k, input(cu[j], cf[j]));
+      for (int j = 0; j < kRL; ++j) r.advance(a.k, input(cu[j], cf[j]));
 #pragma unroll
-      for (int j = 0; j < kRB; ++j) {
+      for (int j = 0; j < kRL; ++j) {
         cu[j] = nu[j];
         cf[j] = nf[j];
       }
     }
-    for (int y = nb * kRB; y < H; ++y)
-      vp[(int64_t)y * Wp] = (float)r.step(a.k, input(up[(int64_t)y * us], p > 0 ? fp[(int64_t)y * fs] : 0.0f));
+    if (nfull < nch) keep(nfull, r);  // the short last chunk needs only its start
   }
-  // ---- up: V = y+ + y-
-  {
-    auto load = [&](int i0, float (&U)[kRB], float (&F)[kRB], float (&Vv)[kRB]) {
+  // ---- phase C: chunks from the bottom; causal restarted from the kept
+  // state, anticausal carried, V = y+ + y-
+  Rec ra;
+  double yp[kRL];
+  if (nfull < nch) {  // the short last chunk: the same steps, predicated
+    const int y0 = nfull * kRL, len = H - y0;
 #pragma unroll
-      for (int j = 0; j < kRB; ++j) {
-        const int64_t y = H - 1 - (i0 + j);
-        U[j] = up[y * us];
-        F[j] = p > 0 ? fp[y * fs] : 0.0f;
-        Vv[j] = vp[y * Wp];
-      }
-    };
-    Rec r;
-    if (nb > 0) load(0, cu, cf, cv);
-    for (int b = 0; b < nb; ++b) {
-      if (b + 1 < nb) load((b + 1) * kRB, nu, nf, nv);
-#pragma unroll
-      for (int j = 0; j < kRB; ++j) {
-        const int64_t y = H - 1 - (b * kRB + j);
-        vp[y * Wp] = (float)((double)cv[j] + r.step(a.k, input(cu[j], cf[j])));
-      }
-#pragma unroll
-      for (int j = 0; j < kRB; ++j) {
-        cu[j] = nu[j];
-        cf[j] = nf[j];
-        cv[j] = nv[j];
-      }
+    for (int j = 0; j < kRL; ++j) {
+      const int64_t yy = y0 + (j < len ? j : len - 1);
+      cu[j] = up[yy * us];
+      cf[j] = fp[yy * fs];
     }
-    for (int i = nb * kRB; i < H; ++i) {
-      const int64_t y = H - 1 - i;
-      const double yv = r.step(a.k, input(up[y * us], p > 0 ? fp[y * fs] : 0.0f));
-      vp[y * Wp] = (float)((double)vp[y * Wp] + yv);
+    Rec rc = restart(nfull);
+#pragma unroll
+    for (int j = 0; j < kRL; ++j)
+      if (j < len) yp[j] = rc.step(a.k, input(cu[j], cf[j]));
+#pragma unroll
+    for (int j = kRL - 1; j >= 0; --j)
+      if (j < len) vp[(int64_t)(y0 + j) * Wp] = (float)(yp[j] + ra.step(a.k, input(cu[j], cf[j])));
+  }
+  // the kept state of the next chunk is loaded with its inputs, one chunk
+  // ahead (a load issued after the prefetch and used at once would make the
+  // wait cover the prefetch as well)
+  Rec rc_next;
+  if (nfull > 0) {
+    rc_next = restart(nfull - 1);
+    load((nfull - 1) * kRL, cu, cf);
+  }
+  for (int c = nfull - 1; c >= 0; --c) {
+    Rec rc = rc_next;
+    if (c > 0) {
+      rc_next = restart(c - 1);
+      load((c - 1) * kRL, nu, nf);
+    }
+#pragma unroll
+    for (int j = 0; j < kRL; ++j) yp[j] = rc.step(a.k, input(cu[j], cf[j]));
+#pragma unroll
+    for (int j = kRL - 1; j >= 0; --j)
+      vp[(int64_t)(c * kRL + j) * Wp] = (float)(yp[j] + ra.step(a.k, input(cu[j], cf[j])));
+#pragma unroll
+    for (int j = 0; j < kRL; ++j) {
+      cu[j] = nu[j];
+      cf[j] = nf[j];
     }
   }
 }
@@ -157,66 +213,75 @@ __global__ __launch_bounds__(256) void rec_rows_kernel(RecArgs a) {
   const int k = blockIdx.y;
   const int y = blockIdx.x * 64 + (threadIdx.x & 63);
   if (y >= a.H) return;
-  const int64_t row = ((int64_t)k * (a.C + 1) + p) * a.plane + (int64_t)y * a.Wp;
-  const float4 *__restrict__ vr = reinterpret_cast<const float4 *>(a.V + row);
-  float4 *__restrict__ zr = reinterpret_cast<float4 *>(a.Z + row);
-  constexpr int Q = kCB / 4;
-  const int nb = a.Wp / kCB;
-  float4 cur[Q], nxt[Q], cz[Q], nz[Q];
-  // ---- right: y+ stored in Z
+  const int64_t line = (int64_t)k * (a.C + 1) + p;
+  float4 *__restrict__ vr = reinterpret_cast<float4 *>(a.V + line * a.plane + (int64_t)y * a.Wp);
+  constexpr int Q = kCL / 4;
+  const int nch = a.Wp / kCL;
+  double *__restrict__ cs = a.carry + line * nch * 3 * a.H + y;  // [chunk][3][H]
+  float4 cur[Q], nxt[Q];
+  // ---- phase A: causal states at the chunk starts
   {
     Rec r;
 #pragma unroll
     for (int q = 0; q < Q; ++q) cur[q] = vr[q];
-    for (int b = 0; b < nb; ++b) {
-      if (b + 1 < nb) {
+    for (int c = 0; c < nch; ++c) {
+      if (c + 1 < nch) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) nxt[q] = vr[(b + 1) * Q + q];
+        for (int q = 0; q < Q; ++q) nxt[q] = vr[(c + 1) * Q + q];
       }
+      cs[(int64_t)(3 * c + 0) * a.H] = r.w1;
+      cs[(int64_t)(3 * c + 1) * a.H] = r.w2;
+      cs[(int64_t)(3 * c + 2) * a.H] = r.w3;
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        float4 o;
-        o.x = (float)r.step(a.k, (double)cur[q].x);
-        o.y = (float)r.step(a.k, (double)cur[q].y);
-        o.z = (float)r.step(a.k, (double)cur[q].z);
-        o.w = (float)r.step(a.k, (double)cur[q].w);
-        zr[b * Q + q] = o;
+        r.advance(a.k, (double)cur[q].x);
+        r.advance(a.k, (double)cur[q].y);
+        r.advance(a.k, (double)cur[q].z);
+        r.advance(a.k, (double)cur[q].w);
       }
 #pragma unroll
       for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
     }
   }
-  // ---- left: Z = y+ + y-
-  {
+  // ---- phase C: chunks from the right end, Z = y+ + y- over V in place
+  Rec ra;
+  double yp[kCL];
+  // the kept state of the next chunk is loaded with its inputs, one chunk ahead
+  auto restart = [&](int c) {
     Rec r;
+    r.w1 = cs[(int64_t)(3 * c + 0) * a.H];
+    r.w2 = cs[(int64_t)(3 * c + 1) * a.H];
+    r.w3 = cs[(int64_t)(3 * c + 2) * a.H];
+    return r;
+  };
+  Rec rc_next = restart(nch - 1);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) cur[q] = vr[(nch - 1) * Q + q];
+  for (int c = nch - 1; c >= 0; --c) {
+    Rec rc = rc_next;
+    if (c > 0) {
+      rc_next = restart(c - 1);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) nxt[q] = vr[(c - 1) * Q + q];
+    }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      cur[q] = vr[(nb - 1) * Q + q];
-      cz[q] = zr[(nb - 1) * Q + q];
+      yp[4 * q + 0] = rc.step(a.k, (double)cur[q].x);
+      yp[4 * q + 1] = rc.step(a.k, (double)cur[q].y);
+      yp[4 * q + 2] = rc.step(a.k, (double)cur[q].z);
+      yp[4 * q + 3] = rc.step(a.k, (double)cur[q].w);
     }
-    for (int b = nb - 1; b >= 0; --b) {
-      if (b > 0) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          nxt[q] = vr[(b - 1) * Q + q];
-          nz[q] = zr[(b - 1) * Q + q];
-        }
-      }
-#pragma unroll
-      for (int q = Q - 1; q >= 0; --q) {
-        float4 o;
-        o.w = (float)((double)cz[q].w + r.step(a.k, (double)cur[q].w));
-        o.z = (float)((double)cz[q].z + r.step(a.k, (double)cur[q].z));
-        o.y = (float)((double)cz[q].y + r.step(a.k, (double)cur[q].y));
-        o.x = (float)((double)cz[q].x + r.step(a.k, (double)cur[q].x));
-        zr[b * Q + q] = o;
-      }
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        cur[q] = nxt[q];
-        cz[q] = nz[q];
-      }
+    for (int q = Q - 1; q >= 0; --q) {
+      float4 o;
+      o.w = (float)(yp[4 * q + 3] + ra.step(a.k, (double)cur[q].w));
+      o.z = (float)(yp[4 * q + 2] + ra.step(a.k, (double)cur[q].z));
+      o.y = (float)(yp[4 * q + 1] + ra.step(a.k, (double)cur[q].y));
+      o.x = (float)(yp[4 * q + 0] + ra.step(a.k, (double)cur[q].x));
+      vr[c * Q + q] = o;
     }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
   }
 }
 
@@ -226,7 +291,7 @@ __global__ __launch_bounds__(256) void rec_contract_kernel(RecArgs a) {
   for (int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pix < a.N;
        pix += (int64_t)gridDim.x * blockDim.x) {
     const int y = (int)(pix / a.W), x = (int)(pix - (int64_t)y * a.W);
-    const float *__restrict__ zp = a.Z + (int64_t)y * a.Wp + x;
+    const float *__restrict__ zp = a.V + (int64_t)y * a.Wp + x;
     const float *__restrict__ up = a.u + pix;
     double e = 0.0, z[C];
 #pragma unroll
@@ -246,7 +311,15 @@ __global__ __launch_bounds__(256) void rec_contract_kernel(RecArgs a) {
   }
 }
 
-int padded_width(int W) { return (W + kCB - 1) / kCB * kCB; }
+int padded_width(int W) { return (W + kCL - 1) / kCL * kCL; }
+
+size_t plane_floats(int H, int W, int C, int r_eff) { return (size_t)r_eff * (C + 1) * H * padded_width(W); }
+
+size_t carry_doubles(int H, int W, int C, int r_eff) {
+  const size_t lines_c = (size_t)r_eff * (C + 1) * padded_width(W), lines_r = (size_t)r_eff * (C + 1) * H;
+  const size_t nc = 3 * lines_c * ((H + kRL - 1) / kRL), nr = 3 * lines_r * (padded_width(W) / kCL);
+  return nc > nr ? nc : nr;
+}
 
 }  // namespace
 
@@ -283,7 +356,10 @@ bool rec_coefficients(double sigma_s, RecCoef *c) {
 }
 
 size_t rec_plane_floats(int H, int W, int C, int r_eff) {
-  return 2 * (size_t)r_eff * (C + 1) * H * padded_width(W);
+  // the planes, the carries, f as channel planes (each 256-byte aligned)
+  const size_t pf = (plane_floats(H, W, C, r_eff) + 63) / 64 * 64;
+  const size_t cf = (2 * carry_doubles(H, W, C, r_eff) + 63) / 64 * 64;
+  return pf + cf + (size_t)C * H * W;
 }
 
 hipError_t launch_rec(const RecProblem &pb, hipStream_t s) {
@@ -300,12 +376,19 @@ hipError_t launch_rec(const RecProblem &pb, hipStream_t s) {
   a.f0 = pb.f0;
   a.u = pb.u;
   a.V = pb.planes;
-  a.Z = pb.planes + (size_t)pb.r_eff * (pb.C + 1) * a.plane;
+  const size_t pf = (plane_floats(pb.H, pb.W, pb.C, pb.r_eff) + 63) / 64 * 64;
+  const size_t cf = (2 * carry_doubles(pb.H, pb.W, pb.C, pb.r_eff) + 63) / 64 * 64;
+  a.carry = reinterpret_cast<double *>(pb.planes + pf);
+  a.fpl = pb.planes + pf + cf;
   a.out = pb.out;
   a.eta_out = pb.eta_out;
   a.k = pb.coef;
   const int P = pb.C + 1;
-  hipLaunchKernelGGL(rec_cols_kernel, dim3((a.Wp + 63) / 64, pb.r_eff), dim3(64 * P), 0, s, a);
+  const int64_t nfl = a.N * pb.C;
+  hipLaunchKernelGGL(planar_kernel, dim3((unsigned)((nfl + 511) / 512 < 4096 ? (nfl + 511) / 512 : 4096)), dim3(512), 0,
+                     s, a);
+  hipLaunchKernelGGL(rec_cols_kernel, dim3((a.Wp + 63) / 64, (pb.r_eff + kColK - 1) / kColK), dim3(64 * P * kColK),
+                     0, s, a);
   hipLaunchKernelGGL(rec_rows_kernel, dim3((pb.H + 63) / 64, pb.r_eff), dim3(64 * P), 0, s, a);
   const int64_t nblk = (a.N + 255) / 256;
   const dim3 g((unsigned)(nblk < 8192 ? nblk : 8192));

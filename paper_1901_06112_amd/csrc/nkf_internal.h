@@ -147,7 +147,7 @@ struct RecCoef {
   double n0, n1, n2, n3;  // numerator of the causal half
   double a1, a2, a3;      // feedback of the cascade's recursion
 };
-constexpr double kRecSigmaMin = 0.5, kRecSigmaMax = 1000.0;
+constexpr double kRecSigmaMin = 0.5, kRecSigmaMax = 200.0;
 // False when sigma_s is outside [kRecSigmaMin, kRecSigmaMax].
 bool rec_coefficients(double sigma_s, RecCoef *c);
 struct RecProblem {
