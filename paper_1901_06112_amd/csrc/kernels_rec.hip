@@ -43,9 +43,11 @@
 //   contract  thread per pixel: eta = sum_k u_k Z_k0 and zeta_c =
 //             sum_k u_k Z_k(c+1) in FP64, g = zeta / eta + f0 (f where eta
 //             <= 0 or not finite).
-// Rows of V are padded to Wp = W rounded up to 32 columns; the padding
+// Rows of V are padded to Wp = W rounded up to 64 columns; the padding
 // columns hold zeros (the zero extension) before the row pass and are never
-// read after it.  Every sweep prefetches its next chunk while it computes the
+// read after it.  The row stride is Wp + 32 floats: with a power-of-two
+// stride the row pass's 64 lanes (64 rows) fall on fewer memory channels
+// (measured 4% slower).  Every sweep prefetches its next chunk while it computes the
 // current one.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -63,7 +65,7 @@ constexpr int kRL = 16;   // rows per chunk of the column pass
 constexpr int kCL = 32;   // columns per chunk of the row pass (eight float4)
 
 struct RecArgs {
-  int H, W, Wp, C, r_eff;
+  int H, W, Wp, ld, C, r_eff;  // ld: row stride of the planes
   int64_t N, plane;        // pixels; floats per stored plane (H * Wp)
   const float *f, *f0, *u;
   float *fpl;              // f as channel planes, [C][N]
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(64 * kColK * 4) void rec_cols_kernel(RecArgs a) {
   const float *__restrict__ up = a.u + (int64_t)k * a.N + xc;
   const float *__restrict__ fp = a.fpl + (int64_t)(p > 0 ? p - 1 : 0) * a.N + xc;
   const double f0 = p > 0 ? (double)a.f0[p - 1] : 0.0;
-  const int H = a.H, Wp = a.Wp;
+  const int H = a.H, Wp = a.Wp, ld = a.ld;
   const int64_t line = (int64_t)k * (a.C + 1) + p;
   float *__restrict__ vp = a.V + line * a.plane + x;
   const int nch = (H + kRL - 1) / kRL, nfull = H / kRL;
@@ -149,7 +151,10 @@ __global__ __launch_bounds__(64 * kColK * 4) void rec_cols_kernel(RecArgs a) {
     Rec r;
     if (nfull > 0) load(0, cu, cf);
     for (int c = 0; c < nfull; ++c) {
-      if (c + 1 < nfull) load((c + 1) * kRL, nu, nf);
+      // unconditional prefetch (the last chunk is loaded again at the end): a
+      // load under a branch makes the compiler's wait at the join cover the
+      // newer loads as well
+      load((c + 1 < nfull ? c + 1 : c) * kRL, nu, nf);
       keep(c, r);
 #pragma unroll
       for (int j = 0; j < kRL; ++j) r.advance(a.k, input(cu[j], cf[j]));
@@ -179,7 +184,7 @@ __global__ __launch_bounds__(64 * kColK * 4) void rec_cols_kernel(RecArgs a) {
       if (j < len) yp[j] = rc.step(a.k, input(cu[j], cf[j]));
 #pragma unroll
     for (int j = kRL - 1; j >= 0; --j)
-      if (j < len) vp[(int64_t)(y0 + j) * Wp] = (float)(yp[j] + ra.step(a.k, input(cu[j], cf[j])));
+      if (j < len) vp[(int64_t)(y0 + j) * ld] = (float)(yp[j] + ra.step(a.k, input(cu[j], cf[j])));
   }
   // the kept state of the next chunk is loaded with its inputs, one chunk
   // ahead (a load issued after the prefetch and used at once would make the
@@ -191,15 +196,13 @@ __global__ __launch_bounds__(64 * kColK * 4) void rec_cols_kernel(RecArgs a) {
   }
   for (int c = nfull - 1; c >= 0; --c) {
     Rec rc = rc_next;
-    if (c > 0) {
-      rc_next = restart(c - 1);
-      load((c - 1) * kRL, nu, nf);
-    }
+    rc_next = restart(c > 0 ? c - 1 : 0);
+    load((c > 0 ? c - 1 : 0) * kRL, nu, nf);
 #pragma unroll
     for (int j = 0; j < kRL; ++j) yp[j] = rc.step(a.k, input(cu[j], cf[j]));
 #pragma unroll
     for (int j = kRL - 1; j >= 0; --j)
-      vp[(int64_t)(c * kRL + j) * Wp] = (float)(yp[j] + ra.step(a.k, input(cu[j], cf[j])));
+      vp[(int64_t)(c * kRL + j) * ld] = (float)(yp[j] + ra.step(a.k, input(cu[j], cf[j])));
 #pragma unroll
     for (int j = 0; j < kRL; ++j) {
       cu[j] = nu[j];
@@ -214,39 +217,44 @@ __global__ __launch_bounds__(256) void rec_rows_kernel(RecArgs a) {
   const int y = blockIdx.x * 64 + (threadIdx.x & 63);
   if (y >= a.H) return;
   const int64_t line = (int64_t)k * (a.C + 1) + p;
-  float4 *__restrict__ vr = reinterpret_cast<float4 *>(a.V + line * a.plane + (int64_t)y * a.Wp);
+  float4 *__restrict__ vr = reinterpret_cast<float4 *>(a.V + line * a.plane + (int64_t)y * a.ld);
   constexpr int Q = kCL / 4;
   const int nch = a.Wp / kCL;
   double *__restrict__ cs = a.carry + line * nch * 3 * a.H + y;  // [chunk][3][H]
-  float4 cur[Q], nxt[Q];
+  // Chunks go in pairs with the two register sets swapping roles (a copy of
+  // the prefetched set would wait for it; nch is even), and prefetches are
+  // unconditional, as in the column pass.
+  float4 b0[Q], b1[Q];
+  auto fetch = [&](int c, float4 (&B)[Q]) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) B[q] = vr[c * Q + q];
+  };
   // ---- phase A: causal states at the chunk starts
   {
     Rec r;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) cur[q] = vr[q];
-    for (int c = 0; c < nch; ++c) {
-      if (c + 1 < nch) {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) nxt[q] = vr[(c + 1) * Q + q];
-      }
+    auto step_a = [&](int c, const float4 (&B)[Q], float4 (&NB)[Q]) {
+      fetch(c + 1 < nch ? c + 1 : c, NB);
       cs[(int64_t)(3 * c + 0) * a.H] = r.w1;
       cs[(int64_t)(3 * c + 1) * a.H] = r.w2;
       cs[(int64_t)(3 * c + 2) * a.H] = r.w3;
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        r.advance(a.k, (double)cur[q].x);
-        r.advance(a.k, (double)cur[q].y);
-        r.advance(a.k, (double)cur[q].z);
-        r.advance(a.k, (double)cur[q].w);
+        r.advance(a.k, (double)B[q].x);
+        r.advance(a.k, (double)B[q].y);
+        r.advance(a.k, (double)B[q].z);
+        r.advance(a.k, (double)B[q].w);
       }
-#pragma unroll
-      for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
+    };
+    fetch(0, b0);
+    for (int c = 0; c < nch; c += 2) {
+      step_a(c, b0, b1);
+      step_a(c + 1, b1, b0);
     }
   }
-  // ---- phase C: chunks from the right end, Z = y+ + y- over V in place
+  // ---- phase C: chunks from the right end, Z = y+ + y- over V in place; the
+  // kept state of the next chunk is loaded with its inputs, one chunk ahead
   Rec ra;
   double yp[kCL];
-  // the kept state of the next chunk is loaded with its inputs, one chunk ahead
   auto restart = [&](int c) {
     Rec r;
     r.w1 = cs[(int64_t)(3 * c + 0) * a.H];
@@ -254,34 +262,33 @@ __global__ __launch_bounds__(256) void rec_rows_kernel(RecArgs a) {
     r.w3 = cs[(int64_t)(3 * c + 2) * a.H];
     return r;
   };
-  Rec rc_next = restart(nch - 1);
-#pragma unroll
-  for (int q = 0; q < Q; ++q) cur[q] = vr[(nch - 1) * Q + q];
-  for (int c = nch - 1; c >= 0; --c) {
-    Rec rc = rc_next;
-    if (c > 0) {
-      rc_next = restart(c - 1);
-#pragma unroll
-      for (int q = 0; q < Q; ++q) nxt[q] = vr[(c - 1) * Q + q];
-    }
+  auto step_c = [&](int c, const Rec &rc0, const float4 (&B)[Q], Rec &rcn, float4 (&NB)[Q]) {
+    const int cn = c > 0 ? c - 1 : 0;
+    rcn = restart(cn);
+    fetch(cn, NB);
+    Rec rc = rc0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      yp[4 * q + 0] = rc.step(a.k, (double)cur[q].x);
-      yp[4 * q + 1] = rc.step(a.k, (double)cur[q].y);
-      yp[4 * q + 2] = rc.step(a.k, (double)cur[q].z);
-      yp[4 * q + 3] = rc.step(a.k, (double)cur[q].w);
+      yp[4 * q + 0] = rc.step(a.k, (double)B[q].x);
+      yp[4 * q + 1] = rc.step(a.k, (double)B[q].y);
+      yp[4 * q + 2] = rc.step(a.k, (double)B[q].z);
+      yp[4 * q + 3] = rc.step(a.k, (double)B[q].w);
     }
 #pragma unroll
     for (int q = Q - 1; q >= 0; --q) {
       float4 o;
-      o.w = (float)(yp[4 * q + 3] + ra.step(a.k, (double)cur[q].w));
-      o.z = (float)(yp[4 * q + 2] + ra.step(a.k, (double)cur[q].z));
-      o.y = (float)(yp[4 * q + 1] + ra.step(a.k, (double)cur[q].y));
-      o.x = (float)(yp[4 * q + 0] + ra.step(a.k, (double)cur[q].x));
+      o.w = (float)(yp[4 * q + 3] + ra.step(a.k, (double)B[q].w));
+      o.z = (float)(yp[4 * q + 2] + ra.step(a.k, (double)B[q].z));
+      o.y = (float)(yp[4 * q + 1] + ra.step(a.k, (double)B[q].y));
+      o.x = (float)(yp[4 * q + 0] + ra.step(a.k, (double)B[q].x));
       vr[c * Q + q] = o;
     }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
+  };
+  Rec r0 = restart(nch - 1), r1;
+  fetch(nch - 1, b0);
+  for (int c = nch - 1; c >= 1; c -= 2) {
+    step_c(c, r0, b0, r1, b1);
+    step_c(c - 1, r1, b1, r0, b0);
   }
 }
 
@@ -291,7 +298,7 @@ __global__ __launch_bounds__(256) void rec_contract_kernel(RecArgs a) {
   for (int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pix < a.N;
        pix += (int64_t)gridDim.x * blockDim.x) {
     const int y = (int)(pix / a.W), x = (int)(pix - (int64_t)y * a.W);
-    const float *__restrict__ zp = a.V + (int64_t)y * a.Wp + x;
+    const float *__restrict__ zp = a.V + (int64_t)y * a.ld + x;
     const float *__restrict__ up = a.u + pix;
     double e = 0.0, z[C];
 #pragma unroll
@@ -311,9 +318,10 @@ __global__ __launch_bounds__(256) void rec_contract_kernel(RecArgs a) {
   }
 }
 
-int padded_width(int W) { return (W + kCL - 1) / kCL * kCL; }
+// a whole number of chunk pairs per row
+int padded_width(int W) { return (W + 2 * kCL - 1) / (2 * kCL) * (2 * kCL); }
 
-size_t plane_floats(int H, int W, int C, int r_eff) { return (size_t)r_eff * (C + 1) * H * padded_width(W); }
+size_t plane_floats(int H, int W, int C, int r_eff) { return (size_t)r_eff * (C + 1) * H * (padded_width(W) + 32); }
 
 size_t carry_doubles(int H, int W, int C, int r_eff) {
   const size_t lines_c = (size_t)r_eff * (C + 1) * padded_width(W), lines_r = (size_t)r_eff * (C + 1) * H;
@@ -371,7 +379,8 @@ hipError_t launch_rec(const RecProblem &pb, hipStream_t s) {
   a.C = pb.C;
   a.r_eff = pb.r_eff;
   a.N = (int64_t)pb.H * pb.W;
-  a.plane = (int64_t)pb.H * a.Wp;
+  a.ld = a.Wp + 32;
+  a.plane = (int64_t)pb.H * a.ld;
   a.f = pb.f;
   a.f0 = pb.f0;
   a.u = pb.u;
