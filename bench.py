@@ -545,11 +545,12 @@ def leg_recursive(steps, warmup):
     truncated window, at sigma_s = 5 (the truncated window's 31 x 31) and at
     sigma_s = 20, where no truncated window here reaches (radius <= 16): the
     recursive filter's work does not depend on sigma_s.  The conv stage's
-    roofline counts the bytes of its three passes: per pixel and embedding
-    plane u_k, the column pass reads u_k twice and writes, reads and writes
-    the C + 1 filtered planes; the row pass reads them twice and writes,
-    reads and writes its own; the contraction reads those and u_k once
-    (12 + 36 (C + 1) bytes), plus f read and g written once."""
+    roofline counts the bytes its passes must move: per pixel and embedding
+    plane u_k, the column pass reads u_k twice and writes the C + 1 filtered
+    planes once, the row pass reads them twice and writes them once, the
+    contraction reads them and u_k once (12 + 20 (C + 1) bytes), plus f read
+    and g written once; the kept chunk states (about 1.1 (C + 1) bytes each
+    way) are not counted."""
     import torch
 
     from paper_1901_06112_amd import nkf, synth
@@ -564,7 +565,7 @@ def leg_recursive(steps, warmup):
                   spatial="recursive")
         ms, st, (g, r_eff) = _timed(lambda: nkf.filter(ft, return_r_eff=True, **kw), steps, warmup, ft)
         conv_s = st["conv"] * 1e-3
-        nbytes = N * (r_eff * (12 + 36 * (C + 1)) + 8 * C)
+        nbytes = N * (r_eff * (12 + 20 * (C + 1)) + 8 * C)
         out[f"sigma_s_{ss:g}"] = {
             "ms_per_call": round(ms, 3), "Mpixel_s": round(N / ms / 1e3, 2), "r_eff": r_eff, "stages_ms": st,
             "conv_roofline": {"kernel": "rec_cols + rec_rows + rec_contract", "bound": "hbm", "unit": "GB/s",

@@ -66,8 +66,9 @@ typedef enum {
  * filtered line is that response convolved with the line.  Up to three
  * channels (else NKF_ERR_UNSUPPORTED); forward calls only (the backward
  * returns NKF_ERR_UNSUPPORTED).  Work and memory do not grow with sigma_s:
- * the filtered planes take 2 r_eff (C + 1) H W' floats of workspace, W' = W
- * rounded up to 16. */
+ * the filtered planes take r_eff (C + 1) H (W' + 32) floats of workspace
+ * (W' = W rounded up to 64), plus the recursion's states at every 16 rows or
+ * 32 columns and a copy of f. */
 enum { NKF_SPATIAL_GAUSSIAN = 0, NKF_SPATIAL_BOX = 1, NKF_SPATIAL_RECURSIVE = 2 };
 /* Guide kinds: EXPLICIT = caller passes p [H, W, D]; SELF = p is f (D == C);
  * PATCH = nonlocal-means guide, the (2pr+1)^2 * C patch of f around each pixel
