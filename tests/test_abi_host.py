@@ -51,6 +51,13 @@ def test_spatial_taps_radius_limit():
     assert ei.value.status == nkf.NKF_ERR_UNSUPPORTED
 
 
+def test_recursive_gaussian_has_no_taps():
+    # the recursive filter is not a truncated window: asking for its taps is refused
+    with pytest.raises(nkf.NkfError) as ei:
+        nkf.spatial_taps(-1, 2.0, "recursive")
+    assert ei.value.status == nkf.NKF_ERR_UNSUPPORTED
+
+
 def _check_factor(c, sr, tau=1e-10):
     Q, al, F, reff = nkf.landmark_factor(c, sr, tau)
     A = nystrom.landmark_gram(c, sr)
