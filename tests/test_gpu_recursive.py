@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import kmeans, nystrom, recursive, seeding
+from oracle import exact, kmeans, nystrom, recursive, seeding
 from paper_1901_06112_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -158,3 +158,47 @@ def test_rejected_requests():
         nkf.filter_landmarks(f3, c3, F, sigma_s=0.4, sigma_r=10.0, spatial="recursive")
     with pytest.raises(RuntimeError, match="no taps"):
         nkf.spatial_taps(-1, 2.0, "recursive")
+
+
+def test_patch_guide_and_16bit_forms():
+    """NLM patch guide (7 x 7 x 3, D = 147) with the recursive Gaussian: the
+    FP32 form to the storage bar, the 16-bit distance forms (embedding on the
+    matrix cores, the same recursive kernels after it) >= 45 dB against the
+    FP64 oracle at the same landmarks."""
+    nkf = _nkf()
+    f, prm = synth.workload("color_nlm_1024", 56, 72)
+    pg = exact.patch_guide(f.astype(np.float64), prm["patch_radius"])
+    c32 = _landmarks(pg.reshape(-1, pg.shape[2]), 24, prm["landmark_seed"], 5)
+    _, _, F, _ = nkf.landmark_factor(c32.astype(np.float64), prm["sigma_r"])
+    ft = torch.from_numpy(f).cuda()
+    go = nystrom.nystrom_filter(f.astype(np.float64), pg, c32.astype(np.float64), 2.0, prm["sigma_r"], 0,
+                                "recursive")
+    for prec in ("fp32", "fp16", "bf16"):
+        g = nkf.filter_landmarks(ft, torch.from_numpy(c32).cuda(), F, sigma_s=2.0, sigma_r=prm["sigma_r"],
+                                 spatial="recursive", guide="patch", patch_radius=prm["patch_radius"],
+                                 precision=prec)
+        g = g.cpu().numpy().astype(np.float64)
+        ps = exact.psnr(g, go)
+        print(f"[rec patch {prec}] PSNR vs FP64 Nystrom {ps:.1f} dB, max|dg|={np.abs(g - go).max():.3e}", flush=True)
+        if prec == "fp32":
+            _check("rec_patch_fp32", f, pg, c32, 2.0, prm["sigma_r"], g)
+        else:
+            assert ps >= 45.0
+
+
+def test_allocation_free_entry_matches():
+    """The allocation-free forward runs the same recursive kernels from the
+    library's static scratch: equal to the workspace call, twice in a row,
+    the second smaller."""
+    nkf = _nkf()
+    for h, w in [(40, 52), (23, 31)]:
+        f, prm = synth.workload("color_blf_256", h, w)
+        c32 = _landmarks(f.reshape(-1, 3).astype(np.float64), 8, 3, 3)
+        _, _, F, _ = nkf.landmark_factor(c32.astype(np.float64), 30.0)
+        ft, ct = torch.from_numpy(f).cuda(), torch.from_numpy(c32).cuda()
+        Ft = torch.from_numpy(np.ascontiguousarray(F)).cuda()
+        kw = dict(sigma_s=2.0, sigma_r=30.0, spatial="recursive", return_eta=True)
+        g1, e1 = nkf.filter_landmarks(ft, ct, Ft, **kw)
+        g2, e2 = nkf.filter_landmarks(ft, ct, Ft, noalloc=True, **kw)
+        torch.cuda.synchronize()
+        assert torch.equal(g1, g2) and torch.equal(e1, e2)
