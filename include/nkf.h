@@ -67,7 +67,7 @@ typedef enum {
  * channels (else NKF_ERR_UNSUPPORTED); forward calls only (the backward
  * returns NKF_ERR_UNSUPPORTED).  Work and memory do not grow with sigma_s:
  * the filtered planes take r_eff (C + 1) H (W' + 32) floats of workspace
- * (W' = W rounded up to 64), plus the recursion's states at every 16 rows or
+ * (W' = W rounded up to 64), plus the recursion's states at every 24 rows or
  * 32 columns and a copy of f. */
 enum { NKF_SPATIAL_GAUSSIAN = 0, NKF_SPATIAL_BOX = 1, NKF_SPATIAL_RECURSIVE = 2 };
 /* Guide kinds: EXPLICIT = caller passes p [H, W, D]; SELF = p is f (D == C);

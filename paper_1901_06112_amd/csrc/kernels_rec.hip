@@ -32,7 +32,7 @@
 // itself (plane 0); every recursion runs in FP64, the filtered planes are
 // stored as FP32 between passes.
 //   columns   block (64 columns, two k), wave = (k, plane): each lane owns a
-//             column, chunks of 16 rows, the plane's input formed from u_k
+//             column, chunks of 24 rows, the plane's input formed from u_k
 //             and f on the fly (f copied to channel planes first, so a wave
 //             reads only its channel, and both k of a block read it from the
 //             same cache lines); output V_kp = column-filtered planes;
@@ -45,9 +45,10 @@
 //             <= 0 or not finite).
 // Rows of V are padded to Wp = W rounded up to 64 columns; the padding
 // columns hold zeros (the zero extension) before the row pass and are never
-// read after it.  The row stride is Wp + 32 floats: a power-of-two stride,
-// with the row pass's 64 lanes reading 64 rows at once, measured 4% slower.
-// Every sweep prefetches its next chunk while it computes the current one.
+// read after it.  The row stride is Wp + 32 floats: with a power-of-two
+// stride the row pass's 64 lanes (64 rows) fall on fewer memory channels
+// (measured 4% slower).  Every sweep prefetches its next chunk while it computes the
+// current one.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -60,7 +61,7 @@ namespace nkf {
 
 namespace {
 
-constexpr int kRL = 16;   // rows per chunk of the column pass
+constexpr int kRL = 24;   // rows per chunk of the column pass
 constexpr int kCL = 32;   // columns per chunk of the row pass (eight float4)
 
 struct RecArgs {
@@ -112,12 +113,14 @@ __global__ __launch_bounds__(64 * kColK * 4) void rec_cols_kernel(RecArgs a) {
   if (k >= a.r_eff || x >= a.Wp) return;
   const bool valid = x < a.W;
   const int xc = valid ? x : a.W - 1;  // in-bounds address; the value is dropped when !valid
-  const float *__restrict__ up = a.u + (int64_t)k * a.N + xc;
-  const float *__restrict__ fp = a.fpl + (int64_t)(p > 0 ? p - 1 : 0) * a.N + xc;
+  // wave-uniform 64-bit bases, the lane's column as a 32-bit offset
+  const float *__restrict__ ub = a.u + (int64_t)k * a.N;
+  const float *__restrict__ fb = a.fpl + (int64_t)(p > 0 ? p - 1 : 0) * a.N;
+  const unsigned xo = (unsigned)xc, xs = (unsigned)x;
   const double f0 = p > 0 ? (double)a.f0[p - 1] : 0.0;
   const int H = a.H, Wp = a.Wp, ld = a.ld;
   const int64_t line = (int64_t)k * (a.C + 1) + p;
-  float *__restrict__ vp = a.V + line * a.plane + x;
+  float *__restrict__ vb = a.V + line * a.plane;
   const int nch = (H + kRL - 1) / kRL, nfull = H / kRL;
   double *__restrict__ cs = a.carry + line * nch * 3 * Wp + x;  // [chunk][3][Wp]
   const int64_t us = a.W, fs = a.W;
@@ -128,8 +131,8 @@ __global__ __launch_bounds__(64 * kColK * 4) void rec_cols_kernel(RecArgs a) {
   auto load = [&](int y0, float (&U)[kRL], float (&F)[kRL]) {
 #pragma unroll
     for (int j = 0; j < kRL; ++j) {
-      U[j] = up[(int64_t)(y0 + j) * us];
-      F[j] = fp[(int64_t)(y0 + j) * fs];  // plane 0 loads channel 0 and ignores it: no branch
+      U[j] = (ub + (int64_t)(y0 + j) * us)[xo];
+      F[j] = (fb + (int64_t)(y0 + j) * fs)[xo];  // plane 0 loads channel 0 and ignores it: no branch
     }
   };
   auto keep = [&](int c, const Rec &r) {
@@ -174,8 +177,8 @@ __global__ __launch_bounds__(64 * kColK * 4) void rec_cols_kernel(RecArgs a) {
 #pragma unroll
     for (int j = 0; j < kRL; ++j) {
       const int64_t yy = y0 + (j < len ? j : len - 1);
-      cu[j] = up[yy * us];
-      cf[j] = fp[yy * fs];
+      cu[j] = (ub + yy * us)[xo];
+      cf[j] = (fb + yy * fs)[xo];
     }
     Rec rc = restart(nfull);
 #pragma unroll
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(64 * kColK * 4) void rec_cols_kernel(RecArgs a) {
       if (j < len) yp[j] = rc.step(a.k, input(cu[j], cf[j]));
 #pragma unroll
     for (int j = kRL - 1; j >= 0; --j)
-      if (j < len) vp[(int64_t)(y0 + j) * ld] = (float)(yp[j] + ra.step(a.k, input(cu[j], cf[j])));
+      if (j < len) (vb + (int64_t)(y0 + j) * ld)[xs] = (float)(yp[j] + ra.step(a.k, input(cu[j], cf[j])));
   }
   // the kept state of the next chunk is loaded with its inputs, one chunk
   // ahead (a load issued after the prefetch and used at once would make the
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(64 * kColK * 4) void rec_cols_kernel(RecArgs a) {
     for (int j = 0; j < kRL; ++j) yp[j] = rc.step(a.k, input(cu[j], cf[j]));
 #pragma unroll
     for (int j = kRL - 1; j >= 0; --j)
-      vp[(int64_t)(c * kRL + j) * ld] = (float)(yp[j] + ra.step(a.k, input(cu[j], cf[j])));
+      (vb + (int64_t)(c * kRL + j) * ld)[xs] = (float)(yp[j] + ra.step(a.k, input(cu[j], cf[j])));
 #pragma unroll
     for (int j = 0; j < kRL; ++j) {
       cu[j] = nu[j];
@@ -216,7 +219,9 @@ __global__ __launch_bounds__(256) void rec_rows_kernel(RecArgs a) {
   const int y = blockIdx.x * 64 + (threadIdx.x & 63);
   if (y >= a.H) return;
   const int64_t line = (int64_t)k * (a.C + 1) + p;
-  float4 *__restrict__ vr = reinterpret_cast<float4 *>(a.V + line * a.plane + (int64_t)y * a.ld);
+  // wave-uniform base of the plane, the lane's row as a 32-bit offset
+  float4 *__restrict__ vb4 = reinterpret_cast<float4 *>(a.V + line * a.plane);
+  const unsigned yo = (unsigned)y * (unsigned)(a.ld / 4);
   constexpr int Q = kCL / 4;
   const int nch = a.Wp / kCL;
   double *__restrict__ cs = a.carry + line * nch * 3 * a.H + y;  // [chunk][3][H]
@@ -226,7 +231,7 @@ __global__ __launch_bounds__(256) void rec_rows_kernel(RecArgs a) {
   float4 b0[Q], b1[Q];
   auto fetch = [&](int c, float4 (&B)[Q]) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) B[q] = vr[c * Q + q];
+    for (int q = 0; q < Q; ++q) B[q] = (vb4 + c * Q + q)[yo];
   };
   // ---- phase A: causal states at the chunk starts
   {
@@ -280,7 +285,7 @@ __global__ __launch_bounds__(256) void rec_rows_kernel(RecArgs a) {
       o.z = (float)(yp[4 * q + 2] + ra.step(a.k, (double)B[q].z));
       o.y = (float)(yp[4 * q + 1] + ra.step(a.k, (double)B[q].y));
       o.x = (float)(yp[4 * q + 0] + ra.step(a.k, (double)B[q].x));
-      vr[c * Q + q] = o;
+      (vb4 + c * Q + q)[yo] = o;
     }
   };
   Rec r0 = restart(nch - 1), r1;
