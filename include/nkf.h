@@ -64,9 +64,11 @@ typedef enum {
  * ignored) and approximates the Gaussian to within a few percent of its peak
  * (about 10% wider in variance).  The image is extended by zeros, so each
  * filtered line is that response convolved with the line.  Up to three
- * channels (else NKF_ERR_UNSUPPORTED); forward calls only (the backward
- * returns NKF_ERR_UNSUPPORTED).  Work and memory do not grow with sigma_s:
- * the filtered planes take r_eff (C + 1) H (W' + 32) floats of workspace
+ * channels (else NKF_ERR_UNSUPPORTED).  nkf_filter_backward gives df, dp and
+ * the sigma_r gradient through it (the filter is symmetric, so the adjoint
+ * runs the same passes); its sigma_s gradient is NKF_ERR_UNSUPPORTED.  Work
+ * and memory do not grow with sigma_s: the filtered planes take
+ * r_eff (C + 1) H (W' + 32) floats of workspace
  * (W' = W rounded up to 64), plus the recursion's states at every 24 rows or
  * 32 columns and a copy of f. */
 enum { NKF_SPATIAL_GAUSSIAN = 0, NKF_SPATIAL_BOX = 1, NKF_SPATIAL_RECURSIVE = 2 };
@@ -236,11 +238,13 @@ nkf_status nkf_filter_landmarks_noalloc(nkf_ctx *ctx, int H, int W, int C, const
  * Outputs (each nullable): grad_f [H, W, C], grad_p [H, W, D] (EXPLICIT or
  * SELF guide; for SELF the caller adds grad_f and grad_p to get the total),
  * grad_sigma_r_host, grad_sigma_s_host (host doubles; sigma_s only for the
- * Gaussian window).  Recomputes the embedding instead of storing r_eff (C+1)
- * planes.  out_fwd [H, W, C] and eta_fwd [H, W] (both nullable, device) are
- * the out and eta_out of the nkf_filter_landmarks call with the same
- * arguments; when both are given the forward convolutions are not repeated
- * (the caller guarantees they match), otherwise they are recomputed.
+ * truncated Gaussian window).  Recomputes the embedding instead of storing
+ * r_eff (C+1) planes.  out_fwd [H, W, C] and eta_fwd [H, W] (both nullable,
+ * device) are the out and eta_out of the nkf_filter_landmarks call with the
+ * same arguments; when both are given the forward convolutions are not
+ * repeated (the caller guarantees they match), otherwise they are recomputed
+ * (always for the recursive Gaussian, whose backward reads the forward's
+ * filtered planes).
  * Synchronises the stream (the r x r_eff reduction for the sigma_r gradient
  * is finished on the host in FP64). */
 nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f, int D,

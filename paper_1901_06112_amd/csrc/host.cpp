@@ -1188,7 +1188,8 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
     return fail(ctx, NKF_ERR_INVALID_ARG, "centroids, eigvecs_host, eigvals_host and grad_out are required");
   if (r_eff < 1 || r_eff > r) return fail(ctx, NKF_ERR_INVALID_ARG, "need 1 <= r_eff <= r");
   if (C > 3) return fail(ctx, NKF_ERR_UNSUPPORTED, "backward supports C <= 3 (got %d)", C);
-  if (rs.rec) return fail(ctx, NKF_ERR_UNSUPPORTED, "backward of the recursive Gaussian is not implemented");
+  if (rs.rec && grad_sigma_s_host)
+    return fail(ctx, NKF_ERR_UNSUPPORTED, "sigma_s gradient of the recursive Gaussian is not implemented");
   if (r > 64) return fail(ctx, NKF_ERR_UNSUPPORTED, "backward supports r <= 64 (got %d)", r);
   if (grad_p && rs.g.kind == GUIDE_PATCH)
     return fail(ctx, NKF_ERR_UNSUPPORTED, "guide gradient of the patch guide is not implemented");
@@ -1246,51 +1247,73 @@ nkf_status nkf_filter_backward(nkf_ctx *ctx, int H, int W, int C, const float *f
     StageTimer tm(ctx, NKF_STAGE_BACKWARD);
     HIP_TRY(ctx, hipMemcpyAsync(Fd, hF, sizeof(double) * r * r_eff, hipMemcpyHostToDevice, ctx->stream));
     if ((st = pinned_release(ctx)) != NKF_OK) return st;
-    const bool have_fwd = out_fwd && eta_fwd;
+    // the recursive filter's backward reads the forward's filtered planes, so
+    // its forward always runs
+    const bool have_fwd = out_fwd && eta_fwd && !rs.rec;
     if ((st = run_fwd(ctx, rs, prm, centroids, Fd, r_eff, out_s, eta_s, fb, !have_fwd)) != NKF_OK) return st;
     const float *outv = have_fwd ? out_fwd : out_s, *etav = have_fwd ? eta_fwd : eta_s;
     HIP_TRY(ctx, launch_bwd_ab(rs.N, C, grad_out, outv, etav, fb.f0, ab, ctx->stream));
-    BwdConvProblem bp{};
-    bp.H = H;
-    bp.W = W;
-    bp.C = C;
-    bp.S = rs.S;
-    bp.r_eff = r_eff;
-    bp.f = f;
-    bp.f0 = fb.f0;
-    bp.u = fb.u;
-    bp.ab = ab;
-    bp.G = grad_out;
-    bp.eta = etav;
-    bp.wr = rs.taps;
-    bp.wc = rs.taps;
-    bp.force_nch = ctx->conv_chunks;
-    bp.plane_out = dud;
-    if (want_S) {
-      // du_dir and the sigma_s terms in one pass over the same planes:
-      // dw/dsigma_s = w1' (x) w1 + w1 (x) w1', w1'(t) = w1(t) t^2 / sigma_s^3
-      Taps dt = rs.taps;
-      const double s3 = prm->sigma_s * prm->sigma_s * prm->sigma_s;
-      for (int t = -rs.S; t <= rs.S; ++t)
-        dt.w[t + rs.S] = (float)(exp(-(double)t * t / (2.0 * prm->sigma_s * prm->sigma_s)) * t * t / s3);
-      bp.mode = 4;  // w1 in wr, w1' in wc
-      bp.partials = sig;
-      bp.wr = rs.taps;
-      bp.wc = dt;
-      bp.nblocks_out = &nb1;
-      HIP_TRY(ctx, launch_bwd_conv(bp, ctx->stream));
-      bp.wr = bp.wc = rs.taps;
-      bp.nblocks_out = nullptr;
-      bp.partials = nullptr;
+    if (rs.rec) {
+      RecProblem rp{};
+      rp.H = H;
+      rp.W = W;
+      rp.C = C;
+      rp.r_eff = r_eff;
+      rp.coef = rs.rc;
+      rp.f = f;
+      rp.f0 = fb.f0;
+      rp.u = fb.u;
+      rp.planes = fb.rec;
+      rp.G = grad_out;
+      rp.eta = etav;
+      rp.ab = ab;
+      rp.dud = dud;
+      rp.du = du;
+      rp.df = grad_f ? grad_f : df_s;
+      HIP_TRY(ctx, launch_rec_bwd(rp, ctx->stream));
     } else {
-      bp.mode = 1;
+      BwdConvProblem bp{};
+      bp.H = H;
+      bp.W = W;
+      bp.C = C;
+      bp.S = rs.S;
+      bp.r_eff = r_eff;
+      bp.f = f;
+      bp.f0 = fb.f0;
+      bp.u = fb.u;
+      bp.ab = ab;
+      bp.G = grad_out;
+      bp.eta = etav;
+      bp.wr = rs.taps;
+      bp.wc = rs.taps;
+      bp.force_nch = ctx->conv_chunks;
+      bp.plane_out = dud;
+      if (want_S) {
+        // du_dir and the sigma_s terms in one pass over the same planes:
+        // dw/dsigma_s = w1' (x) w1 + w1 (x) w1', w1'(t) = w1(t) t^2 / sigma_s^3
+        Taps dt = rs.taps;
+        const double s3 = prm->sigma_s * prm->sigma_s * prm->sigma_s;
+        for (int t = -rs.S; t <= rs.S; ++t)
+          dt.w[t + rs.S] = (float)(exp(-(double)t * t / (2.0 * prm->sigma_s * prm->sigma_s)) * t * t / s3);
+        bp.mode = 4;  // w1 in wr, w1' in wc
+        bp.partials = sig;
+        bp.wr = rs.taps;
+        bp.wc = dt;
+        bp.nblocks_out = &nb1;
+        HIP_TRY(ctx, launch_bwd_conv(bp, ctx->stream));
+        bp.wr = bp.wc = rs.taps;
+        bp.nblocks_out = nullptr;
+        bp.partials = nullptr;
+      } else {
+        bp.mode = 1;
+        HIP_TRY(ctx, launch_bwd_conv(bp, ctx->stream));
+      }
+      bp.mode = 3;
+      bp.plane_in = dud;
+      bp.plane_out = du;
+      bp.df = grad_f ? grad_f : df_s;
       HIP_TRY(ctx, launch_bwd_conv(bp, ctx->stream));
     }
-    bp.mode = 3;
-    bp.plane_in = dud;
-    bp.plane_out = du;
-    bp.df = grad_f ? grad_f : df_s;
-    HIP_TRY(ctx, launch_bwd_conv(bp, ctx->stream));
     HIP_TRY(ctx, launch_bwd_reduce(rs.g, centroids, r, Fd, r_eff, prm->sigma_r, du, dud, grad_p, want_R ? 1 : 0,
                                    red, ctx->stream));
   }

@@ -68,11 +68,15 @@ struct RecArgs {
   int H, W, Wp, ld, C, r_eff;  // ld: row stride of the planes
   int64_t N, plane;        // pixels; floats per stored plane (H * Wp)
   const float *f, *f0, *u;
-  float *fpl;              // f as channel planes, [C][N]
+  float *fpl;              // forward: f as channel planes [C][N]; backward: (beta, a_c) planes [C + 1][N]
   float *V;                // the filtered planes, [r_eff][C + 1][H][Wp]
   double *carry;           // causal states at chunk starts
   float *out, *eta_out;
   RecCoef k;
+  // backward (bwd = 1): the planes' inputs are beta u_k and a_c u_k
+  int bwd;
+  const float *G, *eta, *ab;  // dL/dg [N][C], the forward's eta_hat [N], (beta, a_c) [N][4]
+  float *dud, *du, *df;       // du_dir and du [r_eff][N], df [N][C]
 };
 
 // One half of the filter; w1..w3 hold the all-pole recursion's last three
@@ -104,6 +108,16 @@ __global__ __launch_bounds__(512) void planar_kernel(RecArgs a) {
   }
 }
 
+__global__ __launch_bounds__(512) void planar_ab_kernel(RecArgs a) {
+  const int P = a.C + 1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.N * P;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pix = i / P;
+    const int c = (int)(i - pix * P);
+    a.fpl[c * a.N + pix] = a.ab[pix * 4 + c];
+  }
+}
+
 __global__ __launch_bounds__(64 * kColK * 4) void rec_cols_kernel(RecArgs a) {
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int P = a.C + 1;
@@ -115,7 +129,7 @@ __global__ __launch_bounds__(64 * kColK * 4) void rec_cols_kernel(RecArgs a) {
   const int xc = valid ? x : a.W - 1;  // in-bounds address; the value is dropped when !valid
   // wave-uniform 64-bit bases, the lane's column as a 32-bit offset
   const float *__restrict__ ub = a.u + (int64_t)k * a.N;
-  const float *__restrict__ fb = a.fpl + (int64_t)(p > 0 ? p - 1 : 0) * a.N;
+  const float *__restrict__ fb = a.fpl + (int64_t)(a.bwd ? p : (p > 0 ? p - 1 : 0)) * a.N;
   const unsigned xo = (unsigned)xc, xs = (unsigned)x;
   const double f0 = p > 0 ? (double)a.f0[p - 1] : 0.0;
   const int H = a.H, Wp = a.Wp, ld = a.ld;
@@ -124,9 +138,13 @@ __global__ __launch_bounds__(64 * kColK * 4) void rec_cols_kernel(RecArgs a) {
   const int nch = (H + kRL - 1) / kRL, nfull = H / kRL;
   double *__restrict__ cs = a.carry + line * nch * 3 * Wp + x;  // [chunk][3][Wp]
   const int64_t us = a.W, fs = a.W;
+  // forward: plane 0 is u_k, plane c + 1 is u_k (f_c - f0_c); backward: u_k
+  // times the plane's per-pixel coefficient (beta, a_c)
+  const bool scaled = a.bwd || p > 0;
+  const double off = a.bwd ? 0.0 : f0;
   auto input = [&](float uv, float fv) -> double {
     const double uu = valid ? (double)uv : 0.0;
-    return p > 0 ? uu * ((double)fv - f0) : uu;
+    return scaled ? uu * ((double)fv - off) : uu;
   };
   auto load = [&](int y0, float (&U)[kRL], float (&F)[kRL]) {
 #pragma unroll
@@ -322,6 +340,62 @@ __global__ __launch_bounds__(256) void rec_contract_kernel(RecArgs a) {
   }
 }
 
+// Backward, from the forward's filtered planes Z_kp (E_k = Z_k0):
+// du_dir_k = beta E_k + sum_c a_c Z_k(c+1).
+template <int C>
+__global__ __launch_bounds__(256) void rec_dudir_kernel(RecArgs a) {
+  constexpr int P = C + 1;
+  for (int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pix < a.N;
+       pix += (int64_t)gridDim.x * blockDim.x) {
+    const int y = (int)(pix / a.W), x = (int)(pix - (int64_t)y * a.W);
+    const float *__restrict__ zp = a.V + (int64_t)y * a.ld + x;
+    const float4 co = reinterpret_cast<const float4 *>(a.ab)[pix];
+    const double cf[4] = {co.x, co.y, co.z, co.w};
+    for (int k = 0; k < a.r_eff; ++k) {
+      const float *zk = zp + (int64_t)k * P * a.plane;
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < P; ++q) v = fma(cf[q], (double)zk[(int64_t)q * a.plane], v);
+      a.dud[(int64_t)k * a.N + pix] = (float)v;
+    }
+  }
+}
+
+// Backward, from the planes Y_kp filtered again with inputs beta u_k and a_c u_k:
+// du_k = du_dir_k + Y_k0 + sum_c f~_c Y_k(c+1),  df_c = sum_k u_k Y_k(c+1)
+// (plus dL/dg itself where the forward took the eta <= 0 guard).
+template <int C>
+__global__ __launch_bounds__(256) void rec_bwd_contract_kernel(RecArgs a) {
+  constexpr int P = C + 1;
+  for (int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pix < a.N;
+       pix += (int64_t)gridDim.x * blockDim.x) {
+    const int y = (int)(pix / a.W), x = (int)(pix - (int64_t)y * a.W);
+    const float *__restrict__ zp = a.V + (int64_t)y * a.ld + x;
+    double ft[C], d[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      ft[c] = (double)a.f[pix * C + c] - (double)a.f0[c];
+      d[c] = 0.0;
+    }
+    for (int k = 0; k < a.r_eff; ++k) {
+      const float *zk = zp + (int64_t)k * P * a.plane;
+      const double uk = (double)a.u[(int64_t)k * a.N + pix];
+      double v = (double)a.dud[(int64_t)k * a.N + pix] + (double)zk[0];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const double yc = (double)zk[(int64_t)(c + 1) * a.plane];
+        v = fma(ft[c], yc, v);
+        d[c] = fma(uk, yc, d[c]);
+      }
+      a.du[(int64_t)k * a.N + pix] = (float)v;
+    }
+    const float e = a.eta[pix];
+    const bool guard = !(e > 0.0f && isfinite(e));
+#pragma unroll
+    for (int c = 0; c < C; ++c) a.df[pix * C + c] = (float)d[c] + (guard ? a.G[pix * C + c] : 0.0f);
+  }
+}
+
 // a whole number of chunk pairs per row
 int padded_width(int W) { return (W + 2 * kCL - 1) / (2 * kCL) * (2 * kCL); }
 
@@ -371,11 +445,12 @@ size_t rec_plane_floats(int H, int W, int C, int r_eff) {
   // the planes, the carries, f as channel planes (each 256-byte aligned)
   const size_t pf = (plane_floats(H, W, C, r_eff) + 63) / 64 * 64;
   const size_t cf = (2 * carry_doubles(H, W, C, r_eff) + 63) / 64 * 64;
-  return pf + cf + (size_t)C * H * W;
+  return pf + cf + (size_t)(C + 1) * H * W;  // the backward's C + 1 coefficient planes
 }
 
-hipError_t launch_rec(const RecProblem &pb, hipStream_t s) {
-  if (pb.C < 1 || pb.C > 3 || pb.r_eff < 1) return hipErrorInvalidValue;
+namespace {
+
+RecArgs rec_args(const RecProblem &pb) {
   RecArgs a{};
   a.H = pb.H;
   a.W = pb.W;
@@ -396,19 +471,64 @@ hipError_t launch_rec(const RecProblem &pb, hipStream_t s) {
   a.out = pb.out;
   a.eta_out = pb.eta_out;
   a.k = pb.coef;
-  const int P = pb.C + 1;
-  const int64_t nfl = a.N * pb.C;
-  hipLaunchKernelGGL(planar_kernel, dim3((unsigned)((nfl + 511) / 512 < 4096 ? (nfl + 511) / 512 : 4096)), dim3(512), 0,
-                     s, a);
-  hipLaunchKernelGGL(rec_cols_kernel, dim3((a.Wp + 63) / 64, (pb.r_eff + kColK - 1) / kColK), dim3(64 * P * kColK),
+  a.G = pb.G;
+  a.eta = pb.eta;
+  a.ab = pb.ab;
+  a.dud = pb.dud;
+  a.du = pb.du;
+  a.df = pb.df;
+  return a;
+}
+
+unsigned grid_of(int64_t n, int64_t per_block, int64_t cap) {
+  const int64_t b = (n + per_block - 1) / per_block;
+  return (unsigned)(b < cap ? b : cap);
+}
+
+// the column and row passes over the planes whose inputs the column pass forms
+void rec_filter(const RecArgs &a, hipStream_t s) {
+  const int P = a.C + 1;
+  hipLaunchKernelGGL(rec_cols_kernel, dim3((a.Wp + 63) / 64, (a.r_eff + kColK - 1) / kColK), dim3(64 * P * kColK),
                      0, s, a);
-  hipLaunchKernelGGL(rec_rows_kernel, dim3((pb.H + 63) / 64, pb.r_eff), dim3(64 * P), 0, s, a);
-  const int64_t nblk = (a.N + 255) / 256;
-  const dim3 g((unsigned)(nblk < 8192 ? nblk : 8192));
+  hipLaunchKernelGGL(rec_rows_kernel, dim3((a.H + 63) / 64, a.r_eff), dim3(64 * P), 0, s, a);
+}
+
+}  // namespace
+
+hipError_t launch_rec(const RecProblem &pb, hipStream_t s) {
+  if (pb.C < 1 || pb.C > 3 || pb.r_eff < 1) return hipErrorInvalidValue;
+  RecArgs a = rec_args(pb);
+  hipLaunchKernelGGL(planar_kernel, dim3(grid_of(a.N * pb.C, 512, 4096)), dim3(512), 0, s, a);
+  rec_filter(a, s);
+  const dim3 g(grid_of(a.N, 256, 8192));
   switch (pb.C) {
     case 1: hipLaunchKernelGGL(rec_contract_kernel<1>, g, dim3(256), 0, s, a); break;
     case 2: hipLaunchKernelGGL(rec_contract_kernel<2>, g, dim3(256), 0, s, a); break;
     default: hipLaunchKernelGGL(rec_contract_kernel<3>, g, dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rec_bwd(const RecProblem &pb, hipStream_t s) {
+  if (pb.C < 1 || pb.C > 3 || pb.r_eff < 1 || !pb.G || !pb.eta || !pb.ab || !pb.dud || !pb.du || !pb.df)
+    return hipErrorInvalidValue;
+  RecArgs a = rec_args(pb);
+  const dim3 g(grid_of(a.N, 256, 8192));
+  // du_dir from the forward's planes, still in the plane buffer
+  switch (pb.C) {
+    case 1: hipLaunchKernelGGL(rec_dudir_kernel<1>, g, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(rec_dudir_kernel<2>, g, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(rec_dudir_kernel<3>, g, dim3(256), 0, s, a); break;
+  }
+  // the filter is symmetric (zero-extended convolution with an even
+  // response), so the adjoint's planes go through the same passes
+  a.bwd = 1;
+  hipLaunchKernelGGL(planar_ab_kernel, dim3(grid_of(a.N * (pb.C + 1), 512, 4096)), dim3(512), 0, s, a);
+  rec_filter(a, s);
+  switch (pb.C) {
+    case 1: hipLaunchKernelGGL(rec_bwd_contract_kernel<1>, g, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(rec_bwd_contract_kernel<2>, g, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(rec_bwd_contract_kernel<3>, g, dim3(256), 0, s, a); break;
   }
   return hipGetLastError();
 }

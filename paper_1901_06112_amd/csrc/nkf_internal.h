@@ -159,9 +159,16 @@ struct RecProblem {
   float *out;         // [H, W, C]
   float *eta_out;     // nullable [N]
   float *planes;      // rec_plane_floats(...) floats: the filtered planes
+  // backward only (launch_rec_bwd, after launch_rec on the same planes)
+  const float *G;     // dL/dg [H, W, C]
+  const float *eta;   // the forward's eta_hat [N]
+  const float *ab;    // (beta, a_c) [N][4] of launch_bwd_ab
+  float *dud, *du;    // [r_eff][N] outputs for the reduction
+  float *df;          // [H, W, C]
 };
 size_t rec_plane_floats(int H, int W, int C, int r_eff);
 hipError_t launch_rec(const RecProblem &pb, hipStream_t s);
+hipError_t launch_rec_bwd(const RecProblem &pb, hipStream_t s);
 
 // ---- kernels_wk.hip ---------------------------------------------------------
 // Windowed Nystrom-kernel evaluation on MFMA for many channels (16-bit forms):

@@ -202,3 +202,51 @@ def test_allocation_free_entry_matches():
         g2, e2 = nkf.filter_landmarks(ft, ct, Ft, noalloc=True, **kw)
         torch.cuda.synchronize()
         assert torch.equal(g1, g2) and torch.equal(e1, e2)
+
+
+def test_backward_against_oracle_differences():
+    """Backward of the recursive filter with landmarks fixed, explicit guide:
+    v . df against <G, g(f + v) - g(f)> (exact: g is linear in f when the
+    guide is fixed), v . dp and dsigma_r against central differences of the
+    FP64 oracle's L = <G, g>."""
+    nkf = _nkf()
+    rng = np.random.default_rng(21)
+    f, _ = synth.workload("color_blf_256", 40, 52)
+    f = f.astype(np.float64)
+    p = np.clip(f[:, ::-1] * 0.7 + rng.normal(40, 12, f.shape), 0, 255)  # a guide that is not f
+    c32 = _landmarks(p.reshape(-1, 3), 8, 5, 4)
+    c64 = c32.astype(np.float64)
+    ss, sr = 3.0, 45.0
+    Q, al, F, reff = nkf.landmark_factor(c64, sr)
+    assert reff == 8
+    G = rng.normal(0, 1, f.shape)
+    ft = torch.from_numpy(f.astype(np.float32)).cuda()
+    pt = torch.from_numpy(p.astype(np.float32)).cuda()
+    df, dp, dsr, dss = nkf.filter_backward(ft, torch.from_numpy(c32).cuda(), Q, al, reff,
+                                           torch.from_numpy(G.astype(np.float32)).cuda(), pt, sigma_s=ss,
+                                           sigma_r=sr, spatial="recursive", need_sigma_s=False)
+    df = df.cpu().numpy().astype(np.float64)
+    dp = dp.cpu().numpy().astype(np.float64)
+    f32, p32 = f.astype(np.float32).astype(np.float64), p.astype(np.float32).astype(np.float64)
+
+    def L(fv, pv, s_r=sr):
+        return float((G * nystrom.nystrom_filter(fv, pv, c64, ss, s_r, 0, "recursive")).sum())
+
+    v = rng.normal(0, 1, f.shape)
+    ref_f = L(f32 + v, p32) - L(f32, p32)
+    got_f = float((df * v).sum())
+    w = rng.normal(0, 1, p.shape)
+    eps = 1e-2
+    ref_p = (L(f32, p32 + eps * w) - L(f32, p32 - eps * w)) / (2 * eps)
+    got_p = float((dp * w).sum())
+    e_r = 1e-3 * sr
+    ref_r = (L(f32, p32, sr + e_r) - L(f32, p32, sr - e_r)) / (2 * e_r)
+    print(f"[rec bwd] df.v {got_f:.6e} vs {ref_f:.6e}; dp.w {got_p:.6e} vs {ref_p:.6e}; "
+          f"dsigma_r {dsr:.6e} vs {ref_r:.6e}", flush=True)
+    assert abs(got_f - ref_f) <= 5e-4 * max(abs(ref_f), 1e-3 * np.abs(df).sum())
+    assert abs(got_p - ref_p) <= 5e-4 * max(abs(ref_p), 1e-3 * np.abs(dp).sum())
+    assert abs(dsr - ref_r) <= 5e-4 * max(abs(ref_r), 1.0)
+    with pytest.raises(RuntimeError, match="sigma_s"):
+        nkf.filter_backward(ft, torch.from_numpy(c32).cuda(), Q, al, reff,
+                            torch.from_numpy(G.astype(np.float32)).cuda(), pt, sigma_s=ss, sigma_r=sr,
+                            spatial="recursive")
