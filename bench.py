@@ -551,6 +551,7 @@ def leg_recursive(steps, warmup):
     contraction reads them and u_k once (12 + 20 (C + 1) bytes), plus f read
     and g written once; the kept chunk states (about 1.1 (C + 1) bytes each
     way) are not counted."""
+    import numpy as np
     import torch
 
     from paper_1901_06112_amd import nkf, synth
@@ -577,6 +578,20 @@ def leg_recursive(steps, warmup):
               seed=prm["landmark_seed"])
     g_fir = nkf.filter(ft, **kw)
     out["psnr_recursive_vs_truncated_sigma5_dB"] = round(_psnr(gs[5.0], g_fir, 255.0), 2)
+    # forward + backward (df, dp, dsigma_r) with the landmarks fixed, as the
+    # autograd function runs it, against the truncated 31 x 31 window's
+    c = nkf.kmeans(ft, r=prm["r"], iters=prm["iters"], seed=prm["landmark_seed"])
+    Q, al, F, reff = nkf.landmark_factor(c.cpu().numpy().astype(np.float64), prm["sigma_r"])
+    Fd = torch.from_numpy(F).cuda()
+    G = torch.from_numpy(np.random.default_rng(7).normal(0, 1, f.shape).astype(np.float32)).cuda()
+    for name, kwb in (("recursive", dict(sigma_s=5.0, sigma_r=prm["sigma_r"], spatial="recursive")),
+                      ("truncated", dict(sigma_s=5.0, sigma_r=prm["sigma_r"], radius=prm["S"]))):
+        def fb():
+            o, e = nkf.filter_landmarks(ft, c, Fd, return_eta=True, **kwb)
+            nkf.filter_backward(ft, c, Q, al, reff, G, out=o, eta=e, need_sigma_s=False, **kwb)
+        ms, _, _ = _timed(fb, steps, warmup)
+        out[f"fwd_bwd_{name}_sigma5"] = {"ms": round(ms, 3), "Mpixel_s": round(N / ms / 1e3, 2),
+                                         "grads": "df, dp (self guide), dsigma_r"}
     return out
 
 
