@@ -250,3 +250,35 @@ def test_backward_against_oracle_differences():
         nkf.filter_backward(ft, torch.from_numpy(c32).cuda(), Q, al, reff,
                             torch.from_numpy(G.astype(np.float32)).cuda(), pt, sigma_s=ss, sigma_r=sr,
                             spatial="recursive")
+
+
+def test_autograd_function_self_guided():
+    """NystromFilter with the recursive Gaussian, the image guiding itself:
+    f.grad (through the image and the guide) and sigma_r.grad against central
+    differences of the FP64 oracle's L = <G, g>."""
+    nkf = _nkf()
+    rng = np.random.default_rng(33)
+    f, _ = synth.workload("color_blf_256", 36, 44)
+    f = f.astype(np.float32)
+    c32 = _landmarks(f.reshape(-1, 3).astype(np.float64), 6, 2, 4)
+    ss, sr = 2.5, 40.0
+    G = rng.normal(0, 1, f.shape)
+    ft = torch.from_numpy(f).cuda().requires_grad_(True)
+    srt = torch.tensor(sr, dtype=torch.float64, requires_grad=True)
+    out = nkf.NystromFilter.apply(ft, None, srt, ss, torch.from_numpy(c32).cuda(), -1, "recursive")
+    (out * torch.from_numpy(G.astype(np.float32)).cuda()).sum().backward()
+    c64, f64 = c32.astype(np.float64), f.astype(np.float64)
+
+    def L(fv, s_r=sr):
+        return float((G * nystrom.nystrom_filter(fv, fv, c64, ss, s_r, 0, "recursive")).sum())
+
+    v = rng.normal(0, 1, f.shape)
+    eps = 1e-2
+    ref_f = (L(f64 + eps * v) - L(f64 - eps * v)) / (2 * eps)
+    got_f = float((ft.grad.cpu().numpy().astype(np.float64) * v).sum())
+    e_r = 1e-3 * sr
+    ref_r = (L(f64, sr + e_r) - L(f64, sr - e_r)) / (2 * e_r)
+    print(f"[rec autograd self] df.v {got_f:.6e} vs {ref_f:.6e}; dsigma_r {float(srt.grad):.6e} vs {ref_r:.6e}",
+          flush=True)
+    assert abs(got_f - ref_f) <= 5e-4 * abs(ref_f)
+    assert abs(float(srt.grad) - ref_r) <= 5e-4 * max(abs(ref_r), 1.0)
